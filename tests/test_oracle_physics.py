@@ -1,0 +1,139 @@
+"""Pins of the oracle's full cavity step against properties the equations fix
+(Sec. 2.1 problem statement, Sec. 2.2 scheme, Secs. 4.2-4.3 reductions):
+
+- conduction (Ra = 0) is an exact discrete fixed point for every power-law index:
+  the linear temperature 1 - x makes A and R vanish and the wall closure keeps a
+  y/z-constant field, so nothing moves; then Nu = 1 on both walls and the heat
+  transfer entropy integrates to 1 (Simpson is exact on constants);
+- noise on the conduction state decays;
+- the cavity is symmetric under the half-turn (x, y) -> (1-x, 1-y) with
+  (u, v, w, theta - 1/2, p) -> (-u, -v, w, -(theta - 1/2), p) and under the mirror
+  z -> 1 - z with w -> -w: started symmetric, every step stays symmetric;
+- Newtonian reduction: at n = 1 the viscosity is exactly 1 and the momentum source
+  reduces to -grad p / Pr + Ra (theta - theta_ref); results depend smoothly on n;
+- at steady state the hot and cold wall mean Nusselt numbers agree, and the
+  volume integral of |grad theta|^2 equals the hot-wall Nusselt number (Green's
+  identity with no-slip walls and a solenoidal field) up to an O(h^2) gap.
+"""
+import numpy as np
+import pytest
+
+from paper_2411_06563_amd.inputs import initial_state, random_smooth_state
+
+
+@pytest.mark.parametrize("n_pl", [0.75, 1.0, 1.25])
+def test_conduction_fixed_point(oracle_lib, n_pl):
+    orc = oracle_lib
+    N = 9
+    p = orc.Params(N=N, Ra=0.0, n_pl=n_pl, dt=1e-3)
+    o = orc.Oracle(p)
+    o.set_state(**initial_state(N, 1, noise=0.0))
+    T0 = o.a["T"].copy()
+    x = np.linspace(0, 1, N)
+    assert np.abs(T0 - (1 - x)[None, None, :]).max() <= 1e-15
+    o.step(5)
+    assert np.abs(o.a["T"] - T0).max() <= 1e-14
+    for f in ("u", "v", "w", "p"):
+        assert np.abs(o.a[f]).max() == 0.0
+    d = o.diagnostics()
+    for key in ("nu_mean_hot", "nu_mean_cold", "nu_max_hot", "nu_max_cold", "e_ht", "e_total", "be_global",
+                "be_mean"):
+        assert abs(d[key] - 1.0) <= 1e-13, key
+    assert d["e_ff"] == 0.0
+
+
+def test_conduction_noise_decays(oracle_lib):
+    orc = oracle_lib
+    N = 9
+    p = orc.Params(N=N, Ra=0.0, n_pl=0.75, dt=2e-3)
+    o = orc.Oracle(p)
+    o.set_state(**initial_state(N, 9, noise=1e-2))
+    lin = (1 - np.linspace(0, 1, N))[None, None, :]
+    dist = [np.abs(o.a["T"] - lin).max()]
+    for _ in range(4):
+        o.step(10)
+        dist.append(np.abs(o.a["T"] - lin).max())
+    assert all(dist[q + 1] < dist[q] for q in range(4)), dist
+    assert dist[-1] < 0.5 * dist[0]
+
+
+def _centro(s):
+    return dict(u=-s["u"][:, ::-1, ::-1], v=-s["v"][:, ::-1, ::-1], w=s["w"][:, ::-1, ::-1],
+                T=1.0 - s["T"][:, ::-1, ::-1], p=s["p"][:, ::-1, ::-1])
+
+
+def _mirror_z(s):
+    return dict(u=s["u"][::-1], v=s["v"][::-1], w=-s["w"][::-1], T=s["T"][::-1], p=s["p"][::-1])
+
+
+@pytest.mark.parametrize("n_pl", [0.75, 1.25])
+def test_symmetry_every_step(oracle_lib, n_pl):
+    orc = oracle_lib
+    N = 9
+    p = orc.Params(N=N, Ra=2e4, n_pl=n_pl, dt=2e-3, solve_tol=1e-14)
+    o = orc.Oracle(p)
+    o.set_state(**initial_state(N, 1, noise=0.0))
+    for _ in range(6):
+        o.step(1)
+        s = o.state()
+        assert np.abs(s["v"]).max() > 1e-3   # flow is developing
+        for image in (_centro(s), _mirror_z(s)):
+            for f in s:
+                scale = max(np.abs(s[f]).max(), 1e-300)
+                assert np.abs(image[f] - s[f]).max() <= 1e-12 * scale, f
+
+
+def test_newtonian_reduction(oracle_lib):
+    orc = oracle_lib
+    N = 9
+    s = random_smooth_state(N, seed=2, amp=3.0)
+    p = orc.Params(N=N, Ra=5e3, n_pl=1.0, Pr=0.71, dt=1e-3)
+    eta, I2 = orc.eta_field(p, s["u"], s["v"], s["w"])
+    assert np.all(eta == 1.0) and I2.max() > 1.0
+    E = orc.estar_field(p, s["u"], s["v"], s["w"], s["T"], s["p"], eta)
+    # -grad p / Pr (zero wall-normal derivative) + Ra (theta - theta_ref) in the v equation
+    h = p.h
+    g = [np.zeros((N, N, N)) for _ in range(3)]
+    g[0][:, :, 1:-1] = (s["p"][:, :, 2:] - s["p"][:, :, :-2]) / (2 * h)
+    g[1][:, 1:-1, :] = (s["p"][:, 2:, :] - s["p"][:, :-2, :]) / (2 * h)
+    g[2][1:-1, :, :] = (s["p"][2:, :, :] - s["p"][:-2, :, :]) / (2 * h)
+    assert np.allclose(E[0], -g[0] / p.Pr, rtol=1e-13, atol=1e-12)
+    assert np.allclose(E[1], -g[1] / p.Pr + p.Ra * (s["T"] - 0.5), rtol=1e-13, atol=1e-12)
+    assert np.allclose(E[2], -g[2] / p.Pr, rtol=1e-13, atol=1e-12)
+    # smooth dependence on n around 1
+    out = {}
+    for dn in (0.0, 1e-6, 2e-6):
+        q = orc.Params(N=N, Ra=5e3, n_pl=1.0 + dn, Pr=0.71, dt=1e-3, solve_tol=1e-14)
+        o = orc.Oracle(q)
+        o.set_state(**s)
+        o.step(3)
+        out[dn] = o.state()
+    for f in ("u", "v", "T"):
+        d1 = np.linalg.norm(out[1e-6][f] - out[0.0][f])
+        d2 = np.linalg.norm(out[2e-6][f] - out[0.0][f])
+        assert 0 < d1 < 1e-4 * np.linalg.norm(out[0.0][f])
+        assert abs(d2 / d1 - 2.0) < 1e-2, (f, d1, d2)
+
+
+def _steady(orc, N, dt):
+    p = orc.Params(N=N, Ra=1e3, n_pl=1.0, Pr=1.0, dt=dt, solve_tol=1e-12)
+    o = orc.Oracle(p)
+    o.set_state(**initial_state(N, 1, 1e-3))
+    for _ in range(20000):
+        info = o.step(1)[0]
+        if max(info.res) < 1e-8:
+            break
+    assert max(info.res) < 1e-8
+    return o.diagnostics()
+
+
+def test_steady_state_wall_balance_and_green_identity(oracle_lib):
+    d9 = _steady(oracle_lib, 9, 2e-3)
+    d17 = _steady(oracle_lib, 17, 1e-3)
+    for d in (d9, d17):
+        assert abs(d["nu_mean_hot"] - d["nu_mean_cold"]) <= 1e-5 * d["nu_mean_hot"]
+        assert d["nu_mean_hot"] > 1.05          # convection raises Nu above conduction
+    gap9 = d9["e_ht"] / d9["nu_mean_hot"] - 1.0
+    gap17 = d17["e_ht"] / d17["nu_mean_hot"] - 1.0
+    assert 0 < gap17 < gap9 < 0.01
+    assert 3.0 < gap9 / gap17 < 5.5             # O(h^2)
