@@ -1,0 +1,198 @@
+/*
+ * hosc.h -- C ABI of libhosc, an MI355X (gfx950) implementation of the hot path of
+ * the higher-order super-compact (HOSC) finite-difference scheme for natural
+ * convection of a power-law fluid in a differentially heated cubic cavity
+ * (Punia & Ray, arXiv 2411.06563).
+ *
+ * Problem (Sec. 2.1): unit cube, x = 0 hot wall (theta = theta_hot), x = 1 cold
+ * wall (theta = theta_cold), the other four walls adiabatic; no-slip on every wall;
+ * zero wall-normal pressure derivative; gravity along -y (buoyancy in the v
+ * equation); power-law viscosity eta = I2^((n-1)/2) (Eqs. 6-8); dimensionless
+ * groups Ra and Pr.  Each time step (Sec. 2.2) assembles the compact (19,7) stencil
+ * of the generic transport PDE (Eq. 1) for u, v, w and theta from level-n fields,
+ * solves the four 7-point implicit systems at level n+1, and applies the modified
+ * artificial-compressibility pressure correction; diagnostics give the Nusselt
+ * numbers (Sec. 4.2), entropy generation and Bejan number (Sec. 4.3).
+ *
+ * Conventions for every function:
+ *   - The return value is an hosc_status; HOSC_OK (0) is success.  No C++
+ *     exception crosses the ABI.  hosc_last_error() gives a message for the last
+ *     failing call on a handle (valid until the next call on that handle).
+ *   - Fields are N^3 arrays of double holding every node of the cube including the
+ *     walls, x fastest: node (i, j, k) at index i + N*(j + N*k), x_i = i/(N-1).
+ *   - Host arrays are copied synchronously on the solver's stream; the call returns
+ *     after the copy.  The library never frees caller memory.
+ *   - Device memory: the caller supplies one workspace buffer of at least
+ *     hosc_workspace_bytes() bytes (e.g. a torch tensor); the library only carves it
+ *     and never allocates device memory for a solver.  The workspace must stay
+ *     valid and untouched by the caller until hosc_destroy().
+ *   - A handle may be used by one host thread at a time.  All device work of a
+ *     handle is ordered on the stream given at creation.
+ *   - Errors HOSC_E_NONFINITE and HOSC_E_NOCONV are sticky: the handle refuses to
+ *     step until hosc_set_state() or hosc_init_fields() resets it.
+ */
+#ifndef HOSC_H
+#define HOSC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HOSC_OK = 0,
+    HOSC_E_ARG = -1,        /* invalid argument or parameter */
+    HOSC_E_NOMEM = -2,      /* workspace too small */
+    HOSC_E_DEVICE = -3,     /* a HIP call failed */
+    HOSC_E_NOCONV = -4,     /* an implicit solve hit solve_maxit sweeps */
+    HOSC_E_NONFINITE = -5,  /* a residual or divergence became NaN/Inf */
+    HOSC_E_STATE = -6,      /* handle in a sticky error state / no state set */
+    HOSC_E_BUDGET = -7      /* (server) one request exceeds the whole budget */
+} hosc_status;
+
+typedef enum {
+    HOSC_FP64 = 0,          /* every stage in FP64 */
+    HOSC_FP32_REFINED = 1   /* FP32 implicit matrix and inner sweeps, FP64 residual refinement */
+} hosc_precision;
+
+/* Parameters of one cavity (Sec. 2.1 problem statement, Sec. 2.2 scheme). */
+typedef struct hosc_params {
+    int32_t N;              /* nodes per side including walls, 5 <= N <= 1025; h = 1/(N-1) */
+    int32_t precision;      /* hosc_precision */
+    double Ra;              /* Rayleigh number, >= 0 */
+    double Pr;              /* Prandtl number, > 0 */
+    double n_pl;            /* power-law index n, 0 < n <= 2 (1 = Newtonian) */
+    double dt;              /* time step, > 0 */
+    double theta_hot;       /* theta on x = 0 (default 1) */
+    double theta_cold;      /* theta on x = 1 (default 0) */
+    double theta_ref;       /* buoyancy reference: Ra Pr (theta - theta_ref) (default 0.5) */
+    double lambda;          /* artificial-compressibility relaxation; 0 -> h^2/(3 dt) */
+    double div_tol;         /* correct p when max|div v| > div_tol (default 0: every step) */
+    double solve_rtol;      /* stop a solve when ||r|| <= solve_rtol ||b|| (diagonally scaled 2-norms), default 1e-10 */
+    int32_t solve_maxit;    /* cap on red-black sweeps per solve (default 4000) */
+    int32_t check_every;    /* sweeps between convergence checks; 0 -> adaptive */
+    double omega;           /* SOR relaxation of the red-black sweeps, 0 < omega < 2 (default 1.0) */
+    double i2_floor;        /* eta = max(I2, i2_floor)^((n-1)/2), default 1e-8 */
+    double phi;             /* irreversibility ratio of the fluid-friction entropy, default 1e-4 */
+} hosc_params;
+
+/* Per-step report. */
+typedef struct hosc_step_info {
+    double res[4];          /* steady residual ||chi^{n+1}-chi^n||_2/||chi^{n+1}||_2 of u, v, w, theta */
+    double relres[4];       /* last measured relative residual of each implicit solve */
+    double maxdiv;          /* max |div v^{n+1}| over interior nodes before the correction */
+    int64_t step;           /* steps taken since the state was set */
+    int32_t sweeps[2];      /* red-black sweeps of the momentum and the energy solve (last step) */
+    int32_t corrected;      /* 1 if the pressure correction was applied */
+    int32_t status;         /* hosc_status of the step */
+} hosc_step_info;
+
+/* Scalar diagnostics (Secs. 4.2, 4.3). */
+typedef struct hosc_diag {
+    double nu_mean_hot;     /* int int Nu dy dz on x = 0, Nu = -d theta/dx */
+    double nu_mean_cold;    /* same on x = 1 */
+    double nu_max_hot;      /* max_z Nu_avg(z) on x = 0 (the quantity of Table 2) */
+    double nu_max_cold;
+    double e_total;         /* int E_local dV */
+    double e_ht;            /* int E_HT dV, E_HT = |grad theta|^2 */
+    double e_ff;            /* int E_FF dV, E_FF = phi eta I2 */
+    double be_global;       /* int E_HT / int E_local */
+    double be_mean;         /* int (E_HT / E_local) dV */
+    double nu_local_max_hot;/* max over the hot wall of Nu_local */
+} hosc_diag;
+
+/* Kernel timing of the implicit solves (HIP events around every sweep launch) and
+ * their algorithmic HBM bytes: per launch, each updated node reads its stored row
+ * (momentum s, a_x, a_y, a_z, b_u, b_v, b_w; energy a_x, a_y, a_z, b), reads and
+ * writes its own increments, and each node of the other colour is read once. */
+typedef struct hosc_perf {
+    int64_t sweep_launches;     /* half-sweep kernel launches timed */
+    double sweep_ms;            /* summed kernel time of those launches */
+    double sweep_bytes;         /* summed algorithmic bytes of those launches */
+    int64_t assemble_launches;
+    double assemble_ms;
+    double assemble_bytes;
+} hosc_perf;
+
+typedef struct hosc_solver hosc_solver;
+
+/* Fill p with the defaults (N = 17, Ra = 1e3, Pr = 1, n = 1, dt = 1e-4, ...). */
+hosc_status hosc_params_default(hosc_params *p);
+
+/* Device bytes a solver with these parameters needs (for admission by budget).
+ * Fails with HOSC_E_ARG on invalid parameters. */
+hosc_status hosc_workspace_bytes(const hosc_params *p, size_t *bytes);
+
+/* Create a solver on the current HIP device.  d_ws: device buffer of ws_bytes >=
+ * hosc_workspace_bytes(p), 256-byte aligned; stream: where all work is ordered
+ * (0 = null stream).  The state is unset until hosc_init_fields / hosc_set_state. */
+hosc_status hosc_create(const hosc_params *p, void *d_ws, size_t ws_bytes, hipStream_t stream, hosc_solver **out);
+
+/* Release the handle (not the workspace).  Accepts NULL. */
+hosc_status hosc_destroy(hosc_solver *s);
+
+/* Initial condition of the cavity runs: u = v = w = p = 0; theta = theta_hot +
+ * (theta_cold - theta_hot) x + noise_amp (2U - 1) at interior nodes, U uniform in
+ * [0,1) from SplitMix64 seeded with seed, one draw per interior node in storage
+ * order; then the boundary conditions.  Resets the step counter (level n-1 is
+ * taken equal to level n at the next step). */
+hosc_status hosc_init_fields(hosc_solver *s, uint64_t seed, double noise_amp);
+
+/* Set level n from host arrays (any pointer may be NULL: that field becomes 0).
+ * apply_bc != 0 imposes the boundary conditions (no-slip, wall temperatures, zero
+ * normal derivative of theta on the y/z walls and of p everywhere by the closure
+ * f_0 = (4 f_1 - f_2)/3).  Resets the step counter and clears sticky errors. */
+hosc_status hosc_set_state(hosc_solver *s, const double *u, const double *v, const double *w, const double *theta,
+                           const double *p, int32_t apply_bc);
+
+/* Copy level n to host arrays (any pointer may be NULL). */
+hosc_status hosc_get_state(hosc_solver *s, double *u, double *v, double *w, double *theta, double *p);
+
+/* Advance nsteps time steps (Sec. 2.2).  info (may be NULL) reports the last step. */
+hosc_status hosc_step(hosc_solver *s, int32_t nsteps, hosc_step_info *info);
+
+/* Step until max_f res[f] < res_tol or max_steps steps were taken. */
+hosc_status hosc_run_to_steady(hosc_solver *s, double res_tol, int64_t max_steps, hosc_step_info *info);
+
+/* Nusselt, entropy and Bejan diagnostics of level n.  Optional host outputs (may
+ * be NULL): nuavg_hot[N], nuavg_cold[N] (Nu_avg(z_k)); nu_hot[N*N], nu_cold[N*N]
+ * (Nu_local at node (j, k) stored at j + N*k). */
+hosc_status hosc_diagnostics(hosc_solver *s, hosc_diag *d, double *nuavg_hot, double *nuavg_cold, double *nu_hot,
+                             double *nu_cold);
+
+/* Local entropy generation E_local and local Bejan number at every node (host N^3
+ * arrays; either may be NULL). */
+hosc_status hosc_entropy_fields(hosc_solver *s, double *e_local, double *be_local);
+
+/* Parity hook: assemble the step from the current state without advancing it.
+ * Outputs (host, any may be NULL): eta[N^3], estar[3 N^3] (E*_u, E*_v, E*_w),
+ * b[4 N^3] right-hand sides of the u, v, w, theta increment systems (walls 0),
+ * Bmom[7 N^3], Btheta[7 N^3]: the 7-point weights of the implicit operators in the
+ * order centre, x+, x-, y+, y-, z+, z- (walls 0; theta rows before the wall closure).
+ * When the step counter is 0, level n-1 is taken equal to level n. */
+hosc_status hosc_debug_assemble(hosc_solver *s, double *eta, double *estar, double *b, double *Bmom,
+                                double *Btheta);
+
+/* Switch kernel timing on (on != 0, counters cleared) or off.  Timing adds two
+ * event records per timed launch on the solver's stream. */
+hosc_status hosc_perf_enable(hosc_solver *s, int32_t on);
+
+/* Counters accumulated since the last hosc_perf_enable(s, 1). */
+hosc_status hosc_perf_get(hosc_solver *s, hosc_perf *out);
+
+/* Message of the last failing call on the handle ("" if none; NULL handle: last
+ * failing create). */
+const char *hosc_last_error(const hosc_solver *s);
+
+/* Name of a status code. */
+const char *hosc_status_string(hosc_status st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOSC_H */

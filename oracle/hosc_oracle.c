@@ -942,3 +942,11 @@ int or_diagnostics(const or_params *P, const double *u, const double *v, const d
     free(eta); free(I2); free(wq); free(nh); free(nc);
     return 0;
 }
+
+/* Number of OpenMP threads the oracle's node loops use (1 without OpenMP). */
+#ifdef _OPENMP
+#include <omp.h>
+int or_num_threads(void) { return omp_get_max_threads(); }
+#else
+int or_num_threads(void) { return 1; }
+#endif

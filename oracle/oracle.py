@@ -187,6 +187,10 @@ class Oracle:
         return {f: self.a[f].copy() for f in ("u", "v", "w", "T", "p")}
 
 
+def num_threads() -> int:
+    return int(lib().or_num_threads())
+
+
 def eta_field(params: Params, u, v, w):
     N = params.N
     eta = np.zeros((N, N, N))

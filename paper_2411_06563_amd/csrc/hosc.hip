@@ -1,0 +1,862 @@
+// hosc.hip -- host runtime and C ABI of libhosc (declared in include/hosc.h).
+//
+// One solver = one cavity on one device.  All device memory comes from the
+// caller's workspace; the runtime carves it into natural-layout fields (levels n
+// and n-1, viscosity, momentum sources) and colour-layout rows of the implicit
+// systems, and drives the step of Sec. 2.2 of the paper on the caller's stream:
+//   eta, E*  ->  HOSC assembly  ->  red-black SOR sweeps (both systems together,
+//   convergence measured inside the sweeps)  ->  update + walls + steady residual
+//   ->  divergence and pressure correction + pressure walls.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hosc.h"
+#include "hosc_kernels.hpp"
+
+using namespace hosc;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kRed = 32;    // doubles in the reduction output block
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Launch {
+    dim3 blk_all, grd_all;      // every node (natural layout)
+    dim3 blk_int, grd_int;      // interior nodes (natural layout)
+    dim3 blk_sw, grd_sw;        // one colour of the interior (colour layout)
+    dim3 blk_face, grd_face;    // wall nodes, 6 faces
+    size_t nb_int, nb_sw, nb_face, nb_all;
+};
+
+// Workspace map (element counts in doubles, each region 256-byte aligned).
+struct Layout {
+    size_t n3, cs;
+    size_t natural_arrays = 17;   // u v w T p u2 v2 w2 eta etap E3 Ep3 dbg
+    size_t colour_arrays = 15;    // ms ma3 mb3 md3 ta3 tb td (each 2 colours)
+    size_t partial;               // partial-sum records
+    size_t total_bytes;
+};
+
+Geo make_geo(int N)
+{
+    Geo g;
+    g.N = N;
+    g.H = (N + 1) / 2;
+    g.Q = ((N - 2) >> 1) + 1;
+    g.pad = 0;
+    g.h = 1.0 / (N - 1);
+    g.h2 = g.h * g.h;
+    g.inv2h = 1.0 / (2.0 * g.h);
+    g.invh2 = 1.0 / g.h2;
+    g.n3 = (size_t)N * N * N;
+    g.cs = (size_t)N * N * g.H;
+    return g;
+}
+
+Launch make_launch(const Geo &g)
+{
+    Launch L;
+    const int N = g.N, M = N - 2;
+    L.blk_all = dim3(64, 4, 1);
+    L.grd_all = dim3((N + 63) / 64, (N + 3) / 4, N);
+    L.blk_int = dim3(64, 4, 1);
+    L.grd_int = dim3((M + 63) / 64, (M + 3) / 4, M);
+    int bx = 64;
+    while (bx > 8 && bx / 2 >= g.Q) bx /= 2;
+    L.blk_sw = dim3(bx, 256 / bx, 1);
+    L.grd_sw = dim3((g.Q + bx - 1) / bx, (M + L.blk_sw.y - 1) / L.blk_sw.y, M);
+    L.blk_face = dim3(64, 4, 1);
+    L.grd_face = dim3((N + 63) / 64, (N + 3) / 4, 6);
+    L.nb_all = (size_t)L.grd_all.x * L.grd_all.y * L.grd_all.z;
+    L.nb_int = (size_t)L.grd_int.x * L.grd_int.y * L.grd_int.z;
+    L.nb_sw = (size_t)L.grd_sw.x * L.grd_sw.y * L.grd_sw.z;
+    L.nb_face = (size_t)L.grd_face.x * L.grd_face.y * L.grd_face.z;
+    return L;
+}
+
+Layout make_layout(const Geo &g, const Launch &L)
+{
+    Layout y;
+    y.n3 = g.n3;
+    y.cs = g.cs;
+    const size_t recs = std::max({L.nb_int * 8, L.nb_sw * 4, L.nb_face * 2, L.nb_all * 3});
+    y.partial = recs;
+    size_t b = 0;
+    b += y.natural_arrays * align_up(g.n3 * sizeof(double));
+    b += y.colour_arrays * align_up(2 * g.cs * sizeof(double));
+    b += 2 * align_up(recs * sizeof(double));                 // two partial buffers (red / black half)
+    b += align_up(kRed * sizeof(double));                      // reduction outputs
+    b += align_up((size_t)g.N * sizeof(double));               // Simpson weights
+    b += 2 * align_up((size_t)g.N * g.N * sizeof(double));     // Nu_local hot / cold
+    b += 2 * align_up((size_t)g.N * sizeof(double));           // Nu_avg hot / cold
+    b += align_up(8 * sizeof(double));                         // Nu scalars
+    y.total_bytes = b;
+    return y;
+}
+
+const char *check_params(const hosc_params *p)
+{
+    if (!p) return "params is NULL";
+    if (p->N < 5 || p->N > 1025) return "N must be in [5, 1025]";
+    if (p->precision != HOSC_FP64 && p->precision != HOSC_FP32_REFINED) return "unknown precision";
+    if (!(p->Ra >= 0.0) || !std::isfinite(p->Ra)) return "Ra must be finite and >= 0";
+    if (!(p->Pr > 0.0) || !std::isfinite(p->Pr)) return "Pr must be finite and > 0";
+    if (!(p->n_pl > 0.0 && p->n_pl <= 2.0)) return "n_pl must be in (0, 2]";
+    if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return "dt must be finite and > 0";
+    if (!(p->lambda >= 0.0) || !std::isfinite(p->lambda)) return "lambda must be finite and >= 0";
+    if (!std::isfinite(p->div_tol)) return "div_tol must be finite";
+    if (!(p->solve_rtol > 0.0 && p->solve_rtol < 1.0)) return "solve_rtol must be in (0, 1)";
+    if (p->solve_maxit < 1) return "solve_maxit must be >= 1";
+    if (p->check_every < 0) return "check_every must be >= 0";
+    if (!(p->omega > 0.0 && p->omega < 2.0)) return "omega must be in (0, 2)";
+    if (!(p->i2_floor > 0.0) || !std::isfinite(p->i2_floor)) return "i2_floor must be finite and > 0";
+    if (!(p->phi >= 0.0) || !std::isfinite(p->phi)) return "phi must be finite and >= 0";
+    if (!std::isfinite(p->theta_hot) || !std::isfinite(p->theta_cold) || !std::isfinite(p->theta_ref))
+        return "wall and reference temperatures must be finite";
+    return nullptr;
+}
+
+// Composite Simpson weights on N equally spaced nodes of [0, 1] (Simpson's 3/8 rule
+// on the last three intervals when N-1 is odd).
+std::vector<double> simpson(int N)
+{
+    std::vector<double> w(N, 0.0);
+    const double h = 1.0 / (N - 1);
+    const int nint = N - 1;
+    const int n13 = (nint % 2 == 0) ? nint : nint - 3;
+    for (int q = 0; q < n13; q += 2) {
+        w[q] += h / 3.0;
+        w[q + 1] += 4.0 * h / 3.0;
+        w[q + 2] += h / 3.0;
+    }
+    if (n13 != nint) {
+        const int q = n13;
+        w[q] += 3.0 * h / 8.0;
+        w[q + 1] += 9.0 * h / 8.0;
+        w[q + 2] += 9.0 * h / 8.0;
+        w[q + 3] += 3.0 * h / 8.0;
+    }
+    return w;
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014): output k of the stream seeded with s.
+inline uint64_t splitmix64(uint64_t s, uint64_t k)
+{
+    uint64_t z = s + (k + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+std::string g_create_error;
+
+}  // namespace
+
+struct hosc_solver {
+    hosc_params P;
+    Geo g;
+    Phys ph;
+    Launch L;
+    Layout Y;
+    hipStream_t st = nullptr;
+    int device = 0;
+    // natural layout
+    double *u, *v, *w, *T, *p, *u2, *v2, *w2, *eta, *etap, *E[3], *Ep[3], *dbg;
+    // colour layout
+    double *ms, *ma[3], *mb[3], *md[3], *ta[3], *tb, *td;
+    double *partR, *partB, *red, *wq, *nuh, *nuc, *avh, *avc, *nuout;
+    double *hbuf = nullptr;   // pinned host staging for scalars
+    int64_t step = 0;
+    bool first = true;
+    bool has_state = false;
+    int sticky = HOSC_OK;
+    int last_sweeps[2] = {0, 0};
+    std::string err;
+    // kernel timing
+    bool prof = false;
+    std::vector<hipEvent_t> ev;     // pairs (start, stop)
+    std::vector<double> ev_bytes;   // algorithmic bytes of each timed launch
+    std::vector<int> ev_kind;       // 0 sweep, 1 assemble
+    int ev_used = 0;
+    hosc_perf perf{};
+};
+
+namespace {
+
+hosc_status fail(hosc_solver *s, hosc_status st, const std::string &msg)
+{
+    if (s) s->err = msg;
+    else g_create_error = msg;
+    return st;
+}
+
+#define HIPCHK(s, call)                                                                            \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail((s), HOSC_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+hosc_status launch_check(hosc_solver *s, const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(s, HOSC_E_DEVICE, std::string("launch of ") + what + ": " + hipGetErrorString(e));
+    return HOSC_OK;
+}
+
+void carve(hosc_solver *s, char *base)
+{
+    const size_t nat = align_up(s->g.n3 * sizeof(double));
+    const size_t col = align_up(2 * s->g.cs * sizeof(double));
+    char *q = base;
+    auto take = [&](size_t bytes) {
+        double *r = reinterpret_cast<double *>(q);
+        q += bytes;
+        return r;
+    };
+    s->u = take(nat); s->v = take(nat); s->w = take(nat); s->T = take(nat); s->p = take(nat);
+    s->u2 = take(nat); s->v2 = take(nat); s->w2 = take(nat);
+    s->eta = take(nat); s->etap = take(nat);
+    for (int d = 0; d < 3; ++d) s->E[d] = take(nat);
+    for (int d = 0; d < 3; ++d) s->Ep[d] = take(nat);
+    s->dbg = take(nat);
+    s->ms = take(col);
+    for (int d = 0; d < 3; ++d) s->ma[d] = take(col);
+    for (int d = 0; d < 3; ++d) s->mb[d] = take(col);
+    for (int d = 0; d < 3; ++d) s->md[d] = take(col);
+    for (int d = 0; d < 3; ++d) s->ta[d] = take(col);
+    s->tb = take(col);
+    s->td = take(col);
+    const size_t pb = align_up(s->Y.partial * sizeof(double));
+    s->partR = take(pb);
+    s->partB = take(pb);
+    s->red = take(align_up(kRed * sizeof(double)));
+    s->wq = take(align_up((size_t)s->g.N * sizeof(double)));
+    s->nuh = take(align_up((size_t)s->g.N * s->g.N * sizeof(double)));
+    s->nuc = take(align_up((size_t)s->g.N * s->g.N * sizeof(double)));
+    s->avh = take(align_up((size_t)s->g.N * sizeof(double)));
+    s->avc = take(align_up((size_t)s->g.N * sizeof(double)));
+    s->nuout = take(align_up(8 * sizeof(double)));
+}
+
+constexpr int kEvPairs = 512;
+
+// Algorithmic bytes of one half-sweep launch (see hosc_perf in hosc.h).
+double sweep_bytes(const Geo &g, int mask)
+{
+    const double nodes = 0.5 * (double)(g.N - 2) * (g.N - 2) * (g.N - 2);
+    double per = 0.0;
+    if (mask & 1) per += (7 + 3 + 3 + 3) * sizeof(double);   // row 7, own 3 read + 3 write, other colour 3
+    if (mask & 2) per += (4 + 1 + 1 + 1) * sizeof(double);   // row 4, own 1 + 1, other colour 1
+    return nodes * per;
+}
+
+// Algorithmic bytes of the assembly: 8 level-n fields and 7 level n-1 fields read,
+// 11 row arrays written, per interior node.
+double assemble_bytes(const Geo &g)
+{
+    return (double)(g.N - 2) * (g.N - 2) * (g.N - 2) * (15 + 11) * sizeof(double);
+}
+
+hosc_status harvest_events(hosc_solver *s)
+{
+    if (!s->prof || s->ev_used == 0) return HOSC_OK;
+    HIPCHK(s, hipEventSynchronize(s->ev[2 * (s->ev_used - 1) + 1]));
+    for (int q = 0; q < s->ev_used; ++q) {
+        float ms = 0.0f;
+        HIPCHK(s, hipEventElapsedTime(&ms, s->ev[2 * q], s->ev[2 * q + 1]));
+        if (s->ev_kind[q] == 0) {
+            s->perf.sweep_launches += 1;
+            s->perf.sweep_ms += ms;
+            s->perf.sweep_bytes += s->ev_bytes[q];
+        } else {
+            s->perf.assemble_launches += 1;
+            s->perf.assemble_ms += ms;
+            s->perf.assemble_bytes += s->ev_bytes[q];
+        }
+    }
+    s->ev_used = 0;
+    return HOSC_OK;
+}
+
+// Bracket the next launch with events when timing is on.
+hosc_status timed_begin(hosc_solver *s)
+{
+    if (!s->prof) return HOSC_OK;
+    if (s->ev_used == kEvPairs) {
+        hosc_status r = harvest_events(s);
+        if (r) return r;
+    }
+    HIPCHK(s, hipEventRecord(s->ev[2 * s->ev_used], s->st));
+    return HOSC_OK;
+}
+hosc_status timed_end(hosc_solver *s, int kind, double bytes)
+{
+    if (!s->prof) return HOSC_OK;
+    HIPCHK(s, hipEventRecord(s->ev[2 * s->ev_used + 1], s->st));
+    s->ev_kind[s->ev_used] = kind;
+    s->ev_bytes[s->ev_used] = bytes;
+    s->ev_used += 1;
+    return HOSC_OK;
+}
+
+hosc_status zero_colour_increments(hosc_solver *s)
+{
+    for (int d = 0; d < 3; ++d) HIPCHK(s, hipMemsetAsync(s->md[d], 0, 2 * s->g.cs * sizeof(double), s->st));
+    HIPCHK(s, hipMemsetAsync(s->td, 0, 2 * s->g.cs * sizeof(double), s->st));
+    return HOSC_OK;
+}
+
+// Boundary conditions on level n (device).
+hosc_status impose_bc(hosc_solver *s)
+{
+    k_zero_walls<<<s->L.grd_face, s->L.blk_face, 0, s->st>>>(s->g, s->u, s->v, s->w);
+    k_theta_walls<<<s->L.grd_face, s->L.blk_face, 0, s->st>>>(s->g, s->ph, s->T, s->partR);
+    k_p_walls<<<s->L.grd_face, s->L.blk_face, 0, s->st>>>(s->g, s->p);
+    return launch_check(s, "boundary conditions");
+}
+
+hosc_status reset_state(hosc_solver *s)
+{
+    hosc_status r = zero_colour_increments(s);
+    if (r) return r;
+    s->step = 0;
+    s->first = true;
+    s->has_state = true;
+    s->sticky = HOSC_OK;
+    s->last_sweeps[0] = s->last_sweeps[1] = 0;
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    return HOSC_OK;
+}
+
+// eta and E* at level n; on the first step level n-1 := level n.
+hosc_status stage_sources(hosc_solver *s, bool consume_first)
+{
+    k_eta<<<s->L.grd_all, s->L.blk_all, 0, s->st>>>(s->g, s->ph, s->u, s->v, s->w, s->eta);
+    k_estar<<<s->L.grd_all, s->L.blk_all, 0, s->st>>>(s->g, s->ph, s->u, s->v, s->w, s->T, s->p, s->eta, s->E[0],
+                                                       s->E[1], s->E[2]);
+    hosc_status r = launch_check(s, "eta/estar");
+    if (r) return r;
+    if (s->first) {
+        const size_t b = s->g.n3 * sizeof(double);
+        HIPCHK(s, hipMemcpyAsync(s->u2, s->u, b, hipMemcpyDeviceToDevice, s->st));
+        HIPCHK(s, hipMemcpyAsync(s->v2, s->v, b, hipMemcpyDeviceToDevice, s->st));
+        HIPCHK(s, hipMemcpyAsync(s->w2, s->w, b, hipMemcpyDeviceToDevice, s->st));
+        HIPCHK(s, hipMemcpyAsync(s->etap, s->eta, b, hipMemcpyDeviceToDevice, s->st));
+        for (int d = 0; d < 3; ++d)
+            HIPCHK(s, hipMemcpyAsync(s->Ep[d], s->E[d], b, hipMemcpyDeviceToDevice, s->st));
+        if (consume_first) s->first = false;
+    }
+    return HOSC_OK;
+}
+
+SweepArgs<double> sweep_args(hosc_solver *s)
+{
+    SweepArgs<double> a;
+    a.ms = s->ms;
+    for (int d = 0; d < 3; ++d) {
+        a.ma[d] = s->ma[d];
+        a.mb[d] = s->mb[d];
+        a.md[d] = s->md[d];
+        a.ta[d] = s->ta[d];
+    }
+    a.tb = s->tb;
+    a.td = s->td;
+    return a;
+}
+
+// Red-black SOR on both systems until each meets ||r|| <= rtol ||b|| (scaled rows).
+// One sweep = red half then black half; the sums of squared pre-update residuals of
+// the black half and (1-omega)^2 times those of the red half give the residual of
+// the state between the two halves, so convergence is known without an extra pass.
+hosc_status solve(hosc_solver *s, double relres[4], int sweeps[2])
+{
+    const double om = s->P.omega;
+    const double rtol = s->P.solve_rtol;
+    const double ct = s->g.h2 / 12.0 - s->P.dt / 2.0;
+    const double Ct = 1.0 - 6.0 * ct * s->g.invh2;
+    const double st = (ct * s->g.invh2) / Ct;
+    SweepArgs<double> a = sweep_args(s);
+    int active = 3;
+    sweeps[0] = sweeps[1] = 0;
+    int predicted = std::max(s->last_sweeps[0], s->last_sweeps[1]);
+    int batch = s->P.check_every > 0 ? s->P.check_every : std::max(2, predicted > 0 ? predicted - 1 : 8);
+    bool have_b = false;
+    double bn2[4] = {0, 0, 0, 0};
+    for (;;) {
+        const double bytes = sweep_bytes(s->g, active);
+        for (int q = 0; q < batch; ++q) {
+            const int acc = q == batch - 1;
+            for (int colour = 0; colour < 2; ++colour) {
+                hosc_status r = timed_begin(s);
+                if (r) return r;
+                k_sweep<double, double><<<s->L.grd_sw, s->L.blk_sw, 0, s->st>>>(s->g, colour, active, om, st, a,
+                                                                               colour ? s->partB : s->partR, acc);
+                r = timed_end(s, 0, bytes);
+                if (r) return r;
+            }
+        }
+        hosc_status r = launch_check(s, "sweep");
+        if (r) return r;
+        k_reduce<<<1, 256, 0, s->st>>>(s->partR, (int)s->L.nb_sw, 4, 0, s->red + 4);
+        k_reduce<<<1, 256, 0, s->st>>>(s->partB, (int)s->L.nb_sw, 4, 0, s->red + 8);
+        HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red, 12 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+        HIPCHK(s, hipStreamSynchronize(s->st));
+        r = harvest_events(s);
+        if (r) return r;
+        if (!have_b) {
+            for (int f = 0; f < 4; ++f) bn2[f] = s->hbuf[f];
+            have_b = true;
+        }
+        if (active & 1) sweeps[0] += batch;
+        if (active & 2) sweeps[1] += batch;
+        bool conv[4];
+        for (int f = 0; f < 4; ++f) {
+            const double r2 = s->hbuf[8 + f] + (1.0 - om) * (1.0 - om) * s->hbuf[4 + f];
+            if (!std::isfinite(r2) || !std::isfinite(bn2[f]))
+                return fail(s, HOSC_E_NONFINITE, "non-finite residual in the implicit solve");
+            const bool sys_active = (f < 3) ? (active & 1) : (active & 2);
+            if (sys_active) relres[f] = bn2[f] > 0.0 ? std::sqrt(r2 / bn2[f]) : 0.0;
+            conv[f] = bn2[f] == 0.0 || std::sqrt(r2) <= rtol * std::sqrt(bn2[f]);
+        }
+        if ((active & 1) && conv[0] && conv[1] && conv[2]) {
+            for (int f = 0; f < 3; ++f)
+                if (bn2[f] == 0.0) HIPCHK(s, hipMemsetAsync(s->md[f], 0, 2 * s->g.cs * sizeof(double), s->st));
+            active &= ~1;
+        }
+        if ((active & 2) && conv[3]) {
+            if (bn2[3] == 0.0) HIPCHK(s, hipMemsetAsync(s->td, 0, 2 * s->g.cs * sizeof(double), s->st));
+            active &= ~2;
+        }
+        if (!active) break;
+        const int done = std::max(sweeps[0], sweeps[1]);
+        if (done >= s->P.solve_maxit)
+            return fail(s, HOSC_E_NOCONV, "implicit solve did not converge within solve_maxit sweeps");
+        batch = s->P.check_every > 0 ? s->P.check_every : std::max(2, std::min(done / 2, 64));
+        batch = std::min(batch, s->P.solve_maxit - done);
+    }
+    s->last_sweeps[0] = sweeps[0];
+    s->last_sweeps[1] = sweeps[1];
+    return HOSC_OK;
+}
+
+hosc_status one_step(hosc_solver *s, hosc_step_info *info)
+{
+    hosc_status r = stage_sources(s, true);
+    if (r) return r;
+    ColourArrays ca;
+    ca.ms = s->ms;
+    for (int d = 0; d < 3; ++d) {
+        ca.ma[d] = s->ma[d];
+        ca.mb[d] = s->mb[d];
+        ca.ta[d] = s->ta[d];
+    }
+    ca.tb = s->tb;
+    r = timed_begin(s);
+    if (r) return r;
+    k_assemble<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, s->ph, s->u, s->v, s->w, s->T, s->eta, s->E[0],
+                                                         s->E[1], s->E[2], s->u2, s->v2, s->w2, s->etap, s->Ep[0],
+                                                         s->Ep[1], s->Ep[2], ca, s->partR);
+    r = timed_end(s, 1, assemble_bytes(s->g));
+    if (r) return r;
+    k_reduce<<<1, 256, 0, s->st>>>(s->partR, (int)s->L.nb_int, 4, 0, s->red);
+    r = launch_check(s, "assemble");
+    if (r) return r;
+    double relres[4] = {0, 0, 0, 0};
+    int sweeps[2] = {0, 0};
+    r = solve(s, relres, sweeps);
+    if (r) return r;
+    // update: u, v, w into the level n-1 buffers (which become level n+1)
+    k_update<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, s->u, s->v, s->w, s->u2, s->v2, s->w2, s->T, s->md[0],
+                                                       s->md[1], s->md[2], s->td, s->partR);
+    k_reduce<<<1, 256, 0, s->st>>>(s->partR, (int)s->L.nb_int, 8, 0, s->red + 12);
+    k_theta_walls<<<s->L.grd_face, s->L.blk_face, 0, s->st>>>(s->g, s->ph, s->T, s->partB);
+    k_reduce<<<1, 256, 0, s->st>>>(s->partB, (int)s->L.nb_face, 2, 0, s->red + 20);
+    const bool gate = s->P.div_tol > 0.0;
+    k_divergence<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, s->ph, s->u2, s->v2, s->w2, s->p,
+                                                           gate ? s->dbg : nullptr, gate ? 0 : 1, s->partR);
+    k_reduce<<<1, 256, 0, s->st>>>(s->partR, (int)s->L.nb_int, 1, 1, s->red + 22);
+    r = launch_check(s, "update/divergence");
+    if (r) return r;
+    HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red + 12, 11 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    const double maxdiv = s->hbuf[10];
+    int corrected = 0;
+    if (gate) {
+        if (maxdiv > s->P.div_tol) {
+            k_pressure_apply<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, s->ph, s->dbg, s->p);
+            corrected = 1;
+        }
+    } else {
+        corrected = 1;
+    }
+    if (corrected) k_p_walls<<<s->L.grd_face, s->L.blk_face, 0, s->st>>>(s->g, s->p);
+    r = launch_check(s, "pressure");
+    if (r) return r;
+    std::swap(s->u, s->u2);
+    std::swap(s->v, s->v2);
+    std::swap(s->w, s->w2);
+    std::swap(s->eta, s->etap);
+    for (int d = 0; d < 3; ++d) std::swap(s->E[d], s->Ep[d]);
+    s->step += 1;
+    const double *hb = s->hbuf;
+    auto ratio = [](double num, double den) {
+        if (den > 0.0) return std::sqrt(num) / std::sqrt(den);
+        return num == 0.0 ? 0.0 : HUGE_VAL;
+    };
+    double res[4];
+    res[0] = ratio(hb[0], hb[4]);
+    res[1] = ratio(hb[1], hb[5]);
+    res[2] = ratio(hb[2], hb[6]);
+    res[3] = ratio(hb[3] + hb[8], hb[7] + hb[9]);
+    bool finite = std::isfinite(maxdiv);
+    for (int f = 0; f < 4; ++f) finite = finite && std::isfinite(res[f]);
+    if (info) {
+        for (int f = 0; f < 4; ++f) {
+            info->res[f] = res[f];
+            info->relres[f] = relres[f];
+        }
+        info->maxdiv = maxdiv;
+        info->step = s->step;
+        info->sweeps[0] = sweeps[0];
+        info->sweeps[1] = sweeps[1];
+        info->corrected = corrected;
+        info->status = finite ? HOSC_OK : HOSC_E_NONFINITE;
+    }
+    if (!finite) return fail(s, HOSC_E_NONFINITE, "non-finite steady residual or divergence");
+    return HOSC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hosc_status hosc_params_default(hosc_params *p)
+{
+    if (!p) return HOSC_E_ARG;
+    std::memset(p, 0, sizeof(*p));
+    p->N = 17;
+    p->precision = HOSC_FP64;
+    p->Ra = 1e3;
+    p->Pr = 1.0;
+    p->n_pl = 1.0;
+    p->dt = 1e-4;
+    p->theta_hot = 1.0;
+    p->theta_cold = 0.0;
+    p->theta_ref = 0.5;
+    p->lambda = 0.0;
+    p->div_tol = 0.0;
+    p->solve_rtol = 1e-10;
+    p->solve_maxit = 4000;
+    p->check_every = 0;
+    p->omega = 1.0;
+    p->i2_floor = 1e-8;
+    p->phi = 1e-4;
+    return HOSC_OK;
+}
+
+hosc_status hosc_workspace_bytes(const hosc_params *p, size_t *bytes)
+{
+    const char *e = check_params(p);
+    if (e) return fail(nullptr, HOSC_E_ARG, e);
+    if (!bytes) return fail(nullptr, HOSC_E_ARG, "bytes is NULL");
+    Geo g = make_geo(p->N);
+    Launch L = make_launch(g);
+    *bytes = make_layout(g, L).total_bytes;
+    return HOSC_OK;
+}
+
+hosc_status hosc_create(const hosc_params *p, void *d_ws, size_t ws_bytes, hipStream_t stream, hosc_solver **out)
+{
+    if (!out) return fail(nullptr, HOSC_E_ARG, "out is NULL");
+    *out = nullptr;
+    const char *e = check_params(p);
+    if (e) return fail(nullptr, HOSC_E_ARG, e);
+    if (p->precision != HOSC_FP64) return fail(nullptr, HOSC_E_ARG, "precision FP32_REFINED is not available in this build");
+    if (!d_ws) return fail(nullptr, HOSC_E_ARG, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return fail(nullptr, HOSC_E_ARG, "workspace must be 256-byte aligned");
+    hosc_solver *s = new (std::nothrow) hosc_solver();
+    if (!s) return fail(nullptr, HOSC_E_NOMEM, "host allocation failed");
+    s->P = *p;
+    s->g = make_geo(p->N);
+    s->L = make_launch(s->g);
+    s->Y = make_layout(s->g, s->L);
+    if (ws_bytes < s->Y.total_bytes) {
+        delete s;
+        return fail(nullptr, HOSC_E_NOMEM, "workspace smaller than hosc_workspace_bytes()");
+    }
+    const double h = s->g.h;
+    s->ph.Ra = p->Ra;
+    s->ph.Pr = p->Pr;
+    s->ph.dt = p->dt;
+    s->ph.theta_hot = p->theta_hot;
+    s->ph.theta_cold = p->theta_cold;
+    s->ph.theta_ref = p->theta_ref;
+    s->ph.i2_floor = p->i2_floor;
+    s->ph.ex = 0.5 * (p->n_pl - 1.0);
+    s->ph.lambda = p->lambda > 0.0 ? p->lambda : h * h / (3.0 * p->dt);
+    s->ph.phi = p->phi;
+    s->st = stream;
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return fail(nullptr, HOSC_E_DEVICE, "hipGetDevice failed");
+    }
+    if (hipHostMalloc(reinterpret_cast<void **>(&s->hbuf), 64 * sizeof(double)) != hipSuccess) {
+        delete s;
+        return fail(nullptr, HOSC_E_DEVICE, "hipHostMalloc of the staging buffer failed");
+    }
+    carve(s, static_cast<char *>(d_ws));
+    std::vector<double> wq = simpson(p->N);
+    hipError_t he = hipMemcpy(s->wq, wq.data(), wq.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (he != hipSuccess) {
+        (void)hipHostFree(s->hbuf);
+        delete s;
+        return fail(nullptr, HOSC_E_DEVICE, std::string("copy of quadrature weights: ") + hipGetErrorString(he));
+    }
+    *out = s;
+    return HOSC_OK;
+}
+
+hosc_status hosc_destroy(hosc_solver *s)
+{
+    if (!s) return HOSC_OK;
+    if (s->st) (void)hipStreamSynchronize(s->st);
+    else (void)hipDeviceSynchronize();
+    for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+    if (s->hbuf) (void)hipHostFree(s->hbuf);
+    delete s;
+    return HOSC_OK;
+}
+
+hosc_status hosc_set_state(hosc_solver *s, const double *u, const double *v, const double *w, const double *theta,
+                           const double *p, int32_t apply_bc)
+{
+    if (!s) return HOSC_E_ARG;
+    const size_t b = s->g.n3 * sizeof(double);
+    double *dst[5] = {s->u, s->v, s->w, s->T, s->p};
+    const double *src[5] = {u, v, w, theta, p};
+    for (int f = 0; f < 5; ++f) {
+        if (src[f]) HIPCHK(s, hipMemcpyAsync(dst[f], src[f], b, hipMemcpyHostToDevice, s->st));
+        else HIPCHK(s, hipMemsetAsync(dst[f], 0, b, s->st));
+    }
+    if (apply_bc) {
+        hosc_status r = impose_bc(s);
+        if (r) return r;
+    }
+    return reset_state(s);
+}
+
+hosc_status hosc_init_fields(hosc_solver *s, uint64_t seed, double noise_amp)
+{
+    if (!s) return HOSC_E_ARG;
+    if (!std::isfinite(noise_amp)) return fail(s, HOSC_E_ARG, "noise_amp must be finite");
+    const int N = s->g.N, M = N - 2;
+    std::vector<double> T(s->g.n3);
+    const double th = s->P.theta_hot, tc = s->P.theta_cold;
+    uint64_t draw = 0;
+    for (int k = 0; k < N; ++k)
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) {
+                const double x = (double)i / (N - 1);
+                double t = th + (tc - th) * x;
+                const bool interior = i > 0 && j > 0 && k > 0 && i < N - 1 && j < N - 1 && k < N - 1;
+                if (interior && noise_amp != 0.0 && M > 0) {
+                    const double U = (double)(splitmix64(seed, draw) >> 11) * 0x1.0p-53;
+                    t += noise_amp * (2.0 * U - 1.0);
+                }
+                if (interior) ++draw;
+                T[(size_t)i + (size_t)N * ((size_t)j + (size_t)N * k)] = t;
+            }
+    return hosc_set_state(s, nullptr, nullptr, nullptr, T.data(), nullptr, 1);
+}
+
+hosc_status hosc_get_state(hosc_solver *s, double *u, double *v, double *w, double *theta, double *p)
+{
+    if (!s) return HOSC_E_ARG;
+    if (!s->has_state) return fail(s, HOSC_E_STATE, "no state set");
+    const size_t b = s->g.n3 * sizeof(double);
+    double *dst[5] = {u, v, w, theta, p};
+    const double *src[5] = {s->u, s->v, s->w, s->T, s->p};
+    for (int f = 0; f < 5; ++f)
+        if (dst[f]) HIPCHK(s, hipMemcpyAsync(dst[f], src[f], b, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    return HOSC_OK;
+}
+
+hosc_status hosc_step(hosc_solver *s, int32_t nsteps, hosc_step_info *info)
+{
+    if (!s) return HOSC_E_ARG;
+    if (nsteps < 0) return fail(s, HOSC_E_ARG, "nsteps must be >= 0");
+    if (!s->has_state) return fail(s, HOSC_E_STATE, "no state set");
+    if (s->sticky) return fail(s, HOSC_E_STATE, "solver is in an error state; set a new state");
+    for (int q = 0; q < nsteps; ++q) {
+        hosc_status r = one_step(s, info);
+        if (r) {
+            if (r == HOSC_E_NOCONV || r == HOSC_E_NONFINITE) s->sticky = r;
+            if (info) info->status = r;
+            return r;
+        }
+    }
+    return HOSC_OK;
+}
+
+hosc_status hosc_run_to_steady(hosc_solver *s, double res_tol, int64_t max_steps, hosc_step_info *info)
+{
+    if (!s) return HOSC_E_ARG;
+    if (!(res_tol > 0.0)) return fail(s, HOSC_E_ARG, "res_tol must be > 0");
+    hosc_step_info local;
+    hosc_step_info *ip = info ? info : &local;
+    for (int64_t q = 0; q < max_steps; ++q) {
+        hosc_status r = hosc_step(s, 1, ip);
+        if (r) return r;
+        const double m = std::max(std::max(ip->res[0], ip->res[1]), std::max(ip->res[2], ip->res[3]));
+        if (m < res_tol) return HOSC_OK;
+    }
+    return HOSC_OK;
+}
+
+hosc_status hosc_diagnostics(hosc_solver *s, hosc_diag *d, double *nuavg_hot, double *nuavg_cold, double *nu_hot,
+                             double *nu_cold)
+{
+    if (!s || !d) return HOSC_E_ARG;
+    if (!s->has_state) return fail(s, HOSC_E_STATE, "no state set");
+    const Geo &g = s->g;
+    dim3 b2(16, 16), g2((g.N + 15) / 16, (g.N + 15) / 16);
+    k_nu_local<<<g2, b2, 0, s->st>>>(g, s->T, s->nuh, s->nuc);
+    k_nu_avg<<<(g.N + 63) / 64, 64, 0, s->st>>>(g, s->wq, s->nuh, s->nuc, s->avh, s->avc);
+    k_nu_final<<<1, 64, 0, s->st>>>(g, s->wq, s->avh, s->avc, s->nuh, s->nuout);
+    k_entropy<<<s->L.grd_all, s->L.blk_all, 0, s->st>>>(g, s->ph, s->wq, s->u, s->v, s->w, s->T, nullptr, nullptr,
+                                                         s->partR);
+    k_reduce<<<1, 256, 0, s->st>>>(s->partR, (int)s->L.nb_all, 3, 0, s->red + 24);
+    hosc_status r = launch_check(s, "diagnostics");
+    if (r) return r;
+    HIPCHK(s, hipMemcpyAsync(s->hbuf, s->nuout, 5 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipMemcpyAsync(s->hbuf + 8, s->red + 24, 3 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+    const size_t nb = (size_t)g.N * sizeof(double), n2 = (size_t)g.N * g.N * sizeof(double);
+    if (nuavg_hot) HIPCHK(s, hipMemcpyAsync(nuavg_hot, s->avh, nb, hipMemcpyDeviceToHost, s->st));
+    if (nuavg_cold) HIPCHK(s, hipMemcpyAsync(nuavg_cold, s->avc, nb, hipMemcpyDeviceToHost, s->st));
+    if (nu_hot) HIPCHK(s, hipMemcpyAsync(nu_hot, s->nuh, n2, hipMemcpyDeviceToHost, s->st));
+    if (nu_cold) HIPCHK(s, hipMemcpyAsync(nu_cold, s->nuc, n2, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    const double *hb = s->hbuf;
+    d->nu_mean_hot = hb[0];
+    d->nu_mean_cold = hb[1];
+    d->nu_max_hot = hb[2];
+    d->nu_max_cold = hb[3];
+    d->nu_local_max_hot = hb[4];
+    d->e_ht = hb[8];
+    d->e_ff = hb[9];
+    d->e_total = hb[8] + hb[9];
+    d->be_global = d->e_total > 0.0 ? hb[8] / d->e_total : 1.0;
+    d->be_mean = hb[10];
+    return HOSC_OK;
+}
+
+hosc_status hosc_entropy_fields(hosc_solver *s, double *e_local, double *be_local)
+{
+    if (!s) return HOSC_E_ARG;
+    if (!s->has_state) return fail(s, HOSC_E_STATE, "no state set");
+    // each field goes through the scratch array and is copied out before the next
+    k_entropy<<<s->L.grd_all, s->L.blk_all, 0, s->st>>>(s->g, s->ph, s->wq, s->u, s->v, s->w, s->T, s->dbg,
+                                                         nullptr, s->partR);
+    hosc_status r = launch_check(s, "entropy");
+    if (r) return r;
+    const size_t b = s->g.n3 * sizeof(double);
+    if (e_local) HIPCHK(s, hipMemcpyAsync(e_local, s->dbg, b, hipMemcpyDeviceToHost, s->st));
+    if (be_local) {
+        k_entropy<<<s->L.grd_all, s->L.blk_all, 0, s->st>>>(s->g, s->ph, s->wq, s->u, s->v, s->w, s->T, nullptr,
+                                                             s->dbg, s->partR);
+        r = launch_check(s, "entropy");
+        if (r) return r;
+        HIPCHK(s, hipMemcpyAsync(be_local, s->dbg, b, hipMemcpyDeviceToHost, s->st));
+    }
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    return HOSC_OK;
+}
+
+hosc_status hosc_debug_assemble(hosc_solver *s, double *eta, double *estar, double *b, double *Bmom, double *Btheta)
+{
+    if (!s) return HOSC_E_ARG;
+    if (!s->has_state) return fail(s, HOSC_E_STATE, "no state set");
+    hosc_status r = stage_sources(s, false);
+    if (r) return r;
+    const size_t nb = s->g.n3 * sizeof(double);
+    if (eta) HIPCHK(s, hipMemcpyAsync(eta, s->eta, nb, hipMemcpyDeviceToHost, s->st));
+    for (int d = 0; d < 3; ++d)
+        if (estar) HIPCHK(s, hipMemcpyAsync(estar + d * s->g.n3, s->E[d], nb, hipMemcpyDeviceToHost, s->st));
+    for (int what = 0; what < 18; ++what) {
+        double *dst = nullptr;
+        if (what < 7) dst = Bmom ? Bmom + (size_t)what * s->g.n3 : nullptr;
+        else if (what < 14) dst = Btheta ? Btheta + (size_t)(what - 7) * s->g.n3 : nullptr;
+        else dst = b ? b + (size_t)(what - 14) * s->g.n3 : nullptr;
+        if (!dst) continue;
+        HIPCHK(s, hipMemsetAsync(s->dbg, 0, nb, s->st));
+        k_assemble_debug<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(
+            s->g, s->ph, s->u, s->v, s->w, s->T, s->eta, s->E[0], s->E[1], s->E[2], s->u2, s->v2, s->w2, s->etap,
+            s->Ep[0], s->Ep[1], s->Ep[2], what, s->dbg);
+        r = launch_check(s, "assemble_debug");
+        if (r) return r;
+        HIPCHK(s, hipMemcpyAsync(dst, s->dbg, nb, hipMemcpyDeviceToHost, s->st));
+        HIPCHK(s, hipStreamSynchronize(s->st));
+    }
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    return HOSC_OK;
+}
+
+hosc_status hosc_perf_enable(hosc_solver *s, int32_t on)
+{
+    if (!s) return HOSC_E_ARG;
+    hosc_status r = harvest_events(s);
+    if (r) return r;
+    if (on && s->ev.empty()) {
+        s->ev.resize(2 * kEvPairs);
+        s->ev_bytes.resize(kEvPairs);
+        s->ev_kind.resize(kEvPairs);
+        for (auto &e : s->ev) HIPCHK(s, hipEventCreate(&e));
+    }
+    s->prof = on != 0;
+    s->perf = hosc_perf{};
+    s->ev_used = 0;
+    return HOSC_OK;
+}
+
+hosc_status hosc_perf_get(hosc_solver *s, hosc_perf *out)
+{
+    if (!s || !out) return HOSC_E_ARG;
+    hosc_status r = harvest_events(s);
+    if (r) return r;
+    *out = s->perf;
+    return HOSC_OK;
+}
+
+const char *hosc_last_error(const hosc_solver *s)
+{
+    if (!s) return g_create_error.c_str();
+    return s->err.c_str();
+}
+
+const char *hosc_status_string(hosc_status st)
+{
+    switch (st) {
+    case HOSC_OK: return "HOSC_OK";
+    case HOSC_E_ARG: return "HOSC_E_ARG";
+    case HOSC_E_NOMEM: return "HOSC_E_NOMEM";
+    case HOSC_E_DEVICE: return "HOSC_E_DEVICE";
+    case HOSC_E_NOCONV: return "HOSC_E_NOCONV";
+    case HOSC_E_NONFINITE: return "HOSC_E_NONFINITE";
+    case HOSC_E_STATE: return "HOSC_E_STATE";
+    case HOSC_E_BUDGET: return "HOSC_E_BUDGET";
+    }
+    return "unknown";
+}
+
+}  // extern "C"

@@ -1,0 +1,796 @@
+// hosc_kernels.hpp -- gfx950 kernels of the HOSC time step (Punia & Ray, arXiv
+// 2411.06563, Sec. 2) and of its diagnostics (Secs. 4.2, 4.3).
+//
+// Layouts in HBM
+//   natural   : N^3 doubles, node (i,j,k) at i + N*(j + N*k)  (u, v, w, theta, p,
+//               eta, E*, and their level n-1 copies).  x is the unit-stride axis.
+//   colour    : the red-black split used by the implicit solves.  Node (i,j,k) has
+//               colour c = (i+j+k) & 1 and lives in colour array c at
+//               (k*N + j)*H + (i >> 1), H = (N+1)/2.  Inside one (j,k) row all nodes
+//               of a colour share the parity of i, so a wavefront that updates a row
+//               of one colour reads its x-neighbours at q and q +- 1 of the other
+//               colour and its y/z neighbours at the same q of the rows j+-1, k+-1:
+//               every access is unit-stride and no cache line carries unused nodes.
+//
+// Each implicit 7-point row is stored divided by its centre weight C: for the
+// momentum system s/C and a_d/C (off-diagonal weights (s -+ a_d)/C towards x_d +- h),
+// b/C; for the energy system a_d/C (s/C is a constant).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hosc {
+
+struct Geo {
+    int N;          // nodes per side
+    int H;          // entries per colour row
+    int Q;          // colour-row entries that can hold interior nodes
+    int pad;
+    double h, h2, inv2h, invh2;
+    size_t n3;      // N^3
+    size_t cs;      // entries of one colour array (N*N*H)
+};
+
+struct Phys {
+    double Ra, Pr, dt, theta_hot, theta_cold, theta_ref, i2_floor, ex, lambda, phi;
+};
+
+__device__ __forceinline__ size_t nid(const Geo &g, int i, int j, int k)
+{
+    return (size_t)i + (size_t)g.N * ((size_t)j + (size_t)g.N * (size_t)k);
+}
+__device__ __forceinline__ size_t rowid(const Geo &g, int j, int k) { return ((size_t)k * g.N + j) * g.H; }
+
+// ---------------------------------------------------------------------------
+// Deterministic block reductions (fixed shuffle tree inside a wavefront, fixed
+// order across the wavefronts of a block).  Every thread of the block must call.
+// ---------------------------------------------------------------------------
+template <int NV>
+__device__ __forceinline__ void block_sum_store(double (&v)[NV], double *out)
+{
+    __shared__ double sh[NV][16];
+    const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+    const int nthr = blockDim.x * blockDim.y * blockDim.z;
+    const int lane = tid & 63, wave = tid >> 6, nwave = (nthr + 63) >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double x = v[q];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+        if (lane == 0) sh[q][wave] = x;
+    }
+    __syncthreads();
+    if (tid < NV) {
+        double s = 0.0;
+        for (int w = 0; w < nwave; ++w) s += sh[tid][w];
+        out[tid] = s;
+    }
+}
+
+// max that propagates NaN
+__device__ __forceinline__ double nanmax(double a, double b) { return (a > b || a != a) ? a : b; }
+
+template <int NV>
+__device__ __forceinline__ void block_max_store(double (&v)[NV], double *out)
+{
+    __shared__ double sh[NV][16];
+    const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+    const int nthr = blockDim.x * blockDim.y * blockDim.z;
+    const int lane = tid & 63, wave = tid >> 6, nwave = (nthr + 63) >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double x = v[q];
+        for (int off = 32; off > 0; off >>= 1) x = nanmax(x, __shfl_down(x, off, 64));
+        if (lane == 0) sh[q][wave] = x;
+    }
+    __syncthreads();
+    if (tid < NV) {
+        double s = sh[tid][0];
+        for (int w = 1; w < nwave; ++w) s = nanmax(s, sh[tid][w]);
+        out[tid] = s;
+    }
+}
+
+// Reduce nb partial records of nc values (record b at part[b*nc ...]) with one
+// block of 256 threads; op 0 = sum, 1 = max.  Fixed order: deterministic.
+__global__ void __launch_bounds__(256) k_reduce(const double *part, int nb, int nc, int op, double *out)
+{
+    __shared__ double sh[8][256];
+    const int t = threadIdx.x;
+    for (int c = 0; c < nc; ++c) {
+        double s = op == 0 ? 0.0 : -HUGE_VAL;
+        for (int b = t; b < nb; b += 256) s = op == 0 ? s + part[(size_t)b * nc + c] : nanmax(s, part[(size_t)b * nc + c]);
+        sh[c][t] = s;
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+            for (int c = 0; c < nc; ++c) sh[c][t] = op == 0 ? sh[c][t] + sh[c][t + w] : nanmax(sh[c][t], sh[c][t + w]);
+        __syncthreads();
+    }
+    if (t < nc) out[t] = sh[t][0];
+}
+
+// ---------------------------------------------------------------------------
+// Derivatives at any node: central inside, 2nd-order one-sided on a wall normal to
+// the axis (velocity, eta, theta); the wall-normal pressure derivative is zero.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double dnode(const double *f, size_t c, size_t s, int idx, int N, double inv2h)
+{
+    if (idx == 0) return (-3.0 * f[c] + 4.0 * f[c + s] - f[c + 2 * s]) * inv2h;
+    if (idx == N - 1) return (3.0 * f[c] - 4.0 * f[c - s] + f[c - 2 * s]) * inv2h;
+    return (f[c + s] - f[c - s]) * inv2h;
+}
+__device__ __forceinline__ double dpnode(const double *p, size_t c, size_t s, int idx, int N, double inv2h)
+{
+    if (idx == 0 || idx == N - 1) return 0.0;
+    return (p[c + s] - p[c - s]) * inv2h;
+}
+
+struct VelGrad {
+    double ux, uy, uz, vx, vy, vz, wx, wy, wz;
+};
+
+__device__ __forceinline__ VelGrad vel_grad(const Geo &g, const double *u, const double *v, const double *w, int i,
+                                            int j, int k)
+{
+    const size_t c = nid(g, i, j, k), sy = (size_t)g.N, sz = (size_t)g.N * g.N;
+    VelGrad d;
+    d.ux = dnode(u, c, 1, i, g.N, g.inv2h);
+    d.uy = dnode(u, c, sy, j, g.N, g.inv2h);
+    d.uz = dnode(u, c, sz, k, g.N, g.inv2h);
+    d.vx = dnode(v, c, 1, i, g.N, g.inv2h);
+    d.vy = dnode(v, c, sy, j, g.N, g.inv2h);
+    d.vz = dnode(v, c, sz, k, g.N, g.inv2h);
+    d.wx = dnode(w, c, 1, i, g.N, g.inv2h);
+    d.wy = dnode(w, c, sy, j, g.N, g.inv2h);
+    d.wz = dnode(w, c, sz, k, g.N, g.inv2h);
+    return d;
+}
+
+// Second invariant of the strain rate (Sec. 2.1, viscosity formula).
+__device__ __forceinline__ double strain_I2(const VelGrad &d)
+{
+    const double a = d.uz + d.wx, b = d.uy + d.vx, e = d.vz + d.wy;
+    return 2.0 * (d.ux * d.ux + d.vy * d.vy + d.wz * d.wz) + a * a + b * b + e * e;
+}
+
+// eta = max(I2, floor)^((n-1)/2) at every node (Sec. 2.1, power law).
+__global__ void __launch_bounds__(256) k_eta(Geo g, Phys P, const double *__restrict__ u, const double *__restrict__ v,
+                                             const double *__restrict__ w, double *__restrict__ eta)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y * blockDim.y + threadIdx.y, k = blockIdx.z;
+    if (i >= g.N || j >= g.N) return;
+    const VelGrad d = vel_grad(g, u, v, w, i, j, k);
+    eta[nid(g, i, j, k)] = pow(fmax(strain_I2(d), P.i2_floor), P.ex);
+}
+
+// Momentum sources at every node: the right-hand sides of the three momentum
+// equations (Sec. 2.1, expanded stress divergence) divided by Pr eta, which puts
+// them in the form of the generic transport PDE with L = 1/(Pr eta).
+__global__ void __launch_bounds__(256) k_estar(Geo g, Phys P, const double *__restrict__ u,
+                                               const double *__restrict__ v, const double *__restrict__ w,
+                                               const double *__restrict__ T, const double *__restrict__ p,
+                                               const double *__restrict__ eta, double *__restrict__ Eu,
+                                               double *__restrict__ Ev, double *__restrict__ Ew)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y * blockDim.y + threadIdx.y, k = blockIdx.z;
+    if (i >= g.N || j >= g.N) return;
+    const size_t c = nid(g, i, j, k), sy = (size_t)g.N, sz = (size_t)g.N * g.N;
+    const VelGrad d = vel_grad(g, u, v, w, i, j, k);
+    const double ex = dnode(eta, c, 1, i, g.N, g.inv2h), ey = dnode(eta, c, sy, j, g.N, g.inv2h),
+                 ez = dnode(eta, c, sz, k, g.N, g.inv2h);
+    const double px = dpnode(p, c, 1, i, g.N, g.inv2h), py = dpnode(p, c, sy, j, g.N, g.inv2h),
+                 pz = dpnode(p, c, sz, k, g.N, g.inv2h);
+    const double L = 1.0 / (P.Pr * eta[c]);
+    const double sxy = d.uy + d.vx, sxz = d.uz + d.wx, syz = d.vz + d.wy;
+    Eu[c] = L * (-px + P.Pr * (2.0 * d.ux * ex + sxy * ey + sxz * ez));
+    Ev[c] = L * (-py + P.Pr * (sxy * ex + 2.0 * d.vy * ey + syz * ez) + P.Ra * P.Pr * (T[c] - P.theta_ref));
+    Ew[c] = L * (-pz + P.Pr * (sxz * ex + syz * ey + 2.0 * d.wz * ez));
+}
+
+// ---------------------------------------------------------------------------
+// HOSC assembly at one interior node (Sec. 2.2).
+//
+// Implicit side: the seven weights L1..L7 of the paper, written as
+//     L1, L2 = s -+ a_x,  L3, L4 = s -+ a_y,  L5, L6 = s -+ a_z,  L7 = C
+// with c = L M_1 (= L h^2/12 - dt/2), s = c/h^2, e_d = L M15 (= (h^2/6) delta_d L),
+// a_d = (c V_d - e_d)/(2h), C = L (1 + 2 M_4 M18/dt) - 6 c/h^2.
+// Explicit side: b = sum_m Q_m chi_m + dt R - sum_m L_m chi_m, i.e. the paper's Q
+// weights minus the L weights: on the 7 central points Q - L keeps the dt alpha,
+// dt M1, ... parts of N1..N6; on the 12 edge points Q is taken as printed.  We
+// store W_m = (Q_m - L_m)/dt and form b = dt (R + sum_m W_m chi_m).
+// ---------------------------------------------------------------------------
+
+// Offsets of the 19 points in the paper's Q numbering: centre, x+, x-, y+, y-, z+, z-
+// (Q2, Q1, Q3, Q4, Q5, Q6, Q7), then Q8..Q19.
+struct Coef19 {
+    double W[19];
+};
+
+// W_m = (Q_m - L_m)/dt for a system with convection V = (G, H, I) given at the 7
+// central points (index 0 centre, 1 x+, 2 x-, 3 y+, 4 y-, 5 z+, 6 z-) and at level
+// n-1 at the centre.
+__device__ __forceinline__ void explicit_weights(const Geo &g, double dt, const double (&G)[7], const double (&Hc)[7],
+                                                 const double (&I)[7], double Gp, double Hp, double Ip, Coef19 &cw)
+{
+    const double h = g.h, k = g.h, l = g.h;
+    const double hh = h * h, kk = k * k, ll = l * l;
+    const double i2h = g.inv2h, ih2 = g.invh2;
+    const double G0 = G[0], H0 = Hc[0], I0 = I[0];
+    // first and second central differences of the convective coefficients
+    const double Gx = (G[1] - G[2]) * i2h, Gy = (G[3] - G[4]) * i2h, Gz = (G[5] - G[6]) * i2h;
+    const double Hx = (Hc[1] - Hc[2]) * i2h, Hy = (Hc[3] - Hc[4]) * i2h, Hz = (Hc[5] - Hc[6]) * i2h;
+    const double Ix = (I[1] - I[2]) * i2h, Iy = (I[3] - I[4]) * i2h, Iz = (I[5] - I[6]) * i2h;
+    const double Gxx = (G[1] - 2.0 * G0 + G[2]) * ih2, Gyy = (G[3] - 2.0 * G0 + G[4]) * ih2,
+                 Gzz = (G[5] - 2.0 * G0 + G[6]) * ih2;
+    const double Hxx = (Hc[1] - 2.0 * H0 + Hc[2]) * ih2, Hyy = (Hc[3] - 2.0 * H0 + Hc[4]) * ih2,
+                 Hzz = (Hc[5] - 2.0 * H0 + Hc[6]) * ih2;
+    const double Ixx = (I[1] - 2.0 * I0 + I[2]) * ih2, Iyy = (I[3] - 2.0 * I0 + I[4]) * ih2,
+                 Izz = (I[5] - 2.0 * I0 + I[6]) * ih2;
+    // alpha, beta, gamma (K* = 0)
+    const double alpha = (G0 * G0 - 2.0 * Gx) * hh / 12.0 + 1.0;
+    const double beta = (H0 * H0 - 2.0 * Hy) * kk / 12.0 + 1.0;
+    const double gamma = (I0 * I0 - 2.0 * Iz) * ll / 12.0 + 1.0;
+    // M1, M2, M3: the bracket [1 + (dxx - G dx) h^2/12 + (dyy - H dy) k^2/12 +
+    // (dzz - I dz) l^2/12 + (dt/2) delta_t^-] applied to G*, H*, I*
+    const double M1 = G0 + (Gxx - G0 * Gx) * hh / 12.0 + (Gyy - H0 * Gy) * kk / 12.0 + (Gzz - I0 * Gz) * ll / 12.0
+                      + 0.5 * dt * ((G0 - Gp) / dt);
+    const double M2 = H0 + (Hxx - G0 * Hx) * hh / 12.0 + (Hyy - H0 * Hy) * kk / 12.0 + (Hzz - I0 * Hz) * ll / 12.0
+                      + 0.5 * dt * ((H0 - Hp) / dt);
+    const double M3 = I0 + (Ixx - G0 * Ix) * hh / 12.0 + (Iyy - H0 * Iy) * kk / 12.0 + (Izz - I0 * Iz) * ll / 12.0
+                      + 0.5 * dt * ((I0 - Ip) / dt);
+    const double p1 = -G0 * H0 + 2.0 / (hh + kk) * (kk * Gy + hh * Hx);
+    const double q1 = -H0 * I0 + 2.0 / (kk + ll) * (ll * Hz + kk * Iy);
+    const double r1 = -I0 * G0 + 2.0 / (ll + hh) * (hh * Ix + ll * Gz);
+    const double M5 = (hh + kk) / 12.0, M6 = (kk + ll) / 12.0, M7 = (ll + hh) / 12.0;
+    const double c5 = M5 / (hh * kk), c6 = M6 / (kk * ll), c7 = M7 / (ll * hh);
+    // Q2 - L7 and Q1 - L1 ... Q7 - L6, divided by dt
+    cw.W[0] = -2.0 * (alpha / hh + beta / kk + gamma / ll) + 4.0 * (c5 + c6 + c7);
+    cw.W[1] = alpha / hh - M1 / (2.0 * h) - 2.0 * c5 + M5 * G0 / (h * kk) - 2.0 * c7 + M7 * G0 / (h * ll);
+    cw.W[2] = alpha / hh + M1 / (2.0 * h) - 2.0 * c5 - M5 * G0 / (h * kk) - 2.0 * c7 - M7 * G0 / (h * ll);
+    cw.W[3] = beta / kk - M2 / (2.0 * k) - 2.0 * c5 + M5 * H0 / (hh * k) - 2.0 * c6 + M6 * H0 / (k * ll);
+    cw.W[4] = beta / kk + M2 / (2.0 * k) - 2.0 * c5 - M5 * H0 / (hh * k) - 2.0 * c6 - M6 * H0 / (k * ll);
+    cw.W[5] = gamma / ll - M3 / (2.0 * l) - 2.0 * c6 + M6 * I0 / (kk * l) - 2.0 * c7 + M7 * I0 / (l * hh);
+    cw.W[6] = gamma / ll + M3 / (2.0 * l) - 2.0 * c6 - M6 * I0 / (kk * l) - 2.0 * c7 - M7 * I0 / (l * hh);
+    // Q8..Q19 / dt
+    const double a5 = M5 * p1 / (4.0 * h * k), g5 = M5 * G0 / (2.0 * h * kk), h5 = M5 * H0 / (2.0 * hh * k);
+    cw.W[7] = c5 - a5 - h5 - g5;     // (i+1, j+1)
+    cw.W[8] = c5 + a5 - h5 + g5;     // (i-1, j+1)
+    cw.W[9] = c5 + a5 + h5 - g5;     // (i+1, j-1)
+    cw.W[10] = c5 - a5 + h5 + g5;    // (i-1, j-1)
+    const double a6 = M6 * q1 / (4.0 * k * l), i6 = M6 * I0 / (2.0 * kk * l), h6 = M6 * H0 / (2.0 * k * ll);
+    cw.W[11] = c6 - a6 - i6 - h6;    // (j+1, k+1)
+    cw.W[12] = c6 + a6 - i6 + h6;    // (j-1, k+1)
+    cw.W[13] = c6 + a6 + i6 - h6;    // (j+1, k-1)
+    cw.W[14] = c6 - a6 + i6 + h6;    // (j-1, k-1)
+    const double a7 = M7 * r1 / (4.0 * l * h), g7 = M7 * G0 / (2.0 * ll * h), i7 = M7 * I0 / (2.0 * l * hh);
+    cw.W[15] = c7 - a7 - g7 - i7;    // (i+1, k+1)
+    cw.W[16] = c7 + a7 - g7 + i7;    // (i+1, k-1)
+    cw.W[17] = c7 + a7 + g7 - i7;    // (i-1, k+1)
+    cw.W[18] = c7 - a7 + g7 + i7;    // (i-1, k-1)
+}
+
+__device__ __forceinline__ void offsets19(const Geo &g, size_t c, size_t (&o)[19])
+{
+    const size_t sy = (size_t)g.N, sz = (size_t)g.N * g.N;
+    o[0] = c;
+    o[1] = c + 1; o[2] = c - 1; o[3] = c + sy; o[4] = c - sy; o[5] = c + sz; o[6] = c - sz;
+    o[7] = c + 1 + sy; o[8] = c - 1 + sy; o[9] = c + 1 - sy; o[10] = c - 1 - sy;
+    o[11] = c + sy + sz; o[12] = c - sy + sz; o[13] = c + sy - sz; o[14] = c - sy - sz;
+    o[15] = c + 1 + sz; o[16] = c + 1 - sz; o[17] = c - 1 + sz; o[18] = c - 1 - sz;
+}
+
+// bracket operator of the source: R = [1 + sum (d_dd - V_d d_d) h^2/12 + (dt/2) delta_t^-] E*
+__device__ __forceinline__ double source_R(const Geo &g, double dt, const double (&E)[7], double Ep, double G0,
+                                           double H0, double I0)
+{
+    const double hh = g.h2;
+    const double Ex = (E[1] - E[2]) * g.inv2h, Ey = (E[3] - E[4]) * g.inv2h, Ez = (E[5] - E[6]) * g.inv2h;
+    const double Exx = (E[1] - 2.0 * E[0] + E[2]) * g.invh2, Eyy = (E[3] - 2.0 * E[0] + E[4]) * g.invh2,
+                 Ezz = (E[5] - 2.0 * E[0] + E[6]) * g.invh2;
+    return E[0] + (Exx - G0 * Ex) * hh / 12.0 + (Eyy - H0 * Ey) * hh / 12.0 + (Ezz - I0 * Ez) * hh / 12.0
+           + 0.5 * dt * ((E[0] - Ep) / dt);
+}
+
+struct NodeAssembly {
+    double Cm, sm, am[3];   // momentum row: centre, s, a_d
+    double Ct, st, at[3];   // energy row
+    double b[4];            // right-hand sides of the u, v, w, theta increments
+};
+
+template <typename Tin>
+__device__ __forceinline__ void assemble_node(const Geo &g, const Phys &P, int i, int j, int k, const Tin *u,
+                                              const Tin *v, const Tin *w, const Tin *T, const Tin *eta,
+                                              const Tin *Eu, const Tin *Ev, const Tin *Ew, const Tin *up,
+                                              const Tin *vp, const Tin *wp, const Tin *etap, const Tin *Eup,
+                                              const Tin *Evp, const Tin *Ewp, NodeAssembly &out)
+{
+    const size_t c = nid(g, i, j, k);
+    size_t o[19];
+    offsets19(g, c, o);
+    const double dt = P.dt, hh = g.h2;
+    // ---- momentum coefficients: L = 1/(Pr eta), (G*, H*, I*) = (u, v, w) L
+    double Lm[7], G[7], Hm[7], I[7];
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+        Lm[m] = 1.0 / (P.Pr * eta[o[m]]);
+        G[m] = u[o[m]] * Lm[m];
+        Hm[m] = v[o[m]] * Lm[m];
+        I[m] = w[o[m]] * Lm[m];
+    }
+    const double Lp = 1.0 / (P.Pr * etap[c]);
+    const double Gp = up[c] * Lp, Hp = vp[c] * Lp, Ip = wp[c] * Lp;
+    {
+        const double L0 = Lm[0];
+        const double Lx = (Lm[1] - Lm[2]) * g.inv2h, Ly = (Lm[3] - Lm[4]) * g.inv2h, Lz = (Lm[5] - Lm[6]) * g.inv2h;
+        const double Lxx = (Lm[1] - 2.0 * L0 + Lm[2]) * g.invh2, Lyy = (Lm[3] - 2.0 * L0 + Lm[4]) * g.invh2,
+                     Lzz = (Lm[5] - 2.0 * L0 + Lm[6]) * g.invh2;
+        // M18 = [(dt/2) delta_t^- + sum (d_dd - V_d d_d) h_d^2/12] L
+        const double M18 = dt / 2.0 * ((L0 - Lp) / dt) + (Lxx - G[0] * Lx) * hh / 12.0
+                           + (Lyy - Hm[0] * Ly) * hh / 12.0 + (Lzz - I[0] * Lz) * hh / 12.0;
+        const double M_1 = -dt / (2.0 * L0) + hh / 12.0;   // M_1 = M_2 = M_3 (h = k = l)
+        const double cc = L0 * M_1;
+        const double M_4 = dt / (2.0 * L0);
+        out.Cm = (1.0 + 2.0 * M_4 * M18 / dt) * L0 - 6.0 * cc * g.invh2;
+        out.sm = cc * g.invh2;
+        // L M15 = (h^2/6) dL/dx, etc.
+        out.am[0] = (cc * G[0] - hh / 6.0 * Lx) * g.inv2h;
+        out.am[1] = (cc * Hm[0] - hh / 6.0 * Ly) * g.inv2h;
+        out.am[2] = (cc * I[0] - hh / 6.0 * Lz) * g.inv2h;
+    }
+    // ---- momentum right-hand sides
+    {
+        Coef19 cw;
+        explicit_weights(g, dt, G, Hm, I, Gp, Hp, Ip, cw);
+        double su = 0.0, sv = 0.0, sw = 0.0;
+#pragma unroll
+        for (int m = 0; m < 19; ++m) {
+            su += cw.W[m] * u[o[m]];
+            sv += cw.W[m] * v[o[m]];
+            sw += cw.W[m] * w[o[m]];
+        }
+        double E7[7];
+#pragma unroll
+        for (int m = 0; m < 7; ++m) E7[m] = Eu[o[m]];
+        const double Ru = source_R(g, dt, E7, Eup[c], G[0], Hm[0], I[0]);
+#pragma unroll
+        for (int m = 0; m < 7; ++m) E7[m] = Ev[o[m]];
+        const double Rv = source_R(g, dt, E7, Evp[c], G[0], Hm[0], I[0]);
+#pragma unroll
+        for (int m = 0; m < 7; ++m) E7[m] = Ew[o[m]];
+        const double Rw = source_R(g, dt, E7, Ewp[c], G[0], Hm[0], I[0]);
+        out.b[0] = dt * (Ru + su);
+        out.b[1] = dt * (Rv + sv);
+        out.b[2] = dt * (Rw + sw);
+    }
+    // ---- energy: L = 1, (G*, H*, I*) = (u, v, w), K* = E* = 0
+    {
+        double uu[7], vv[7], ww[7];
+#pragma unroll
+        for (int m = 0; m < 7; ++m) {
+            uu[m] = u[o[m]];
+            vv[m] = v[o[m]];
+            ww[m] = w[o[m]];
+        }
+        const double ct = hh / 12.0 - dt / 2.0;     // L M_1 with L = 1
+        out.Ct = 1.0 - 6.0 * ct * g.invh2;          // M18 = 0 and M15..M17 = 0 for constant L
+        out.st = ct * g.invh2;
+        out.at[0] = ct * uu[0] * g.inv2h;
+        out.at[1] = ct * vv[0] * g.inv2h;
+        out.at[2] = ct * ww[0] * g.inv2h;
+        Coef19 cw;
+        explicit_weights(g, dt, uu, vv, ww, up[c], vp[c], wp[c], cw);
+        double st = 0.0;
+#pragma unroll
+        for (int m = 0; m < 19; ++m) st += cw.W[m] * T[o[m]];
+        out.b[3] = dt * st;
+    }
+}
+
+struct ColourArrays {
+    double *ms, *ma[3], *mb[3];     // momentum: s/C, a_d/C, b/C (u, v, w)
+    double *ta[3], *tb;             // energy: a_d/C, b/C
+};
+
+// Assemble every interior node and write the scaled rows in the colour layout;
+// per-block partial sums of ||b/C||^2 for the four systems.
+__global__ void __launch_bounds__(256) k_assemble(Geo g, Phys P, const double *__restrict__ u,
+                                                  const double *__restrict__ v, const double *__restrict__ w,
+                                                  const double *__restrict__ T, const double *__restrict__ eta,
+                                                  const double *__restrict__ Eu, const double *__restrict__ Ev,
+                                                  const double *__restrict__ Ew, const double *__restrict__ up,
+                                                  const double *__restrict__ vp, const double *__restrict__ wp,
+                                                  const double *__restrict__ etap, const double *__restrict__ Eup,
+                                                  const double *__restrict__ Evp, const double *__restrict__ Ewp,
+                                                  ColourArrays ca, double *__restrict__ partial)
+{
+    const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x, j = 1 + blockIdx.y * blockDim.y + threadIdx.y,
+              k = 1 + blockIdx.z;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i <= g.N - 2 && j <= g.N - 2) {
+        NodeAssembly a;
+        assemble_node(g, P, i, j, k, u, v, w, T, eta, Eu, Ev, Ew, up, vp, wp, etap, Eup, Evp, Ewp, a);
+        const size_t idx = (size_t)((i + j + k) & 1) * g.cs + rowid(g, j, k) + (i >> 1);
+        const double rm = 1.0 / a.Cm, rt = 1.0 / a.Ct;
+        ca.ms[idx] = a.sm * rm;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            ca.ma[d][idx] = a.am[d] * rm;
+            const double bb = a.b[d] * rm;
+            ca.mb[d][idx] = bb;
+            acc[d] = bb * bb;
+            ca.ta[d][idx] = a.at[d] * rt;
+        }
+        const double bt = a.b[3] * rt;
+        ca.tb[idx] = bt;
+        acc[3] = bt * bt;
+    }
+    const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    block_sum_store<4>(acc, partial + (size_t)blk * 4);
+}
+
+// Parity hook: one selected assembled quantity, unscaled, in the natural layout:
+// what 0..6 momentum weight (centre, x+, x-, y+, y-, z+, z-), 7..13 energy weight,
+// 14..17 b of u, v, w, theta.
+__global__ void __launch_bounds__(256) k_assemble_debug(Geo g, Phys P, const double *u, const double *v,
+                                                        const double *w, const double *T, const double *eta,
+                                                        const double *Eu, const double *Ev, const double *Ew,
+                                                        const double *up, const double *vp, const double *wp,
+                                                        const double *etap, const double *Eup, const double *Evp,
+                                                        const double *Ewp, int what, double *out)
+{
+    const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x, j = 1 + blockIdx.y * blockDim.y + threadIdx.y,
+              k = 1 + blockIdx.z;
+    if (i > g.N - 2 || j > g.N - 2) return;
+    NodeAssembly a;
+    assemble_node(g, P, i, j, k, u, v, w, T, eta, Eu, Ev, Ew, up, vp, wp, etap, Eup, Evp, Ewp, a);
+    double val;
+    if (what < 14) {
+        const bool mom = what < 7;
+        const int m = what % 7;
+        const double C = mom ? a.Cm : a.Ct, s = mom ? a.sm : a.st;
+        const double *ad = mom ? a.am : a.at;
+        if (m == 0) val = C;
+        else {
+            const int d = (m - 1) >> 1;
+            val = (m & 1) ? s - ad[d] : s + ad[d];
+        }
+    } else {
+        val = a.b[what - 14];
+    }
+    out[nid(g, i, j, k)] = val;
+}
+
+// ---------------------------------------------------------------------------
+// Red-black SOR half-sweep on the scaled rows (momentum: three right-hand sides
+// on one matrix; energy: with the zero-normal-derivative walls eliminated:
+// next to a y or z wall the wall increment equals (4 d_1 - d_2)/3, which moves
+// 4/3 of the wall weight onto the centre and -1/3 of it onto the next node).
+// Per-block partial sums of the squared scaled residuals r = b - B d at the
+// updated nodes, before their update (when acc != 0).
+// ---------------------------------------------------------------------------
+template <typename TM>
+struct SweepArgs {
+    const TM *ms, *ma[3], *mb[3];
+    TM *md[3];
+    const TM *ta[3], *tb;
+    TM *td;
+};
+
+template <typename TM, typename TA>
+__global__ void __launch_bounds__(256) k_sweep(Geo g, int colour, int mask, TA omega, TA st, SweepArgs<TM> a,
+                                               double *__restrict__ partial, int acc)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y, k = 1 + blockIdx.z;
+    const int N = g.N;
+    double r2[4] = {0.0, 0.0, 0.0, 0.0};
+    const int i = 2 * q + ((colour + j + k) & 1);
+    if (q < g.Q && j <= N - 2 && i >= 1 && i <= N - 2) {
+        const size_t row = rowid(g, j, k);
+        const size_t me = (size_t)colour * g.cs + row + q;
+        const size_t ob = (size_t)(1 - colour) * g.cs;
+        const int sh = i & 1;
+        const size_t ixp = ob + row + q + sh, ixm = ob + row + q + sh - 1;
+        const size_t iyp = ob + rowid(g, j + 1, k) + q, iym = ob + rowid(g, j - 1, k) + q;
+        const size_t izp = ob + rowid(g, j, k + 1) + q, izm = ob + rowid(g, j, k - 1) + q;
+        if (mask & 1) {
+            const TA s = (TA)a.ms[me], ax = (TA)a.ma[0][me], ay = (TA)a.ma[1][me], az = (TA)a.ma[2][me];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                TM *d = a.md[f];
+                const TA sum = (s - ax) * (TA)d[ixp] + (s + ax) * (TA)d[ixm] + (s - ay) * (TA)d[iyp]
+                               + (s + ay) * (TA)d[iym] + (s - az) * (TA)d[izp] + (s + az) * (TA)d[izm];
+                const TA old = (TA)d[me];
+                const TA gs = (TA)a.mb[f][me] - sum;
+                const TA dlt = gs - old;
+                d[me] = (TM)(old + omega * dlt);
+                r2[f] = (double)dlt * (double)dlt;
+            }
+        }
+        if (mask & 2) {
+            const TA ax = (TA)a.ta[0][me], ay = (TA)a.ta[1][me], az = (TA)a.ta[2][me];
+            TM *d = a.td;
+            const TA wxp = st - ax, wxm = st + ax, wyp = st - ay, wym = st + ay, wzp = st - az, wzm = st + az;
+            TA den = (TA)1.0;
+            TA sum = wxp * (TA)d[ixp] + wxm * (TA)d[ixm];
+            if (j == 1) {
+                den += (TA)(4.0 / 3.0) * wym;
+                sum += (wyp - wym * (TA)(1.0 / 3.0)) * (TA)d[iyp];
+            } else if (j == N - 2) {
+                den += (TA)(4.0 / 3.0) * wyp;
+                sum += (wym - wyp * (TA)(1.0 / 3.0)) * (TA)d[iym];
+            } else {
+                sum += wyp * (TA)d[iyp] + wym * (TA)d[iym];
+            }
+            if (k == 1) {
+                den += (TA)(4.0 / 3.0) * wzm;
+                sum += (wzp - wzm * (TA)(1.0 / 3.0)) * (TA)d[izp];
+            } else if (k == N - 2) {
+                den += (TA)(4.0 / 3.0) * wzp;
+                sum += (wzm - wzp * (TA)(1.0 / 3.0)) * (TA)d[izm];
+            } else {
+                sum += wzp * (TA)d[izp] + wzm * (TA)d[izm];
+            }
+            const TA old = (TA)d[me];
+            const TA gs = ((TA)a.tb[me] - sum) / den;
+            const TA dlt = gs - old;
+            d[me] = (TM)(old + omega * dlt);
+            const double r = (double)den * (double)dlt;
+            r2[3] = r * r;
+        }
+    }
+    if (acc) {
+        const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+        block_sum_store<4>(r2, partial + (size_t)blk * 4);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Update chi^{n+1} = chi^n + dchi at interior nodes.  u, v, w go to new buffers
+// (the old level becomes level n-1); theta is updated in place.  Partial sums:
+// ||du||^2, ||dv||^2, ||dw||^2, ||dtheta||^2, ||u'||^2, ||v'||^2, ||w'||^2, ||theta'||^2.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_update(Geo g, const double *__restrict__ u, const double *__restrict__ v,
+                                                const double *__restrict__ w, double *__restrict__ un,
+                                                double *__restrict__ vn, double *__restrict__ wn,
+                                                double *__restrict__ T, const double *__restrict__ du,
+                                                const double *__restrict__ dv, const double *__restrict__ dw,
+                                                const double *__restrict__ dT, double *__restrict__ partial)
+{
+    const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x, j = 1 + blockIdx.y * blockDim.y + threadIdx.y,
+              k = 1 + blockIdx.z;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (i <= g.N - 2 && j <= g.N - 2) {
+        const size_t c = nid(g, i, j, k);
+        const size_t idx = (size_t)((i + j + k) & 1) * g.cs + rowid(g, j, k) + (i >> 1);
+        const double a = du[idx], b = dv[idx], e = dw[idx], t = dT[idx];
+        const double nu = u[c] + a, nv = v[c] + b, nw = w[c] + e, nt = T[c] + t;
+        un[c] = nu;
+        vn[c] = nv;
+        wn[c] = nw;
+        T[c] = nt;
+        acc[0] = a * a; acc[1] = b * b; acc[2] = e * e; acc[3] = t * t;
+        acc[4] = nu * nu; acc[5] = nv * nv; acc[6] = nw * nw; acc[7] = nt * nt;
+    }
+    const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    block_sum_store<8>(acc, partial + (size_t)blk * 8);
+}
+
+// ---------------------------------------------------------------------------
+// Wall closures.  Every wall node is owned by the first face (x0, x1, y0, y1, z0,
+// z1) that contains it; thread (a, b, f) handles the node (a, b) of face f.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool face_node(int N, int a, int b, int f, int &i, int &j, int &k)
+{
+    const int e = (f & 1) ? N - 1 : 0;
+    if (f < 2) { i = e; j = a; k = b; return true; }
+    if (f < 4) { i = a; j = e; k = b; return !(a == 0 || a == N - 1); }
+    i = a; j = b; k = e;
+    return !(a == 0 || a == N - 1 || b == 0 || b == N - 1);
+}
+
+// theta on the y/z walls at interior x: z walls at interior y first, then y walls
+// at every z, each by f_0 = (4 f_1 - f_2)/3 (composed here from interior values).
+__device__ __forceinline__ double theta_z_closed(const Geo &g, const double *T, int i, int j, int k)
+{
+    const int N = g.N;
+    if (k == 0) return (4.0 * T[nid(g, i, j, 1)] - T[nid(g, i, j, 2)]) / 3.0;
+    if (k == N - 1) return (4.0 * T[nid(g, i, j, N - 2)] - T[nid(g, i, j, N - 3)]) / 3.0;
+    return T[nid(g, i, j, k)];
+}
+__device__ __forceinline__ double theta_closed(const Geo &g, const double *T, int i, int j, int k)
+{
+    const int N = g.N;
+    if (j == 0) return (4.0 * theta_z_closed(g, T, i, 1, k) - theta_z_closed(g, T, i, 2, k)) / 3.0;
+    if (j == N - 1) return (4.0 * theta_z_closed(g, T, i, N - 2, k) - theta_z_closed(g, T, i, N - 3, k)) / 3.0;
+    return theta_z_closed(g, T, i, j, k);
+}
+
+// Impose the theta walls; partial sums of (new - old)^2 and new^2 over wall nodes.
+__global__ void __launch_bounds__(256) k_theta_walls(Geo g, Phys P, double *__restrict__ T, double *__restrict__ partial)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y * blockDim.y + threadIdx.y, f = blockIdx.z;
+    double acc[2] = {0.0, 0.0};
+    int i, j, k;
+    if (a < g.N && b < g.N && face_node(g.N, a, b, f, i, j, k)) {
+        const size_t c = nid(g, i, j, k);
+        double nv;
+        if (i == 0) nv = P.theta_hot;
+        else if (i == g.N - 1) nv = P.theta_cold;
+        else nv = theta_closed(g, T, i, j, k);
+        const double d = nv - T[c];
+        T[c] = nv;
+        acc[0] = d * d;
+        acc[1] = nv * nv;
+    }
+    const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    block_sum_store<2>(acc, partial + (size_t)blk * 2);
+}
+
+// p walls: x faces at interior (j,k), then y faces at every x and interior z, then z
+// faces everywhere, each by f_0 = (4 f_1 - f_2)/3 (composed from interior values).
+__device__ __forceinline__ double p_x_closed(const Geo &g, const double *p, int i, int j, int k)
+{
+    const int N = g.N;
+    if (i == 0) return (4.0 * p[nid(g, 1, j, k)] - p[nid(g, 2, j, k)]) / 3.0;
+    if (i == N - 1) return (4.0 * p[nid(g, N - 2, j, k)] - p[nid(g, N - 3, j, k)]) / 3.0;
+    return p[nid(g, i, j, k)];
+}
+__device__ __forceinline__ double p_y_closed(const Geo &g, const double *p, int i, int j, int k)
+{
+    const int N = g.N;
+    if (j == 0) return (4.0 * p_x_closed(g, p, i, 1, k) - p_x_closed(g, p, i, 2, k)) / 3.0;
+    if (j == N - 1) return (4.0 * p_x_closed(g, p, i, N - 2, k) - p_x_closed(g, p, i, N - 3, k)) / 3.0;
+    return p_x_closed(g, p, i, j, k);
+}
+__device__ __forceinline__ double p_closed(const Geo &g, const double *p, int i, int j, int k)
+{
+    const int N = g.N;
+    if (k == 0) return (4.0 * p_y_closed(g, p, i, j, 1) - p_y_closed(g, p, i, j, 2)) / 3.0;
+    if (k == N - 1) return (4.0 * p_y_closed(g, p, i, j, N - 2) - p_y_closed(g, p, i, j, N - 3)) / 3.0;
+    return p_y_closed(g, p, i, j, k);
+}
+
+__global__ void __launch_bounds__(256) k_p_walls(Geo g, double *__restrict__ p)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y * blockDim.y + threadIdx.y, f = blockIdx.z;
+    int i, j, k;
+    if (a < g.N && b < g.N && face_node(g.N, a, b, f, i, j, k)) p[nid(g, i, j, k)] = p_closed(g, p, i, j, k);
+}
+
+// No-slip walls (velocity 0) for set_state with boundary conditions.
+__global__ void __launch_bounds__(256) k_zero_walls(Geo g, double *__restrict__ u, double *__restrict__ v,
+                                                    double *__restrict__ w)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y * blockDim.y + threadIdx.y, f = blockIdx.z;
+    int i, j, k;
+    if (a < g.N && b < g.N && face_node(g.N, a, b, f, i, j, k)) {
+        const size_t c = nid(g, i, j, k);
+        u[c] = 0.0; v[c] = 0.0; w[c] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Modified artificial compressibility (Sec. 2.2): D = div v^{n+1} by central
+// differences at interior nodes, p <- p - lambda D (when apply != 0); partial max |D|.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_divergence(Geo g, Phys P, const double *__restrict__ u,
+                                                    const double *__restrict__ v, const double *__restrict__ w,
+                                                    double *__restrict__ p, double *__restrict__ dstore, int apply,
+                                                    double *__restrict__ partial)
+{
+    const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x, j = 1 + blockIdx.y * blockDim.y + threadIdx.y,
+              k = 1 + blockIdx.z;
+    double acc[1] = {0.0};
+    if (i <= g.N - 2 && j <= g.N - 2) {
+        const size_t c = nid(g, i, j, k), sy = (size_t)g.N, sz = (size_t)g.N * g.N;
+        const double D = (u[c + 1] - u[c - 1]) * g.inv2h + (v[c + sy] - v[c - sy]) * g.inv2h
+                         + (w[c + sz] - w[c - sz]) * g.inv2h;
+        acc[0] = fabs(D);
+        if (apply) p[c] -= P.lambda * D;
+        if (dstore) dstore[c] = D;
+    }
+    const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    block_max_store<1>(acc, partial + blk);
+}
+
+// p <- p - lambda D from a stored divergence (when the correction is gated by a
+// positive tolerance the decision needs the global max first).
+__global__ void __launch_bounds__(256) k_pressure_apply(Geo g, Phys P, const double *__restrict__ dstore,
+                                                        double *__restrict__ p)
+{
+    const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x, j = 1 + blockIdx.y * blockDim.y + threadIdx.y,
+              k = 1 + blockIdx.z;
+    if (i <= g.N - 2 && j <= g.N - 2) {
+        const size_t c = nid(g, i, j, k);
+        p[c] -= P.lambda * dstore[c];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Nusselt numbers (Sec. 4.2): Nu = -d theta/dx on x = 0 and x = 1 by the 5-point
+// 4th-order one-sided difference; Simpson over y gives Nu_avg(z); Simpson over z
+// the mean; the max over z of Nu_avg is the quantity of Table 2.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_nu_local(Geo g, const double *__restrict__ T, double *__restrict__ nuh,
+                                                  double *__restrict__ nuc)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x, k = blockIdx.y * blockDim.y + threadIdx.y;
+    if (j >= g.N || k >= g.N) return;
+    const int N = g.N;
+    const double inv12h = 1.0 / (12.0 * g.h);
+    const double dh = (-25.0 * T[nid(g, 0, j, k)] + 48.0 * T[nid(g, 1, j, k)] - 36.0 * T[nid(g, 2, j, k)]
+                       + 16.0 * T[nid(g, 3, j, k)] - 3.0 * T[nid(g, 4, j, k)]) * inv12h;
+    const double dc = (25.0 * T[nid(g, N - 1, j, k)] - 48.0 * T[nid(g, N - 2, j, k)] + 36.0 * T[nid(g, N - 3, j, k)]
+                       - 16.0 * T[nid(g, N - 4, j, k)] + 3.0 * T[nid(g, N - 5, j, k)]) * inv12h;
+    nuh[j + (size_t)N * k] = -dh;
+    nuc[j + (size_t)N * k] = -dc;
+}
+
+// Nu_avg(z_k) for both walls (one thread per k, sequential Simpson sum over j).
+__global__ void k_nu_avg(Geo g, const double *__restrict__ wq, const double *__restrict__ nuh,
+                         const double *__restrict__ nuc, double *__restrict__ avh, double *__restrict__ avc)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= g.N) return;
+    double sh = 0.0, sc = 0.0;
+    for (int j = 0; j < g.N; ++j) {
+        sh += wq[j] * nuh[j + (size_t)g.N * k];
+        sc += wq[j] * nuc[j + (size_t)g.N * k];
+    }
+    avh[k] = sh;
+    avc[k] = sc;
+}
+
+// mean over z, max over z, max of the local hot-wall Nu (single thread).
+__global__ void k_nu_final(Geo g, const double *__restrict__ wq, const double *__restrict__ avh,
+                           const double *__restrict__ avc, const double *__restrict__ nuh, double *__restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double mh = 0.0, mc = 0.0, xh = -HUGE_VAL, xc = -HUGE_VAL, xl = -HUGE_VAL;
+    for (int k = 0; k < g.N; ++k) {
+        mh += wq[k] * avh[k];
+        mc += wq[k] * avc[k];
+        xh = nanmax(xh, avh[k]);
+        xc = nanmax(xc, avc[k]);
+    }
+    for (size_t q = 0; q < (size_t)g.N * g.N; ++q) xl = nanmax(xl, nuh[q]);
+    out[0] = mh; out[1] = mc; out[2] = xh; out[3] = xc; out[4] = xl;
+}
+
+// Entropy generation (Sec. 4.3): E_HT = |grad theta|^2, E_FF = phi eta I2 with eta
+// from the current velocity, E_local = E_HT + E_FF, Be_local = E_HT / E_local (1
+// where E_local = 0).  Partial Simpson-weighted sums of E_HT, E_FF and Be_local.
+__global__ void __launch_bounds__(256) k_entropy(Geo g, Phys P, const double *__restrict__ wq,
+                                                 const double *__restrict__ u, const double *__restrict__ v,
+                                                 const double *__restrict__ w, const double *__restrict__ T,
+                                                 double *__restrict__ el, double *__restrict__ bl,
+                                                 double *__restrict__ partial)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y * blockDim.y + threadIdx.y, k = blockIdx.z;
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (i < g.N && j < g.N) {
+        const size_t c = nid(g, i, j, k), sy = (size_t)g.N, sz = (size_t)g.N * g.N;
+        const double tx = dnode(T, c, 1, i, g.N, g.inv2h), ty = dnode(T, c, sy, j, g.N, g.inv2h),
+                     tz = dnode(T, c, sz, k, g.N, g.inv2h);
+        const double eht = tx * tx + ty * ty + tz * tz;
+        const VelGrad d = vel_grad(g, u, v, w, i, j, k);
+        const double I2 = strain_I2(d);
+        const double eta = pow(fmax(I2, P.i2_floor), P.ex);
+        const double eff = P.phi * eta * I2;
+        const double e = eht + eff;
+        const double be = e > 0.0 ? eht / e : 1.0;
+        const double wv = wq[i] * wq[j] * wq[k];
+        acc[0] = wv * eht;
+        acc[1] = wv * eff;
+        acc[2] = wv * be;
+        if (el) el[c] = e;
+        if (bl) bl[c] = be;
+    }
+    const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    block_sum_store<3>(acc, partial + (size_t)blk * 3);
+}
+
+}  // namespace hosc

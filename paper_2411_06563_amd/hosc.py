@@ -1,0 +1,248 @@
+"""Python binding of libhosc (include/hosc.h): argument marshalling only.
+
+Every step of the method runs in the HIP library; PyTorch only provides the
+device workspace and the stream.  The library must be built (``build.py``); if the
+shared object is missing it is built once, and if the build is impossible the
+import fails loudly -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import build as _build
+
+LIB_PATH = _build.LIB
+HEADER = os.path.join(_build.ROOT, "include", "hosc.h")
+
+HOSC_FP64 = 0
+HOSC_FP32_REFINED = 1
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class HoscError(RuntimeError):
+    def __init__(self, status: int, name: str, msg: str):
+        super().__init__(f"{name}: {msg}")
+        self.status = status
+        self.name = name
+
+
+class CParams(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("precision", ctypes.c_int32), ("Ra", ctypes.c_double),
+                ("Pr", ctypes.c_double), ("n_pl", ctypes.c_double), ("dt", ctypes.c_double),
+                ("theta_hot", ctypes.c_double), ("theta_cold", ctypes.c_double), ("theta_ref", ctypes.c_double),
+                ("lam", ctypes.c_double), ("div_tol", ctypes.c_double), ("solve_rtol", ctypes.c_double),
+                ("solve_maxit", ctypes.c_int32), ("check_every", ctypes.c_int32), ("omega", ctypes.c_double),
+                ("i2_floor", ctypes.c_double), ("phi", ctypes.c_double)]
+
+
+class CStepInfo(ctypes.Structure):
+    _fields_ = [("res", ctypes.c_double * 4), ("relres", ctypes.c_double * 4), ("maxdiv", ctypes.c_double),
+                ("step", ctypes.c_int64), ("sweeps", ctypes.c_int32 * 2), ("corrected", ctypes.c_int32),
+                ("status", ctypes.c_int32)]
+
+
+class CDiag(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("nu_mean_hot", "nu_mean_cold", "nu_max_hot", "nu_max_cold",
+                                               "e_total", "e_ht", "e_ff", "be_global", "be_mean",
+                                               "nu_local_max_hot")]
+
+
+class CPerf(ctypes.Structure):
+    _fields_ = [("sweep_launches", ctypes.c_int64), ("sweep_ms", ctypes.c_double), ("sweep_bytes", ctypes.c_double),
+                ("assemble_launches", ctypes.c_int64), ("assemble_ms", ctypes.c_double),
+                ("assemble_bytes", ctypes.c_double)]
+
+
+_lib = None
+
+
+def library_exports() -> list[str]:
+    """Function names declared in include/hosc.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\s*(?:hosc_status|const char \*|void)\s*\*?\s*(hosc_\w+)\s*\(", text, re.M)))
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        _build.build()
+    L = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    P = ctypes.POINTER(CParams)
+    L.hosc_params_default.argtypes = [P]
+    L.hosc_workspace_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+    L.hosc_create.argtypes = [P, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.hosc_destroy.argtypes = [vp]
+    L.hosc_init_fields.argtypes = [vp, ctypes.c_uint64, ctypes.c_double]
+    L.hosc_set_state.argtypes = [vp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int32]
+    L.hosc_get_state.argtypes = [vp, _dp, _dp, _dp, _dp, _dp]
+    L.hosc_step.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(CStepInfo)]
+    L.hosc_run_to_steady.argtypes = [vp, ctypes.c_double, ctypes.c_int64, ctypes.POINTER(CStepInfo)]
+    L.hosc_diagnostics.argtypes = [vp, ctypes.POINTER(CDiag), _dp, _dp, _dp, _dp]
+    L.hosc_entropy_fields.argtypes = [vp, _dp, _dp]
+    L.hosc_debug_assemble.argtypes = [vp, _dp, _dp, _dp, _dp, _dp]
+    L.hosc_perf_enable.argtypes = [vp, ctypes.c_int32]
+    L.hosc_perf_get.argtypes = [vp, ctypes.POINTER(CPerf)]
+    L.hosc_last_error.argtypes = [vp]
+    L.hosc_last_error.restype = ctypes.c_char_p
+    L.hosc_status_string.argtypes = [ctypes.c_int]
+    L.hosc_status_string.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_dp)
+
+
+def _check(st: int, handle=None):
+    if st != 0:
+        L = lib()
+        raise HoscError(st, L.hosc_status_string(st).decode(), (L.hosc_last_error(handle) or b"").decode())
+
+
+def params(N: int, **kw) -> CParams:
+    """hosc_params with the library defaults, overridden by keyword arguments
+    (``lam`` is the artificial-compressibility lambda; 0 -> h^2/(3 dt))."""
+    p = CParams()
+    _check(lib().hosc_params_default(ctypes.byref(p)))
+    p.N = N
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise TypeError(f"unknown parameter {k}")
+        setattr(p, k, v)
+    return p
+
+
+def workspace_bytes(p: CParams) -> int:
+    n = ctypes.c_size_t(0)
+    _check(lib().hosc_workspace_bytes(ctypes.byref(p), ctypes.byref(n)))
+    return n.value
+
+
+@dataclass
+class StepInfo:
+    res: list
+    relres: list
+    maxdiv: float
+    step: int
+    sweeps: list
+    corrected: int
+    status: int
+
+    @classmethod
+    def of(cls, c: CStepInfo):
+        return cls(list(c.res), list(c.relres), c.maxdiv, c.step, list(c.sweeps), c.corrected, c.status)
+
+
+class Solver:
+    """One cavity on one device; workspace and stream from torch."""
+
+    def __init__(self, p: CParams, device: str = "cuda:0", stream=None):
+        import torch
+        self.p = p
+        self.N = p.N
+        self.device = torch.device(device)
+        nbytes = workspace_bytes(p)
+        with torch.cuda.device(self.device):
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            base = self.ws.data_ptr()
+            off = (-base) % 256
+            h = ctypes.c_void_p()
+            _check(lib().hosc_create(ctypes.byref(p), ctypes.c_void_p(base + off), nbytes,
+                                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hosc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def init_fields(self, seed: int, noise: float = 1e-3):
+        _check(lib().hosc_init_fields(self.h, seed, noise), self.h)
+
+    def set_state(self, u=None, v=None, w=None, T=None, p=None, apply_bc: bool = True):
+        arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in (u, v, w, T, p)]
+        for a in arrs:
+            if a is not None and a.size != self.N ** 3:
+                raise ValueError("fields must hold N^3 values")
+        _check(lib().hosc_set_state(self.h, *(_ptr(a) for a in arrs), int(apply_bc)), self.h)
+
+    def get_state(self) -> dict:
+        N = self.N
+        out = {f: np.empty((N, N, N)) for f in ("u", "v", "w", "T", "p")}
+        _check(lib().hosc_get_state(self.h, *(_ptr(out[f]) for f in ("u", "v", "w", "T", "p"))), self.h)
+        return out
+
+    def step(self, n: int = 1) -> StepInfo:
+        info = CStepInfo()
+        _check(lib().hosc_step(self.h, n, ctypes.byref(info)), self.h)
+        return StepInfo.of(info)
+
+    def run_to_steady(self, tol: float, max_steps: int) -> StepInfo:
+        info = CStepInfo()
+        _check(lib().hosc_run_to_steady(self.h, tol, max_steps, ctypes.byref(info)), self.h)
+        return StepInfo.of(info)
+
+    def diagnostics(self, arrays: bool = True) -> dict:
+        N = self.N
+        d = CDiag()
+        if arrays:
+            avh, avc = np.empty(N), np.empty(N)
+            nuh, nuc = np.empty((N, N)), np.empty((N, N))
+        else:
+            avh = avc = nuh = nuc = None
+        _check(lib().hosc_diagnostics(self.h, ctypes.byref(d), _ptr(avh), _ptr(avc), _ptr(nuh), _ptr(nuc)), self.h)
+        out = {n: getattr(d, n) for n, _ in CDiag._fields_}
+        if arrays:
+            out.update(nuavg_hot=avh, nuavg_cold=avc, nu_hot=nuh, nu_cold=nuc)
+        return out
+
+    def perf_enable(self, on: bool = True):
+        _check(lib().hosc_perf_enable(self.h, int(on)), self.h)
+
+    def perf(self) -> dict:
+        c = CPerf()
+        _check(lib().hosc_perf_get(self.h, ctypes.byref(c)), self.h)
+        return {n: getattr(c, n) for n, _ in CPerf._fields_}
+
+    def entropy_fields(self):
+        N = self.N
+        el, bl = np.empty((N, N, N)), np.empty((N, N, N))
+        _check(lib().hosc_entropy_fields(self.h, _ptr(el), _ptr(bl)), self.h)
+        return el, bl
+
+    def debug_assemble(self) -> dict:
+        N = self.N
+        eta = np.empty((N, N, N))
+        E = np.empty((3, N, N, N))
+        b = np.empty((4, N, N, N))
+        Bm = np.empty((7, N, N, N))
+        Bt = np.empty((7, N, N, N))
+        _check(lib().hosc_debug_assemble(self.h, _ptr(eta), _ptr(E), _ptr(b), _ptr(Bm), _ptr(Bt)), self.h)
+        return dict(eta=eta, E=E, b=b, Bmom=Bm, Btheta=Bt)

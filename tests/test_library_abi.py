@@ -1,0 +1,46 @@
+"""The C-ABI library loads on a host without a GPU and exports every function that
+include/hosc.h declares; parameter validation and workspace sizing run on the
+host (no compute call is made here)."""
+import ctypes
+
+import pytest
+
+from paper_2411_06563_amd import hosc
+
+
+def test_exports_every_declared_symbol():
+    L = hosc.lib()
+    names = hosc.library_exports()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_params_default_and_validation():
+    p = hosc.params(17)
+    assert p.N == 17 and p.Ra == 1e3 and p.Pr == 1.0 and p.n_pl == 1.0 and p.solve_rtol == 1e-10
+    assert hosc.workspace_bytes(p) > 30 * 17 ** 3 * 8
+    for N, bad in ((4, {}), (17, dict(Pr=0.0)), (17, dict(dt=-1.0)), (17, dict(n_pl=0.0)), (17, dict(omega=2.0)),
+                   (17, dict(solve_rtol=0.0))):
+        q = hosc.params(N, **bad)
+        with pytest.raises(hosc.HoscError) as e:
+            hosc.workspace_bytes(q)
+        assert e.value.name == "HOSC_E_ARG"
+
+
+def test_workspace_scales_with_grid():
+    b65 = hosc.workspace_bytes(hosc.params(65))
+    b129 = hosc.workspace_bytes(hosc.params(129))
+    assert 6.0 < b129 / b65 < 9.0
+    assert b129 < 1.0e9          # one 129^3 FP64 cavity fits in well under 1 GB
+
+
+def test_create_rejects_bad_workspace():
+    L = hosc.lib()
+    p = hosc.params(17)
+    h = ctypes.c_void_p()
+    st = L.hosc_create(ctypes.byref(p), None, 0, None, ctypes.byref(h))
+    assert hosc.lib().hosc_status_string(st).decode() == "HOSC_E_ARG"
+    st = L.hosc_create(ctypes.byref(p), ctypes.c_void_p(256), 10, None, ctypes.byref(h))
+    assert hosc.lib().hosc_status_string(st).decode() == "HOSC_E_NOMEM"
+    assert b"workspace" in L.hosc_last_error(None)
