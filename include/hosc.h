@@ -59,6 +59,15 @@ typedef enum {
     HOSC_FP32_REFINED = 1   /* FP32 implicit matrix and inner sweeps, FP64 residual refinement */
 } hosc_precision;
 
+/* Solver of the 7-point implicit systems (Sec. 2.2 uses BiCGSTAB without
+ * preconditioning because SOR fails where the rows lose diagonal dominance). */
+typedef enum {
+    HOSC_SOLVER_AUTO = 0,       /* red-black SOR; a system whose SOR residual stalls or grows is
+                                   re-solved with BiCGSTAB (kept for the next 50 steps) */
+    HOSC_SOLVER_SOR = 1,        /* red-black SOR only (fails with HOSC_E_NOCONV / NONFINITE) */
+    HOSC_SOLVER_BICGSTAB = 2    /* BiCGSTAB on the diagonally scaled rows only */
+} hosc_solver_kind;
+
 /* Parameters of one cavity (Sec. 2.1 problem statement, Sec. 2.2 scheme). */
 typedef struct hosc_params {
     int32_t N;              /* nodes per side including walls, 5 <= N <= 1025; h = 1/(N-1) */
@@ -75,6 +84,8 @@ typedef struct hosc_params {
     double solve_rtol;      /* stop a solve when ||r|| <= solve_rtol ||b|| (diagonally scaled 2-norms), default 1e-10 */
     int32_t solve_maxit;    /* cap on red-black sweeps per solve (default 4000) */
     int32_t check_every;    /* sweeps between convergence checks; 0 -> adaptive */
+    int32_t solver;         /* hosc_solver_kind (default HOSC_SOLVER_AUTO) */
+    int32_t reserved;       /* must be 0 */
     double omega;           /* SOR relaxation of the red-black sweeps, 0 < omega < 2 (default 1.0) */
     double i2_floor;        /* eta = max(I2, i2_floor)^((n-1)/2), default 1e-8 */
     double phi;             /* irreversibility ratio of the fluid-friction entropy, default 1e-4 */
@@ -87,6 +98,7 @@ typedef struct hosc_step_info {
     double maxdiv;          /* max |div v^{n+1}| over interior nodes before the correction */
     int64_t step;           /* steps taken since the state was set */
     int32_t sweeps[2];      /* red-black sweeps of the momentum and the energy solve (last step) */
+    int32_t bicg_iters[2];  /* BiCGSTAB iterations of the momentum and the energy solve (last step) */
     int32_t corrected;      /* 1 if the pressure correction was applied */
     int32_t status;         /* hosc_status of the step */
 } hosc_step_info;
@@ -116,6 +128,9 @@ typedef struct hosc_perf {
     int64_t assemble_launches;
     double assemble_ms;
     double assemble_bytes;
+    int64_t bicg_launches;      /* BiCGSTAB vector-phase launches (matrix-vector products and updates) */
+    double bicg_ms;
+    double bicg_bytes;          /* per launch: rows of the active systems once, each vector read or written once */
 } hosc_perf;
 
 typedef struct hosc_solver hosc_solver;

@@ -34,7 +34,8 @@ struct Launch {
     dim3 blk_int, grd_int;      // interior nodes (natural layout)
     dim3 blk_sw, grd_sw;        // one colour of the interior (colour layout)
     dim3 blk_face, grd_face;    // wall nodes, 6 faces
-    size_t nb_int, nb_sw, nb_face, nb_all;
+    dim3 grd_bc;                // both colours of the interior (BiCGSTAB)
+    size_t nb_int, nb_sw, nb_face, nb_all, nb_bc;
 };
 
 // Workspace map (element counts in doubles, each region 256-byte aligned).
@@ -42,6 +43,7 @@ struct Layout {
     size_t n3, cs;
     size_t natural_arrays = 17;   // u v w T p u2 v2 w2 eta etap E3 Ep3 dbg
     size_t colour_arrays = 15;    // ms ma3 mb3 md3 ta3 tb td (each 2 colours)
+    size_t bicg_arrays = 0;       // r rh p pn v vn t for 4 systems (BiCGSTAB enabled)
     size_t partial;               // partial-sum records
     size_t total_bytes;
 };
@@ -80,25 +82,29 @@ Launch make_launch(const Geo &g)
     L.nb_int = (size_t)L.grd_int.x * L.grd_int.y * L.grd_int.z;
     L.nb_sw = (size_t)L.grd_sw.x * L.grd_sw.y * L.grd_sw.z;
     L.nb_face = (size_t)L.grd_face.x * L.grd_face.y * L.grd_face.z;
+    L.grd_bc = dim3(L.grd_sw.x, L.grd_sw.y, 2 * M);
+    L.nb_bc = (size_t)L.grd_bc.x * L.grd_bc.y * L.grd_bc.z;
     return L;
 }
 
-Layout make_layout(const Geo &g, const Launch &L)
+Layout make_layout(const Geo &g, const Launch &L, int solver)
 {
     Layout y;
     y.n3 = g.n3;
     y.cs = g.cs;
-    const size_t recs = std::max({L.nb_int * 8, L.nb_sw * 4, L.nb_face * 2, L.nb_all * 3});
+    y.bicg_arrays = solver == HOSC_SOLVER_SOR ? 0 : 28;
+    const size_t recs = std::max({L.nb_int * 8, L.nb_sw * 4, L.nb_face * 2, L.nb_all * 3, L.nb_bc * 8});
     y.partial = recs;
     size_t b = 0;
     b += y.natural_arrays * align_up(g.n3 * sizeof(double));
-    b += y.colour_arrays * align_up(2 * g.cs * sizeof(double));
+    b += (y.colour_arrays + y.bicg_arrays) * align_up(2 * g.cs * sizeof(double));
     b += 2 * align_up(recs * sizeof(double));                 // two partial buffers (red / black half)
     b += align_up(kRed * sizeof(double));                      // reduction outputs
     b += align_up((size_t)g.N * sizeof(double));               // Simpson weights
     b += 2 * align_up((size_t)g.N * g.N * sizeof(double));     // Nu_local hot / cold
     b += 2 * align_up((size_t)g.N * sizeof(double));           // Nu_avg hot / cold
     b += align_up(8 * sizeof(double));                         // Nu scalars
+    b += align_up(32 * sizeof(double));                        // BiCGSTAB scalars
     y.total_bytes = b;
     return y;
 }
@@ -118,6 +124,8 @@ const char *check_params(const hosc_params *p)
     if (p->solve_maxit < 1) return "solve_maxit must be >= 1";
     if (p->check_every < 0) return "check_every must be >= 0";
     if (!(p->omega > 0.0 && p->omega < 2.0)) return "omega must be in (0, 2)";
+    if (p->solver < HOSC_SOLVER_AUTO || p->solver > HOSC_SOLVER_BICGSTAB) return "unknown solver";
+    if (p->reserved != 0) return "reserved must be 0";
     if (!(p->i2_floor > 0.0) || !std::isfinite(p->i2_floor)) return "i2_floor must be finite and > 0";
     if (!(p->phi >= 0.0) || !std::isfinite(p->phi)) return "phi must be finite and >= 0";
     if (!std::isfinite(p->theta_hot) || !std::isfinite(p->theta_cold) || !std::isfinite(p->theta_ref))
@@ -174,18 +182,23 @@ struct hosc_solver {
     // colour layout
     double *ms, *ma[3], *mb[3], *md[3], *ta[3], *tb, *td;
     double *partR, *partB, *red, *wq, *nuh, *nuc, *avh, *avc, *nuout;
+    // BiCGSTAB vectors (4 systems) and scalars
+    double *br[4], *brh[4], *bp[4], *bpn[4], *bv[4], *bvn[4], *bt[4];
+    double *bsc;
+    int64_t bicg_until[2] = {-1, -1};   // auto mode: use BiCGSTAB for the group until this step
     double *hbuf = nullptr;   // pinned host staging for scalars
     int64_t step = 0;
     bool first = true;
     bool has_state = false;
     int sticky = HOSC_OK;
     int last_sweeps[2] = {0, 0};
+    int last_bicg[2] = {0, 0};
     std::string err;
     // kernel timing
     bool prof = false;
     std::vector<hipEvent_t> ev;     // pairs (start, stop)
     std::vector<double> ev_bytes;   // algorithmic bytes of each timed launch
-    std::vector<int> ev_kind;       // 0 sweep, 1 assemble
+    std::vector<int> ev_kind;       // 0 sweep, 1 assemble, 2 BiCGSTAB phase
     int ev_used = 0;
     hosc_perf perf{};
 };
@@ -246,6 +259,13 @@ void carve(hosc_solver *s, char *base)
     s->avh = take(align_up((size_t)s->g.N * sizeof(double)));
     s->avc = take(align_up((size_t)s->g.N * sizeof(double)));
     s->nuout = take(align_up(8 * sizeof(double)));
+    s->bsc = take(align_up(32 * sizeof(double)));
+    for (int f = 0; f < 4; ++f) s->br[f] = s->brh[f] = s->bp[f] = s->bpn[f] = s->bv[f] = s->bvn[f] = s->bt[f] = nullptr;
+    if (s->Y.bicg_arrays)
+        for (int f = 0; f < 4; ++f) {
+            s->br[f] = take(col); s->brh[f] = take(col); s->bp[f] = take(col); s->bpn[f] = take(col);
+            s->bv[f] = take(col); s->bvn[f] = take(col); s->bt[f] = take(col);
+        }
 }
 
 constexpr int kEvPairs = 512;
@@ -278,10 +298,14 @@ hosc_status harvest_events(hosc_solver *s)
             s->perf.sweep_launches += 1;
             s->perf.sweep_ms += ms;
             s->perf.sweep_bytes += s->ev_bytes[q];
-        } else {
+        } else if (s->ev_kind[q] == 1) {
             s->perf.assemble_launches += 1;
             s->perf.assemble_ms += ms;
             s->perf.assemble_bytes += s->ev_bytes[q];
+        } else {
+            s->perf.bicg_launches += 1;
+            s->perf.bicg_ms += ms;
+            s->perf.bicg_bytes += s->ev_bytes[q];
         }
     }
     s->ev_used = 0;
@@ -334,6 +358,8 @@ hosc_status reset_state(hosc_solver *s)
     s->has_state = true;
     s->sticky = HOSC_OK;
     s->last_sweeps[0] = s->last_sweeps[1] = 0;
+    s->last_bicg[0] = s->last_bicg[1] = 0;
+    s->bicg_until[0] = s->bicg_until[1] = -1;
     HIPCHK(s, hipStreamSynchronize(s->st));
     return HOSC_OK;
 }
@@ -374,25 +400,57 @@ SweepArgs<double> sweep_args(hosc_solver *s)
     return a;
 }
 
-// Red-black SOR on both systems until each meets ||r|| <= rtol ||b|| (scaled rows).
-// One sweep = red half then black half; the sums of squared pre-update residuals of
-// the black half and (1-omega)^2 times those of the red half give the residual of
-// the state between the two halves, so convergence is known without an extra pass.
-hosc_status solve(hosc_solver *s, double relres[4], int sweeps[2])
+// Algorithmic bytes of one BiCGSTAB phase launch over both colours.
+double bicg_bytes(const Geo &g, int phase, int mask)
+{
+    const double nodes = (double)(g.N - 2) * (g.N - 2) * (g.N - 2);
+    // per system: vectors touched (reads + writes); rows counted once per matrix
+    static const int vec[4] = {6, 5, 3, 8};   // phase 0: b, x | r, rh, p, v;  1: r, p, v, rh | pn, vn;  2: r, vn | t;  3: r, vn, x, pn, t, rh | x, r
+    static const int rows[4] = {1, 1, 1, 0};
+    double per = 0.0;
+    if (mask & 1) per += 3 * vec[phase] + rows[phase] * 4;
+    if (mask & 2) per += vec[phase] + rows[phase] * 3;
+    return nodes * per * sizeof(double);
+}
+
+struct SolveOut {
+    double relres[4] = {0, 0, 0, 0};
+    int sweeps[2] = {0, 0};
+    int bicg[2] = {0, 0};
+};
+
+hosc_status zero_group(hosc_solver *s, int group)
+{
+    const size_t b = 2 * s->g.cs * sizeof(double);
+    if (group == 0)
+        for (int f = 0; f < 3; ++f) HIPCHK(s, hipMemsetAsync(s->md[f], 0, b, s->st));
+    else
+        HIPCHK(s, hipMemsetAsync(s->td, 0, b, s->st));
+    return HOSC_OK;
+}
+
+// Red-black SOR on the groups in `mask` (1 momentum, 2 energy) until each meets
+// ||r|| <= rtol ||b|| (scaled rows).  One sweep = red half then black half; the sums
+// of squared pre-update residuals of the black half and (1-omega)^2 times those of
+// the red half give the residual of the state between the two halves, so
+// convergence is known without an extra pass.  In auto mode a group whose
+// residual grows or stalls is returned in *failed instead of raising an error.
+hosc_status run_sor(hosc_solver *s, int mask, const double bn2[4], SolveOut &o, int *failed)
 {
     const double om = s->P.omega;
     const double rtol = s->P.solve_rtol;
     const double ct = s->g.h2 / 12.0 - s->P.dt / 2.0;
     const double Ct = 1.0 - 6.0 * ct * s->g.invh2;
     const double st = (ct * s->g.invh2) / Ct;
+    const bool autom = s->P.solver == HOSC_SOLVER_AUTO;
     SweepArgs<double> a = sweep_args(s);
-    int active = 3;
-    sweeps[0] = sweeps[1] = 0;
+    int active = mask;
+    *failed = 0;
+    double prev[2] = {-1.0, -1.0};
+    int prev_at[2] = {0, 0};
     int predicted = std::max(s->last_sweeps[0], s->last_sweeps[1]);
     int batch = s->P.check_every > 0 ? s->P.check_every : std::max(2, predicted > 0 ? predicted - 1 : 8);
-    bool have_b = false;
-    double bn2[4] = {0, 0, 0, 0};
-    for (;;) {
+    while (active) {
         const double bytes = sweep_bytes(s->g, active);
         for (int q = 0; q < batch; ++q) {
             const int acc = q == batch - 1;
@@ -413,39 +471,205 @@ hosc_status solve(hosc_solver *s, double relres[4], int sweeps[2])
         HIPCHK(s, hipStreamSynchronize(s->st));
         r = harvest_events(s);
         if (r) return r;
-        if (!have_b) {
-            for (int f = 0; f < 4; ++f) bn2[f] = s->hbuf[f];
-            have_b = true;
-        }
-        if (active & 1) sweeps[0] += batch;
-        if (active & 2) sweeps[1] += batch;
-        bool conv[4];
-        for (int f = 0; f < 4; ++f) {
-            const double r2 = s->hbuf[8 + f] + (1.0 - om) * (1.0 - om) * s->hbuf[4 + f];
-            if (!std::isfinite(r2) || !std::isfinite(bn2[f]))
-                return fail(s, HOSC_E_NONFINITE, "non-finite residual in the implicit solve");
-            const bool sys_active = (f < 3) ? (active & 1) : (active & 2);
-            if (sys_active) relres[f] = bn2[f] > 0.0 ? std::sqrt(r2 / bn2[f]) : 0.0;
-            conv[f] = bn2[f] == 0.0 || std::sqrt(r2) <= rtol * std::sqrt(bn2[f]);
-        }
-        if ((active & 1) && conv[0] && conv[1] && conv[2]) {
-            for (int f = 0; f < 3; ++f)
-                if (bn2[f] == 0.0) HIPCHK(s, hipMemsetAsync(s->md[f], 0, 2 * s->g.cs * sizeof(double), s->st));
-            active &= ~1;
-        }
-        if ((active & 2) && conv[3]) {
-            if (bn2[3] == 0.0) HIPCHK(s, hipMemsetAsync(s->td, 0, 2 * s->g.cs * sizeof(double), s->st));
-            active &= ~2;
+        for (int grp = 0; grp < 2; ++grp) {
+            if (!(active & (1 << grp))) continue;
+            o.sweeps[grp] += batch;
+            const int f0 = grp == 0 ? 0 : 3, f1 = grp == 0 ? 3 : 4;
+            bool conv = true, finite = true;
+            double worst = 0.0;
+            for (int f = f0; f < f1; ++f) {
+                const double r2 = s->hbuf[8 + f] + (1.0 - om) * (1.0 - om) * s->hbuf[4 + f];
+                if (!std::isfinite(r2)) finite = false;
+                const double rel = bn2[f] > 0.0 ? std::sqrt(r2 / bn2[f]) : 0.0;
+                o.relres[f] = rel;
+                worst = std::max(worst, rel);
+                if (!(bn2[f] == 0.0 || std::sqrt(r2) <= rtol * std::sqrt(bn2[f]))) conv = false;
+            }
+            if (finite && conv) {
+                for (int f = f0; f < f1; ++f)
+                    if (bn2[f] == 0.0) {
+                        const size_t b = 2 * s->g.cs * sizeof(double);
+                        HIPCHK(s, hipMemsetAsync(f < 3 ? s->md[f] : s->td, 0, b, s->st));
+                    }
+                active &= ~(1 << grp);
+                continue;
+            }
+            const int done = o.sweeps[grp];
+            // divergence: residual not finite or grown by 2x; stall: < 2x reduction over 100 sweeps
+            const bool diverged = !finite || (prev[grp] >= 0.0 && worst > 2.0 * prev[grp]);
+            const bool stalled = prev[grp] >= 0.0 && done - prev_at[grp] >= 100 && worst > 0.5 * prev[grp];
+            if (diverged || stalled || done >= s->P.solve_maxit) {
+                if (autom) {
+                    *failed |= 1 << grp;
+                    active &= ~(1 << grp);
+                    continue;
+                }
+                if (!finite) return fail(s, HOSC_E_NONFINITE, "non-finite residual in the implicit solve");
+                if (done >= s->P.solve_maxit)
+                    return fail(s, HOSC_E_NOCONV, "implicit solve did not converge within solve_maxit sweeps");
+            }
+            if (prev[grp] < 0.0 || done - prev_at[grp] >= 100) {
+                prev[grp] = worst;
+                prev_at[grp] = done;
+            } else if (worst < prev[grp]) {
+                // keep the reference for the stall test, but track progress for divergence
+            }
         }
         if (!active) break;
-        const int done = std::max(sweeps[0], sweeps[1]);
-        if (done >= s->P.solve_maxit)
-            return fail(s, HOSC_E_NOCONV, "implicit solve did not converge within solve_maxit sweeps");
+        const int done = std::max(o.sweeps[0], o.sweeps[1]);
         batch = s->P.check_every > 0 ? s->P.check_every : std::max(2, std::min(done / 2, 64));
-        batch = std::min(batch, s->P.solve_maxit - done);
+        batch = std::min(batch, std::max(1, s->P.solve_maxit - done));
     }
-    s->last_sweeps[0] = sweeps[0];
-    s->last_sweeps[1] = sweeps[1];
+    return HOSC_OK;
+}
+
+BicgArgs<double> bicg_args(hosc_solver *s)
+{
+    BicgArgs<double> a;
+    a.ms = s->ms;
+    for (int d = 0; d < 3; ++d) {
+        a.ma[d] = s->ma[d];
+        a.mb[d] = s->mb[d];
+        a.ta[d] = s->ta[d];
+    }
+    a.tb = s->tb;
+    for (int f = 0; f < 4; ++f) {
+        a.x[f] = f < 3 ? s->md[f] : s->td;
+        a.r[f] = s->br[f]; a.rh[f] = s->brh[f]; a.p[f] = s->bp[f]; a.pn[f] = s->bpn[f];
+        a.v[f] = s->bv[f]; a.vn[f] = s->bvn[f]; a.t[f] = s->bt[f];
+    }
+    return a;
+}
+
+hosc_status bicg_phase(hosc_solver *s, int phase, int mask, double st, const BicgArgs<double> &a)
+{
+    hosc_status r = timed_begin(s);
+    if (r) return r;
+    k_bicg<double, double><<<s->L.grd_bc, s->L.blk_sw, 0, s->st>>>(s->g, phase, mask, st, a, s->bsc, s->partR);
+    r = timed_end(s, 2, bicg_bytes(s->g, phase, mask));
+    if (r) return r;
+    k_bicg_scalars<<<1, 256, 0, s->st>>>(phase, mask, s->partR, (int)s->L.nb_bc, s->bsc);
+    return launch_check(s, "bicgstab");
+}
+
+// BiCGSTAB (the paper's solver) on the groups in `mask`, from the current
+// increments, until the true scaled residual meets the tolerance.
+hosc_status run_bicg(hosc_solver *s, int mask, const double bn2[4], SolveOut &o)
+{
+    if (!mask) return HOSC_OK;
+    const double rtol = s->P.solve_rtol;
+    const double ct = s->g.h2 / 12.0 - s->P.dt / 2.0;
+    const double Ct = 1.0 - 6.0 * ct * s->g.invh2;
+    const double st = (ct * s->g.invh2) / Ct;
+    BicgArgs<double> a = bicg_args(s);
+    int active = mask;
+    for (int grp = 0; grp < 2; ++grp) {     // groups with b = 0 have the zero solution
+        if (!(active & (1 << grp))) continue;
+        const int f0 = grp == 0 ? 0 : 3, f1 = grp == 0 ? 3 : 4;
+        bool zero = true;
+        for (int f = f0; f < f1; ++f) zero = zero && bn2[f] == 0.0;
+        if (zero) {
+            hosc_status r = zero_group(s, grp);
+            if (r) return r;
+            active &= ~(1 << grp);
+        }
+    }
+    if (!active) return HOSC_OK;
+    hosc_status r = bicg_phase(s, 0, active, st, a);
+    if (r) return r;
+    int m = std::max(2, std::max(s->last_bicg[0], s->last_bicg[1]) / 2);
+    if (s->P.check_every > 0) m = s->P.check_every;
+    while (active) {
+        for (int q = 0; q < m; ++q) {
+            for (int ph = 1; ph <= 3; ++ph) {
+                r = bicg_phase(s, ph, active, st, a);
+                if (r) return r;
+            }
+            for (int f = 0; f < 4; ++f) {
+                std::swap(a.p[f], a.pn[f]);
+                std::swap(a.v[f], a.vn[f]);
+            }
+        }
+        for (int grp = 0; grp < 2; ++grp)
+            if (active & (1 << grp)) o.bicg[grp] += m;
+        HIPCHK(s, hipMemcpyAsync(s->hbuf, s->bsc, 32 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+        HIPCHK(s, hipStreamSynchronize(s->st));
+        r = harvest_events(s);
+        if (r) return r;
+        // candidates: recursive residual small enough, or breakdown -> recompute the true
+        // residual from x (this also restarts the recurrence)
+        int recheck = 0;
+        for (int grp = 0; grp < 2; ++grp) {
+            if (!(active & (1 << grp))) continue;
+            const int f0 = grp == 0 ? 0 : 3, f1 = grp == 0 ? 3 : 4;
+            bool small = true, broke = false;
+            for (int f = f0; f < f1; ++f) {
+                const double *S = s->hbuf + 8 * f;
+                if (!std::isfinite(S[4])) return fail(s, HOSC_E_NONFINITE, "non-finite residual in BiCGSTAB");
+                if (S[5] != 0.0) broke = true;
+                if (!(bn2[f] == 0.0 || std::sqrt(S[4]) <= rtol * std::sqrt(bn2[f]))) small = false;
+            }
+            if (small || broke) recheck |= 1 << grp;
+        }
+        if (recheck) {
+            r = bicg_phase(s, 0, recheck, st, a);
+            if (r) return r;
+            HIPCHK(s, hipMemcpyAsync(s->hbuf, s->bsc, 32 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+            HIPCHK(s, hipStreamSynchronize(s->st));
+            for (int grp = 0; grp < 2; ++grp) {
+                if (!(recheck & (1 << grp))) continue;
+                const int f0 = grp == 0 ? 0 : 3, f1 = grp == 0 ? 3 : 4;
+                bool conv = true;
+                for (int f = f0; f < f1; ++f) {
+                    const double rr = s->hbuf[8 * f + 4];
+                    o.relres[f] = bn2[f] > 0.0 ? std::sqrt(rr / bn2[f]) : 0.0;
+                    if (!(bn2[f] == 0.0 || std::sqrt(rr) <= rtol * std::sqrt(bn2[f]))) conv = false;
+                }
+                if (conv) active &= ~(1 << grp);
+            }
+        }
+        const int done = std::max(o.bicg[0], o.bicg[1]);
+        if (active && done >= s->P.solve_maxit)
+            return fail(s, HOSC_E_NOCONV, "BiCGSTAB did not converge within solve_maxit iterations");
+    }
+    return HOSC_OK;
+}
+
+// Solve the momentum (3 right-hand sides) and energy systems of the step.
+hosc_status solve(hosc_solver *s, SolveOut &o)
+{
+    // ||b/C||^2 of the four systems (reduced after the assembly)
+    HIPCHK(s, hipMemcpyAsync(s->hbuf + 32, s->red, 4 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    double bn2[4];
+    for (int f = 0; f < 4; ++f) bn2[f] = s->hbuf[32 + f];
+    for (int f = 0; f < 4; ++f)
+        if (!std::isfinite(bn2[f])) return fail(s, HOSC_E_NONFINITE, "non-finite right-hand side");
+    int sor_mask = 0, bicg_mask = 0;
+    for (int grp = 0; grp < 2; ++grp) {
+        const bool use_bicg = s->P.solver == HOSC_SOLVER_BICGSTAB
+                              || (s->P.solver == HOSC_SOLVER_AUTO && s->step < s->bicg_until[grp]);
+        if (use_bicg) bicg_mask |= 1 << grp;
+        else sor_mask |= 1 << grp;
+    }
+    if (sor_mask) {
+        int failed = 0;
+        hosc_status r = run_sor(s, sor_mask, bn2, o, &failed);
+        if (r) return r;
+        for (int grp = 0; grp < 2; ++grp)
+            if (failed & (1 << grp)) {
+                r = zero_group(s, grp);     // restart from zero: the SOR iterate may have diverged
+                if (r) return r;
+                s->bicg_until[grp] = s->step + 50;
+                bicg_mask |= 1 << grp;
+            }
+    }
+    hosc_status r = run_bicg(s, bicg_mask, bn2, o);
+    if (r) return r;
+    s->last_sweeps[0] = o.sweeps[0];
+    s->last_sweeps[1] = o.sweeps[1];
+    s->last_bicg[0] = o.bicg[0];
+    s->last_bicg[1] = o.bicg[1];
     return HOSC_OK;
 }
 
@@ -471,9 +695,8 @@ hosc_status one_step(hosc_solver *s, hosc_step_info *info)
     k_reduce<<<1, 256, 0, s->st>>>(s->partR, (int)s->L.nb_int, 4, 0, s->red);
     r = launch_check(s, "assemble");
     if (r) return r;
-    double relres[4] = {0, 0, 0, 0};
-    int sweeps[2] = {0, 0};
-    r = solve(s, relres, sweeps);
+    SolveOut so;
+    r = solve(s, so);
     if (r) return r;
     // update: u, v, w into the level n-1 buffers (which become level n+1)
     k_update<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, s->u, s->v, s->w, s->u2, s->v2, s->w2, s->T, s->md[0],
@@ -523,12 +746,14 @@ hosc_status one_step(hosc_solver *s, hosc_step_info *info)
     if (info) {
         for (int f = 0; f < 4; ++f) {
             info->res[f] = res[f];
-            info->relres[f] = relres[f];
+            info->relres[f] = so.relres[f];
         }
         info->maxdiv = maxdiv;
         info->step = s->step;
-        info->sweeps[0] = sweeps[0];
-        info->sweeps[1] = sweeps[1];
+        info->sweeps[0] = so.sweeps[0];
+        info->sweeps[1] = so.sweeps[1];
+        info->bicg_iters[0] = so.bicg[0];
+        info->bicg_iters[1] = so.bicg[1];
         info->corrected = corrected;
         info->status = finite ? HOSC_OK : HOSC_E_NONFINITE;
     }
@@ -558,6 +783,8 @@ hosc_status hosc_params_default(hosc_params *p)
     p->solve_rtol = 1e-10;
     p->solve_maxit = 4000;
     p->check_every = 0;
+    p->solver = HOSC_SOLVER_AUTO;
+    p->reserved = 0;
     p->omega = 1.0;
     p->i2_floor = 1e-8;
     p->phi = 1e-4;
@@ -571,7 +798,7 @@ hosc_status hosc_workspace_bytes(const hosc_params *p, size_t *bytes)
     if (!bytes) return fail(nullptr, HOSC_E_ARG, "bytes is NULL");
     Geo g = make_geo(p->N);
     Launch L = make_launch(g);
-    *bytes = make_layout(g, L).total_bytes;
+    *bytes = make_layout(g, L, p->solver).total_bytes;
     return HOSC_OK;
 }
 
@@ -589,7 +816,7 @@ hosc_status hosc_create(const hosc_params *p, void *d_ws, size_t ws_bytes, hipSt
     s->P = *p;
     s->g = make_geo(p->N);
     s->L = make_launch(s->g);
-    s->Y = make_layout(s->g, s->L);
+    s->Y = make_layout(s->g, s->L, p->solver);
     if (ws_bytes < s->Y.total_bytes) {
         delete s;
         return fail(nullptr, HOSC_E_NOMEM, "workspace smaller than hosc_workspace_bytes()");

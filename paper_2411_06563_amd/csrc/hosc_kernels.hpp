@@ -463,12 +463,78 @@ __global__ void __launch_bounds__(256) k_assemble_debug(Geo g, Phys P, const dou
 }
 
 // ---------------------------------------------------------------------------
+// Scaled implicit rows in the colour layout.
+//
+// Momentum row at a node: d_c + sum_d [(s - a_d) d(x_d + h) + (s + a_d) d(x_d - h)] = b
+// (everything divided by the centre weight; walls hold zero increments).
+// Energy row: the same with s = st constant; next to a y or z wall the wall
+// increment is (4 d_1 - d_2)/3, which moves 4/3 of the wall weight onto the centre
+// (den) and -1/3 of it onto the next node.
+// ---------------------------------------------------------------------------
+struct RowIdx {
+    size_t me, xp, xm, yp, ym, zp, zm;
+};
+
+__device__ __forceinline__ bool row_index(const Geo &g, int colour, int q, int j, int k, RowIdx &r)
+{
+    const int N = g.N;
+    const int i = 2 * q + ((colour + j + k) & 1);
+    if (q >= g.Q || j > N - 2 || k > N - 2 || i < 1 || i > N - 2) return false;
+    const size_t row = rowid(g, j, k);
+    const size_t ob = (size_t)(1 - colour) * g.cs;
+    const int sh = i & 1;
+    r.me = (size_t)colour * g.cs + row + q;
+    r.xp = ob + row + q + sh;
+    r.xm = ob + row + q + sh - 1;
+    r.yp = ob + rowid(g, j + 1, k) + q;
+    r.ym = ob + rowid(g, j - 1, k) + q;
+    r.zp = ob + rowid(g, j, k + 1) + q;
+    r.zm = ob + rowid(g, j, k - 1) + q;
+    return true;
+}
+
+// off-diagonal sum of a momentum row for the vector given by f(index)
+template <typename TA, typename F>
+__device__ __forceinline__ TA mom_off(TA s, TA ax, TA ay, TA az, const RowIdx &r, F f)
+{
+    return (s - ax) * f(r.xp) + (s + ax) * f(r.xm) + (s - ay) * f(r.yp) + (s + ay) * f(r.ym) + (s - az) * f(r.zp)
+           + (s + az) * f(r.zm);
+}
+
+// off-diagonal sum and centre factor of an energy row (walls eliminated)
+template <typename TA, typename F>
+__device__ __forceinline__ TA theta_off(TA st, TA ax, TA ay, TA az, int j, int k, int N, const RowIdx &r, F f, TA &den)
+{
+    const TA wxp = st - ax, wxm = st + ax, wyp = st - ay, wym = st + ay, wzp = st - az, wzm = st + az;
+    const TA third = (TA)(1.0 / 3.0), four3 = (TA)(4.0 / 3.0);
+    den = (TA)1.0;
+    TA sum = wxp * f(r.xp) + wxm * f(r.xm);
+    if (j == 1) {
+        den += four3 * wym;
+        sum += (wyp - wym * third) * f(r.yp);
+    } else if (j == N - 2) {
+        den += four3 * wyp;
+        sum += (wym - wyp * third) * f(r.ym);
+    } else {
+        sum += wyp * f(r.yp) + wym * f(r.ym);
+    }
+    if (k == 1) {
+        den += four3 * wzm;
+        sum += (wzp - wzm * third) * f(r.zp);
+    } else if (k == N - 2) {
+        den += four3 * wzp;
+        sum += (wzm - wzp * third) * f(r.zm);
+    } else {
+        sum += wzp * f(r.zp) + wzm * f(r.zm);
+    }
+    return sum;
+}
+
+// ---------------------------------------------------------------------------
 // Red-black SOR half-sweep on the scaled rows (momentum: three right-hand sides
-// on one matrix; energy: with the zero-normal-derivative walls eliminated:
-// next to a y or z wall the wall increment equals (4 d_1 - d_2)/3, which moves
-// 4/3 of the wall weight onto the centre and -1/3 of it onto the next node).
-// Per-block partial sums of the squared scaled residuals r = b - B d at the
-// updated nodes, before their update (when acc != 0).
+// on one matrix; energy with the walls eliminated).  Per-block partial sums of
+// the squared scaled residuals r = b - B d at the updated nodes, before their
+// update (when acc != 0).
 // ---------------------------------------------------------------------------
 template <typename TM>
 struct SweepArgs {
@@ -484,66 +550,176 @@ __global__ void __launch_bounds__(256) k_sweep(Geo g, int colour, int mask, TA o
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y, k = 1 + blockIdx.z;
-    const int N = g.N;
     double r2[4] = {0.0, 0.0, 0.0, 0.0};
-    const int i = 2 * q + ((colour + j + k) & 1);
-    if (q < g.Q && j <= N - 2 && i >= 1 && i <= N - 2) {
-        const size_t row = rowid(g, j, k);
-        const size_t me = (size_t)colour * g.cs + row + q;
-        const size_t ob = (size_t)(1 - colour) * g.cs;
-        const int sh = i & 1;
-        const size_t ixp = ob + row + q + sh, ixm = ob + row + q + sh - 1;
-        const size_t iyp = ob + rowid(g, j + 1, k) + q, iym = ob + rowid(g, j - 1, k) + q;
-        const size_t izp = ob + rowid(g, j, k + 1) + q, izm = ob + rowid(g, j, k - 1) + q;
+    RowIdx r;
+    if (row_index(g, colour, q, j, k, r)) {
         if (mask & 1) {
-            const TA s = (TA)a.ms[me], ax = (TA)a.ma[0][me], ay = (TA)a.ma[1][me], az = (TA)a.ma[2][me];
+            const TA s = (TA)a.ms[r.me], ax = (TA)a.ma[0][r.me], ay = (TA)a.ma[1][r.me], az = (TA)a.ma[2][r.me];
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
                 TM *d = a.md[f];
-                const TA sum = (s - ax) * (TA)d[ixp] + (s + ax) * (TA)d[ixm] + (s - ay) * (TA)d[iyp]
-                               + (s + ay) * (TA)d[iym] + (s - az) * (TA)d[izp] + (s + az) * (TA)d[izm];
-                const TA old = (TA)d[me];
-                const TA gs = (TA)a.mb[f][me] - sum;
-                const TA dlt = gs - old;
-                d[me] = (TM)(old + omega * dlt);
+                const TA sum = mom_off<TA>(s, ax, ay, az, r, [&](size_t x) { return (TA)d[x]; });
+                const TA old = (TA)d[r.me];
+                const TA dlt = (TA)a.mb[f][r.me] - sum - old;
+                d[r.me] = (TM)(old + omega * dlt);
                 r2[f] = (double)dlt * (double)dlt;
             }
         }
         if (mask & 2) {
-            const TA ax = (TA)a.ta[0][me], ay = (TA)a.ta[1][me], az = (TA)a.ta[2][me];
+            const TA ax = (TA)a.ta[0][r.me], ay = (TA)a.ta[1][r.me], az = (TA)a.ta[2][r.me];
             TM *d = a.td;
-            const TA wxp = st - ax, wxm = st + ax, wyp = st - ay, wym = st + ay, wzp = st - az, wzm = st + az;
-            TA den = (TA)1.0;
-            TA sum = wxp * (TA)d[ixp] + wxm * (TA)d[ixm];
-            if (j == 1) {
-                den += (TA)(4.0 / 3.0) * wym;
-                sum += (wyp - wym * (TA)(1.0 / 3.0)) * (TA)d[iyp];
-            } else if (j == N - 2) {
-                den += (TA)(4.0 / 3.0) * wyp;
-                sum += (wym - wyp * (TA)(1.0 / 3.0)) * (TA)d[iym];
-            } else {
-                sum += wyp * (TA)d[iyp] + wym * (TA)d[iym];
-            }
-            if (k == 1) {
-                den += (TA)(4.0 / 3.0) * wzm;
-                sum += (wzp - wzm * (TA)(1.0 / 3.0)) * (TA)d[izp];
-            } else if (k == N - 2) {
-                den += (TA)(4.0 / 3.0) * wzp;
-                sum += (wzm - wzp * (TA)(1.0 / 3.0)) * (TA)d[izm];
-            } else {
-                sum += wzp * (TA)d[izp] + wzm * (TA)d[izm];
-            }
-            const TA old = (TA)d[me];
-            const TA gs = ((TA)a.tb[me] - sum) / den;
+            TA den;
+            const TA sum = theta_off<TA>(st, ax, ay, az, j, k, g.N, r, [&](size_t x) { return (TA)d[x]; }, den);
+            const TA old = (TA)d[r.me];
+            const TA gs = ((TA)a.tb[r.me] - sum) / den;
             const TA dlt = gs - old;
-            d[me] = (TM)(old + omega * dlt);
-            const double r = (double)den * (double)dlt;
-            r2[3] = r * r;
+            d[r.me] = (TM)(old + omega * dlt);
+            const double rr = (double)den * (double)dlt;
+            r2[3] = rr * rr;
         }
     }
     if (acc) {
         const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
         block_sum_store<4>(r2, partial + (size_t)blk * 4);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// BiCGSTAB (van der Vorst 1992) on the scaled rows, for up to four systems at once
+// (u, v, w share the momentum matrix; theta has its own).  Vectors live in the
+// colour layout; one launch covers both colours (blockIdx.z = 2 (k-1) + colour).
+// Scalars stay on the device: sc[8*sys + {0 rho, 1 alpha, 2 omega, 3 beta,
+// 4 ||r||^2, 5 breakdown flag}].  Iteration (p and v double-buffered):
+//   p' = r + beta (p - omega v),  v' = B p'              alpha = rho / (rh, v')
+//   s = r - alpha v',  t = B s                           omega = (t, s) / (t, t)
+//   x += alpha p' + omega s,  r = s - omega t            beta = (rho'/rho)(alpha/omega)
+// ---------------------------------------------------------------------------
+template <typename TM>
+struct BicgArgs {
+    const TM *ms, *ma[3], *mb[3];   // momentum rows
+    const TM *ta[3], *tb;           // energy rows
+    TM *x[4], *r[4], *rh[4], *p[4], *pn[4], *v[4], *vn[4], *t[4];
+};
+
+__device__ __forceinline__ bool bicg_node(const Geo &g, int q, int &j, int &k, int &colour, RowIdx &r)
+{
+    j = 1 + blockIdx.y * blockDim.y + threadIdx.y;
+    k = 1 + (blockIdx.z >> 1);
+    colour = blockIdx.z & 1;
+    return row_index(g, colour, q, j, k, r);
+}
+
+// phase 0: r = b - B x, rh = r, p = v = 0;  partials (r, r) twice
+// phase 1: p' = r + beta (p - omega v), v' = B p';  partials (rh, v')
+// phase 2: s = r - alpha v', t = B s;  partials (t, s), (t, t)
+// phase 3: x += alpha p' + omega s, r = s - omega t;  partials (rh, r), (r, r)
+template <typename TM, typename TA>
+__global__ void __launch_bounds__(256) k_bicg(Geo g, int phase, int mask, TA st, BicgArgs<TM> a,
+                                              const double *__restrict__ sc, double *__restrict__ partial)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    int j, k, colour;
+    RowIdx r;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (bicg_node(g, q, j, k, colour, r)) {
+        TA ms = 0, max = 0, may = 0, maz = 0, tax = 0, tay = 0, taz = 0;
+        if (mask & 1) {
+            ms = (TA)a.ms[r.me]; max = (TA)a.ma[0][r.me]; may = (TA)a.ma[1][r.me]; maz = (TA)a.ma[2][r.me];
+        }
+        if (mask & 2) {
+            tax = (TA)a.ta[0][r.me]; tay = (TA)a.ta[1][r.me]; taz = (TA)a.ta[2][r.me];
+        }
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            if (!((f < 3) ? (mask & 1) : (mask & 2))) continue;
+            const double *S = sc + 8 * f;
+            const TA alpha = (TA)S[1], omega = (TA)S[2], beta = (TA)S[3];
+            // y -> (B y)_me for the vector given by the functor
+            auto apply = [&](auto fy) -> TA {
+                if (f < 3) return fy(r.me) + mom_off<TA>(ms, max, may, maz, r, fy);
+                TA den;
+                const TA off = theta_off<TA>(st, tax, tay, taz, j, k, g.N, r, fy, den);
+                return den * fy(r.me) + off;
+            };
+            if (phase == 0) {
+                const TM *x = a.x[f];
+                const TA bx = apply([&](size_t i) { return (TA)x[i]; });
+                const TA b = f < 3 ? (TA)a.mb[f][r.me] : (TA)a.tb[r.me];
+                const TA rr = b - bx;
+                a.r[f][r.me] = (TM)rr;
+                a.rh[f][r.me] = (TM)rr;
+                a.p[f][r.me] = (TM)0;
+                a.v[f][r.me] = (TM)0;
+                acc[2 * f] = (double)rr * (double)rr;
+                acc[2 * f + 1] = acc[2 * f];
+            } else if (phase == 1) {
+                const TM *R = a.r[f], *P = a.p[f], *V = a.v[f];
+                auto pnew = [&](size_t i) { return (TA)R[i] + beta * ((TA)P[i] - omega * (TA)V[i]); };
+                const TA vv = apply(pnew);
+                a.pn[f][r.me] = (TM)pnew(r.me);
+                a.vn[f][r.me] = (TM)vv;
+                acc[2 * f] = (double)a.rh[f][r.me] * (double)vv;
+            } else if (phase == 2) {
+                const TM *R = a.r[f], *V = a.vn[f];
+                auto sv = [&](size_t i) { return (TA)R[i] - alpha * (TA)V[i]; };
+                const TA tt = apply(sv);
+                a.t[f][r.me] = (TM)tt;
+                const TA s0 = sv(r.me);
+                acc[2 * f] = (double)tt * (double)s0;
+                acc[2 * f + 1] = (double)tt * (double)tt;
+            } else {
+                const size_t m = r.me;
+                const TA s0 = (TA)a.r[f][m] - alpha * (TA)a.vn[f][m];
+                const TA xn = (TA)a.x[f][m] + alpha * (TA)a.pn[f][m] + omega * s0;
+                const TA rn = s0 - omega * (TA)a.t[f][m];
+                a.x[f][m] = (TM)xn;
+                a.r[f][m] = (TM)rn;
+                acc[2 * f] = (double)a.rh[f][m] * (double)rn;
+                acc[2 * f + 1] = (double)rn * (double)rn;
+            }
+        }
+    }
+    const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    block_sum_store<8>(acc, partial + (size_t)blk * 8);
+}
+
+// Reduce the partial records (8 values each) of one BiCGSTAB phase in fixed order
+// and update the scalars of the active systems (one block of 256 threads).
+__global__ void __launch_bounds__(256) k_bicg_scalars(int phase, int mask, const double *__restrict__ part, int nb,
+                                                      double *__restrict__ sc)
+{
+    __shared__ double sh[8][256];
+    const int t = threadIdx.x;
+    for (int c = 0; c < 8; ++c) {
+        double s = 0.0;
+        for (int b = t; b < nb; b += 256) s += part[(size_t)b * 8 + c];
+        sh[c][t] = s;
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+            for (int c = 0; c < 8; ++c) sh[c][t] += sh[c][t + w];
+        __syncthreads();
+    }
+    if (t != 0) return;
+    for (int f = 0; f < 4; ++f) {
+        if (!((f < 3) ? (mask & 1) : (mask & 2))) continue;
+        double *S = sc + 8 * f;
+        const double a = sh[2 * f][0], b = sh[2 * f + 1][0];
+        if (phase == 0) {
+            S[0] = a; S[1] = 0.0; S[2] = 1.0; S[3] = 0.0; S[4] = b; S[5] = 0.0;
+        } else if (phase == 1) {
+            if (a != 0.0 && isfinite(a) && isfinite(S[0])) S[1] = S[0] / a;
+            else { S[1] = 0.0; S[5] = 1.0; }
+        } else if (phase == 2) {
+            S[2] = (b > 0.0 && isfinite(a) && isfinite(b)) ? a / b : 0.0;
+        } else {
+            const double rho = a;
+            if (S[0] != 0.0 && S[2] != 0.0 && isfinite(rho)) S[3] = (rho / S[0]) * (S[1] / S[2]);
+            else { S[3] = 0.0; if (b > 0.0) S[5] = 1.0; }
+            S[0] = rho;
+            S[4] = b;
+        }
     }
 }
 

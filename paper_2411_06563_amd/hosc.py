@@ -21,6 +21,9 @@ HEADER = os.path.join(_build.ROOT, "include", "hosc.h")
 
 HOSC_FP64 = 0
 HOSC_FP32_REFINED = 1
+SOLVER_AUTO = 0
+SOLVER_SOR = 1
+SOLVER_BICGSTAB = 2
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -37,13 +40,15 @@ class CParams(ctypes.Structure):
                 ("Pr", ctypes.c_double), ("n_pl", ctypes.c_double), ("dt", ctypes.c_double),
                 ("theta_hot", ctypes.c_double), ("theta_cold", ctypes.c_double), ("theta_ref", ctypes.c_double),
                 ("lam", ctypes.c_double), ("div_tol", ctypes.c_double), ("solve_rtol", ctypes.c_double),
-                ("solve_maxit", ctypes.c_int32), ("check_every", ctypes.c_int32), ("omega", ctypes.c_double),
+                ("solve_maxit", ctypes.c_int32), ("check_every", ctypes.c_int32), ("solver", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("omega", ctypes.c_double),
                 ("i2_floor", ctypes.c_double), ("phi", ctypes.c_double)]
 
 
 class CStepInfo(ctypes.Structure):
     _fields_ = [("res", ctypes.c_double * 4), ("relres", ctypes.c_double * 4), ("maxdiv", ctypes.c_double),
-                ("step", ctypes.c_int64), ("sweeps", ctypes.c_int32 * 2), ("corrected", ctypes.c_int32),
+                ("step", ctypes.c_int64), ("sweeps", ctypes.c_int32 * 2), ("bicg_iters", ctypes.c_int32 * 2),
+                ("corrected", ctypes.c_int32),
                 ("status", ctypes.c_int32)]
 
 
@@ -56,7 +61,8 @@ class CDiag(ctypes.Structure):
 class CPerf(ctypes.Structure):
     _fields_ = [("sweep_launches", ctypes.c_int64), ("sweep_ms", ctypes.c_double), ("sweep_bytes", ctypes.c_double),
                 ("assemble_launches", ctypes.c_int64), ("assemble_ms", ctypes.c_double),
-                ("assemble_bytes", ctypes.c_double)]
+                ("assemble_bytes", ctypes.c_double), ("bicg_launches", ctypes.c_int64), ("bicg_ms", ctypes.c_double),
+                ("bicg_bytes", ctypes.c_double)]
 
 
 _lib = None
@@ -139,12 +145,14 @@ class StepInfo:
     maxdiv: float
     step: int
     sweeps: list
+    bicg_iters: list
     corrected: int
     status: int
 
     @classmethod
     def of(cls, c: CStepInfo):
-        return cls(list(c.res), list(c.relres), c.maxdiv, c.step, list(c.sweeps), c.corrected, c.status)
+        return cls(list(c.res), list(c.relres), c.maxdiv, c.step, list(c.sweeps), list(c.bicg_iters), c.corrected,
+                   c.status)
 
 
 class Solver:

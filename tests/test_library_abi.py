@@ -32,7 +32,8 @@ def test_workspace_scales_with_grid():
     b65 = hosc.workspace_bytes(hosc.params(65))
     b129 = hosc.workspace_bytes(hosc.params(129))
     assert 6.0 < b129 / b65 < 9.0
-    assert b129 < 1.0e9          # one 129^3 FP64 cavity fits in well under 1 GB
+    sor = hosc.workspace_bytes(hosc.params(129, solver=hosc.SOLVER_SOR))
+    assert sor < 0.6e9 < b129 < 1.1e9    # BiCGSTAB vectors are carved only when that solver may run
 
 
 def test_create_rejects_bad_workspace():
