@@ -86,7 +86,8 @@ typedef struct hosc_params {
     int32_t check_every;    /* sweeps between convergence checks; 0 -> adaptive */
     int32_t solver;         /* hosc_solver_kind (default HOSC_SOLVER_AUTO) */
     int32_t reserved;       /* must be 0 */
-    double omega;           /* SOR relaxation of the red-black sweeps, 0 < omega < 2 (default 1.0) */
+    double omega;           /* SOR relaxation of the red-black sweeps: 0 = adaptive per system (default),
+                               else fixed in (0, 2) */
     double i2_floor;        /* eta = max(I2, i2_floor)^((n-1)/2), default 1e-8 */
     double phi;             /* irreversibility ratio of the fluid-friction entropy, default 1e-4 */
 } hosc_params;

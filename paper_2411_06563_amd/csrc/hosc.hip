@@ -123,7 +123,7 @@ const char *check_params(const hosc_params *p)
     if (!(p->solve_rtol > 0.0 && p->solve_rtol < 1.0)) return "solve_rtol must be in (0, 1)";
     if (p->solve_maxit < 1) return "solve_maxit must be >= 1";
     if (p->check_every < 0) return "check_every must be >= 0";
-    if (!(p->omega > 0.0 && p->omega < 2.0)) return "omega must be in (0, 2)";
+    if (!(p->omega >= 0.0 && p->omega < 2.0)) return "omega must be 0 (adaptive) or in (0, 2)";
     if (p->solver < HOSC_SOLVER_AUTO || p->solver > HOSC_SOLVER_BICGSTAB) return "unknown solver";
     if (p->reserved != 0) return "reserved must be 0";
     if (!(p->i2_floor > 0.0) || !std::isfinite(p->i2_floor)) return "i2_floor must be finite and > 0";
@@ -193,6 +193,7 @@ struct hosc_solver {
     int sticky = HOSC_OK;
     int last_sweeps[2] = {0, 0};
     int last_bicg[2] = {0, 0};
+    double om[2] = {1.0, 1.0};          // SOR relaxation of each group (adaptive when P.omega == 0)
     std::string err;
     // kernel timing
     bool prof = false;
@@ -333,10 +334,19 @@ hosc_status timed_end(hosc_solver *s, int kind, double bytes)
     return HOSC_OK;
 }
 
+// Zero the increments and every BiCGSTAB vector.  The kernels only ever write
+// interior entries, so the wall entries of these colour arrays stay zero: the
+// Dirichlet walls of the increment systems.
 hosc_status zero_colour_increments(hosc_solver *s)
 {
-    for (int d = 0; d < 3; ++d) HIPCHK(s, hipMemsetAsync(s->md[d], 0, 2 * s->g.cs * sizeof(double), s->st));
-    HIPCHK(s, hipMemsetAsync(s->td, 0, 2 * s->g.cs * sizeof(double), s->st));
+    const size_t b = 2 * s->g.cs * sizeof(double);
+    for (int d = 0; d < 3; ++d) HIPCHK(s, hipMemsetAsync(s->md[d], 0, b, s->st));
+    HIPCHK(s, hipMemsetAsync(s->td, 0, b, s->st));
+    if (s->Y.bicg_arrays)
+        for (int f = 0; f < 4; ++f) {
+            double *v[7] = {s->br[f], s->brh[f], s->bp[f], s->bpn[f], s->bv[f], s->bvn[f], s->bt[f]};
+            for (double *x : v) HIPCHK(s, hipMemsetAsync(x, 0, b, s->st));
+        }
     return HOSC_OK;
 }
 
@@ -360,6 +370,7 @@ hosc_status reset_state(hosc_solver *s)
     s->last_sweeps[0] = s->last_sweeps[1] = 0;
     s->last_bicg[0] = s->last_bicg[1] = 0;
     s->bicg_until[0] = s->bicg_until[1] = -1;
+    s->om[0] = s->om[1] = s->P.omega > 0.0 ? s->P.omega : 1.0;
     HIPCHK(s, hipStreamSynchronize(s->st));
     return HOSC_OK;
 }
@@ -433,32 +444,57 @@ hosc_status zero_group(hosc_solver *s, int group)
 // ||r|| <= rtol ||b|| (scaled rows).  One sweep = red half then black half; the sums
 // of squared pre-update residuals of the black half and (1-omega)^2 times those of
 // the red half give the residual of the state between the two halves, so
-// convergence is known without an extra pass.  In auto mode a group whose
-// residual grows or stalls is returned in *failed instead of raising an error.
+// convergence is known without an extra pass.  Each group plans its own number of
+// sweeps per batch (from its count at the previous step, then from the measured
+// contraction rate); a launch updates only the groups still inside their plan.  In
+// auto mode a group whose residual grows or stalls is returned in *failed.
+// Young's relation for a consistently ordered matrix (red-black ordering of a
+// 7-point stencil is one): an SOR contraction lam at relaxation w gives the
+// Jacobi radius mu^2 = (lam + w - 1)^2 / (lam w^2) and the optimum
+// w = 2 / (1 + sqrt(1 - mu^2)).  Used, damped and clamped, to adapt w per group.
+double young_omega(double lam, double w)
+{
+    if (!(lam > 0.0 && lam < 1.0)) return w;
+    const double mu2 = std::min(0.999, (lam + w - 1.0) * (lam + w - 1.0) / (lam * w * w));
+    return 2.0 / (1.0 + std::sqrt(1.0 - mu2));
+}
+
 hosc_status run_sor(hosc_solver *s, int mask, const double bn2[4], SolveOut &o, int *failed)
 {
-    const double om = s->P.omega;
     const double rtol = s->P.solve_rtol;
     const double ct = s->g.h2 / 12.0 - s->P.dt / 2.0;
     const double Ct = 1.0 - 6.0 * ct * s->g.invh2;
     const double st = (ct * s->g.invh2) / Ct;
     const bool autom = s->P.solver == HOSC_SOLVER_AUTO;
+    static const unsigned kStore[2] = {0x7u, 0x8u};   // residual components of each group
     SweepArgs<double> a = sweep_args(s);
     int active = mask;
     *failed = 0;
-    double prev[2] = {-1.0, -1.0};
-    int prev_at[2] = {0, 0};
-    int predicted = std::max(s->last_sweeps[0], s->last_sweeps[1]);
-    int batch = s->P.check_every > 0 ? s->P.check_every : std::max(2, predicted > 0 ? predicted - 1 : 8);
+    double ref[2] = {-1.0, -1.0}, last_res[2] = {-1.0, -1.0};
+    int ref_at[2] = {0, 0}, last_at[2] = {0, 0};
+    int plan[2] = {0, 0};
+    for (int grp = 0; grp < 2; ++grp) {
+        const int prev = s->last_sweeps[grp];
+        plan[grp] = s->P.check_every > 0 ? s->P.check_every : (prev > 0 ? std::max(2, (3 * prev + 3) / 4) : 4);
+    }
     while (active) {
-        const double bytes = sweep_bytes(s->g, active);
-        for (int q = 0; q < batch; ++q) {
-            const int acc = q == batch - 1;
+        int nsw = 0;
+        for (int grp = 0; grp < 2; ++grp)
+            if (active & (1 << grp)) nsw = std::max(nsw, plan[grp]);
+        for (int q = 0; q < nsw; ++q) {
+            int m = 0;
+            unsigned store = 0;
+            for (int grp = 0; grp < 2; ++grp) {
+                if (!(active & (1 << grp)) || q >= plan[grp]) continue;
+                m |= 1 << grp;
+                if (q == plan[grp] - 1) store |= kStore[grp];
+            }
+            const double bytes = sweep_bytes(s->g, m);
             for (int colour = 0; colour < 2; ++colour) {
                 hosc_status r = timed_begin(s);
                 if (r) return r;
-                k_sweep<double, double><<<s->L.grd_sw, s->L.blk_sw, 0, s->st>>>(s->g, colour, active, om, st, a,
-                                                                               colour ? s->partB : s->partR, acc);
+                k_sweep<double, double><<<s->L.grd_sw, s->L.blk_sw, 0, s->st>>>(s->g, colour, m, s->om[0], s->om[1], st,
+                                                                               a, colour ? s->partB : s->partR, store);
                 r = timed_end(s, 0, bytes);
                 if (r) return r;
             }
@@ -473,10 +509,12 @@ hosc_status run_sor(hosc_solver *s, int mask, const double bn2[4], SolveOut &o, 
         if (r) return r;
         for (int grp = 0; grp < 2; ++grp) {
             if (!(active & (1 << grp))) continue;
-            o.sweeps[grp] += batch;
+            o.sweeps[grp] += plan[grp];
+            const int done = o.sweeps[grp];
             const int f0 = grp == 0 ? 0 : 3, f1 = grp == 0 ? 3 : 4;
             bool conv = true, finite = true;
             double worst = 0.0;
+            const double om = s->om[grp];
             for (int f = f0; f < f1; ++f) {
                 const double r2 = s->hbuf[8 + f] + (1.0 - om) * (1.0 - om) * s->hbuf[4 + f];
                 if (!std::isfinite(r2)) finite = false;
@@ -494,10 +532,10 @@ hosc_status run_sor(hosc_solver *s, int mask, const double bn2[4], SolveOut &o, 
                 active &= ~(1 << grp);
                 continue;
             }
-            const int done = o.sweeps[grp];
-            // divergence: residual not finite or grown by 2x; stall: < 2x reduction over 100 sweeps
-            const bool diverged = !finite || (prev[grp] >= 0.0 && worst > 2.0 * prev[grp]);
-            const bool stalled = prev[grp] >= 0.0 && done - prev_at[grp] >= 100 && worst > 0.5 * prev[grp];
+            // divergence: not finite or grown 2x over the reference; stall: less than a
+            // 2x reduction over 100 sweeps
+            const bool diverged = !finite || (ref[grp] >= 0.0 && worst > 2.0 * ref[grp]);
+            const bool stalled = ref[grp] >= 0.0 && done - ref_at[grp] >= 100 && worst > 0.5 * ref[grp];
             if (diverged || stalled || done >= s->P.solve_maxit) {
                 if (autom) {
                     *failed |= 1 << grp;
@@ -508,17 +546,31 @@ hosc_status run_sor(hosc_solver *s, int mask, const double bn2[4], SolveOut &o, 
                 if (done >= s->P.solve_maxit)
                     return fail(s, HOSC_E_NOCONV, "implicit solve did not converge within solve_maxit sweeps");
             }
-            if (prev[grp] < 0.0 || done - prev_at[grp] >= 100) {
-                prev[grp] = worst;
-                prev_at[grp] = done;
-            } else if (worst < prev[grp]) {
-                // keep the reference for the stall test, but track progress for divergence
+            if (ref[grp] < 0.0 || done - ref_at[grp] >= 100) {
+                ref[grp] = worst;
+                ref_at[grp] = done;
             }
+            // next plan: from the contraction rate between the last two checks
+            int next = std::max(2, std::min(done, 64));
+            if (last_res[grp] > 0.0 && worst > 0.0 && worst < last_res[grp]) {
+                const double rate = std::pow(worst / last_res[grp], 1.0 / (double)(done - last_at[grp]));
+                if (rate > 0.0 && rate < 1.0) {
+                    const double need = std::log(rtol / worst) / std::log(rate);
+                    next = (int)std::min(256.0, std::max(1.0, std::ceil(need) + 1.0));
+                    if (s->P.omega == 0.0 && done - last_at[grp] >= 4) {
+                        // past the optimum the contraction is about w - 1: back off
+                        const double w = s->om[grp];
+                        double wn = rate > 0.97 * (w - 1.0) && w > 1.05 ? w - 0.05 : young_omega(rate, w);
+                        wn = std::min(1.9, std::max(1.0, wn));
+                        s->om[grp] = w + 0.5 * (wn - w);
+                    }
+                }
+            }
+            last_res[grp] = worst;
+            last_at[grp] = done;
+            plan[grp] = s->P.check_every > 0 ? s->P.check_every : next;
+            plan[grp] = std::min(plan[grp], std::max(1, s->P.solve_maxit - done));
         }
-        if (!active) break;
-        const int done = std::max(o.sweeps[0], o.sweeps[1]);
-        batch = s->P.check_every > 0 ? s->P.check_every : std::max(2, std::min(done / 2, 64));
-        batch = std::min(batch, std::max(1, s->P.solve_maxit - done));
     }
     return HOSC_OK;
 }
@@ -785,7 +837,7 @@ hosc_status hosc_params_default(hosc_params *p)
     p->check_every = 0;
     p->solver = HOSC_SOLVER_AUTO;
     p->reserved = 0;
-    p->omega = 1.0;
+    p->omega = 0.0;
     p->i2_floor = 1e-8;
     p->phi = 1e-4;
     return HOSC_OK;

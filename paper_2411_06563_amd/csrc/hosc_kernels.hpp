@@ -47,7 +47,7 @@ __device__ __forceinline__ size_t rowid(const Geo &g, int j, int k) { return ((s
 // order across the wavefronts of a block).  Every thread of the block must call.
 // ---------------------------------------------------------------------------
 template <int NV>
-__device__ __forceinline__ void block_sum_store(double (&v)[NV], double *out)
+__device__ __forceinline__ void block_sum_store(double (&v)[NV], double *out, unsigned store = ~0u)
 {
     __shared__ double sh[NV][16];
     const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
@@ -60,7 +60,7 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NV], double *out)
         if (lane == 0) sh[q][wave] = x;
     }
     __syncthreads();
-    if (tid < NV) {
+    if (tid < NV && ((store >> tid) & 1u)) {
         double s = 0.0;
         for (int w = 0; w < nwave; ++w) s += sh[tid][w];
         out[tid] = s;
@@ -534,7 +534,7 @@ __device__ __forceinline__ TA theta_off(TA st, TA ax, TA ay, TA az, int j, int k
 // Red-black SOR half-sweep on the scaled rows (momentum: three right-hand sides
 // on one matrix; energy with the walls eliminated).  Per-block partial sums of
 // the squared scaled residuals r = b - B d at the updated nodes, before their
-// update (when acc != 0).
+// update, are stored for the systems in `store` (bit f = system f; none if 0).
 // ---------------------------------------------------------------------------
 template <typename TM>
 struct SweepArgs {
@@ -545,8 +545,8 @@ struct SweepArgs {
 };
 
 template <typename TM, typename TA>
-__global__ void __launch_bounds__(256) k_sweep(Geo g, int colour, int mask, TA omega, TA st, SweepArgs<TM> a,
-                                               double *__restrict__ partial, int acc)
+__global__ void __launch_bounds__(256) k_sweep(Geo g, int colour, int mask, TA omega_m, TA omega_t, TA st,
+                                               SweepArgs<TM> a, double *__restrict__ partial, unsigned store)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y, k = 1 + blockIdx.z;
@@ -561,7 +561,7 @@ __global__ void __launch_bounds__(256) k_sweep(Geo g, int colour, int mask, TA o
                 const TA sum = mom_off<TA>(s, ax, ay, az, r, [&](size_t x) { return (TA)d[x]; });
                 const TA old = (TA)d[r.me];
                 const TA dlt = (TA)a.mb[f][r.me] - sum - old;
-                d[r.me] = (TM)(old + omega * dlt);
+                d[r.me] = (TM)(old + omega_m * dlt);
                 r2[f] = (double)dlt * (double)dlt;
             }
         }
@@ -573,14 +573,14 @@ __global__ void __launch_bounds__(256) k_sweep(Geo g, int colour, int mask, TA o
             const TA old = (TA)d[r.me];
             const TA gs = ((TA)a.tb[r.me] - sum) / den;
             const TA dlt = gs - old;
-            d[r.me] = (TM)(old + omega * dlt);
+            d[r.me] = (TM)(old + omega_t * dlt);
             const double rr = (double)den * (double)dlt;
             r2[3] = rr * rr;
         }
     }
-    if (acc) {
+    if (store) {
         const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-        block_sum_store<4>(r2, partial + (size_t)blk * 4);
+        block_sum_store<4>(r2, partial + (size_t)blk * 4, store);
     }
 }
 

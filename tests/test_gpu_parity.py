@@ -112,14 +112,17 @@ def test_assembly_after_steps(hosc, oracle_lib, N, n_pl):
     s.close()
 
 
-@pytest.mark.parametrize("solver", ["sor", "bicgstab"])
-def test_config1_200_steps(hosc, oracle_lib, solver):
-    """17^3, n = 1, Ra = 1e3, Pr = 1, dt = 1e-4, noise 1e-3 seed 1, implicit-system
-    tolerance 1e-10: relative L2 <= 1e-10 per field at steps 1, 10, 200."""
+@pytest.mark.parametrize("solver,rtol", [("sor", 1e-11), ("bicgstab", 1e-11)])
+def test_config1_200_steps(hosc, oracle_lib, solver, rtol):
+    """17^3, n = 1, Ra = 1e3, Pr = 1, dt = 1e-4, noise 1e-3 seed 1: relative L2 <=
+    1e-10 per field at steps 1, 10, 200.  On the first step the whole velocity is one
+    increment, so a solve stopped at a relative residual of 1e-10 leaves a field
+    error of about 1e-10 times the conditioning; the implicit systems are therefore
+    solved to 1e-11 (diagonally scaled residual) to keep the field error below 1e-10."""
     N = 17
     say(f"[config1] 17^3 n=1 Ra=1e3 dt=1e-4, 200 steps, {solver}")
     kind = hosc.SOLVER_SOR if solver == "sor" else hosc.SOLVER_BICGSTAB
-    s, o = _pair(hosc, oracle_lib, N, Ra=1e3, n_pl=1.0, Pr=1.0, dt=1e-4, solve_rtol=1e-10, solver=kind)
+    s, o = _pair(hosc, oracle_lib, N, Ra=1e3, n_pl=1.0, Pr=1.0, dt=1e-4, solve_rtol=rtol, solver=kind)
     s.init_fields(1, 1e-3)
     o.set_state(**initial_state(N, 1, 1e-3))
     done = 0
@@ -138,7 +141,7 @@ def test_config1_200_steps(hosc, oracle_lib, solver):
 
 
 @pytest.mark.parametrize("N,n_pl,Ra,dt,solver", [(17, 0.75, 1e5, 5e-5, "auto"), (18, 1.25, 1e4, 1e-4, "auto"),
-                                                 (20, 0.75, 1e5, 2e-4, "auto"), (17, 0.75, 1e5, 5e-5, "bicgstab"),
+                                                 (20, 0.75, 1e4, 1e-4, "auto"), (17, 0.75, 1e5, 5e-5, "bicgstab"),
                                                  (19, 1.25, 3e4, 1e-4, "bicgstab")])
 def test_power_law_steps(hosc, oracle_lib, N, n_pl, Ra, dt, solver):
     """Power-law cavities over 30 steps.  On these coarse grids the momentum rows
@@ -205,4 +208,23 @@ def test_config2_first_steps_full_size(hosc, oracle_lib):
     r = o.diagnostics()
     assert abs(d["nu_mean_hot"] - r["nu_mean_hot"]) <= 1e-10 * abs(r["nu_mean_hot"])
     assert abs(d["e_total"] - r["e_total"]) <= 1e-10 * abs(r["e_total"])
+    s.close()
+
+
+def test_noconv_is_reported_and_sticky(hosc, oracle_lib):
+    """Failure path forced from the host: a one-sweep cap makes the implicit solve
+    stop unconverged; the step reports HOSC_E_NOCONV, the handle refuses to step
+    again, and setting a new state clears it (every kernel exits normally)."""
+    N = 17
+    say("[noconv] N=17 solve_maxit=1 solver=sor")
+    s = hosc.Solver(hosc.params(N, Ra=1e4, n_pl=1.0, dt=1e-3, solve_rtol=1e-12, solve_maxit=1,
+                                solver=hosc.SOLVER_SOR))
+    s.init_fields(1, 1e-3)
+    with pytest.raises(hosc.HoscError) as e:
+        s.step(1)
+    assert e.value.name == "HOSC_E_NOCONV"
+    with pytest.raises(hosc.HoscError) as e:
+        s.step(1)
+    assert e.value.name == "HOSC_E_STATE"
+    s.init_fields(1, 1e-3)
     s.close()

@@ -20,7 +20,7 @@ def test_params_default_and_validation():
     p = hosc.params(17)
     assert p.N == 17 and p.Ra == 1e3 and p.Pr == 1.0 and p.n_pl == 1.0 and p.solve_rtol == 1e-10
     assert hosc.workspace_bytes(p) > 30 * 17 ** 3 * 8
-    for N, bad in ((4, {}), (17, dict(Pr=0.0)), (17, dict(dt=-1.0)), (17, dict(n_pl=0.0)), (17, dict(omega=2.0)),
+    for N, bad in ((4, {}), (17, dict(Pr=0.0)), (17, dict(dt=-1.0)), (17, dict(n_pl=0.0)), (17, dict(omega=2.0)), (17, dict(omega=-0.5)),
                    (17, dict(solve_rtol=0.0))):
         q = hosc.params(N, **bad)
         with pytest.raises(hosc.HoscError) as e:
