@@ -25,7 +25,7 @@ using namespace hosc;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kRed = 32;    // doubles in the reduction output block
+constexpr int kRed = 64;    // doubles in the reduction output block
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -98,7 +98,7 @@ Layout make_layout(const Geo &g, const Launch &L, int solver)
     size_t b = 0;
     b += y.natural_arrays * align_up(g.n3 * sizeof(double));
     b += (y.colour_arrays + y.bicg_arrays) * align_up(2 * g.cs * sizeof(double));
-    b += 2 * align_up(recs * sizeof(double));                 // two partial buffers (red / black half)
+    b += 4 * align_up(recs * sizeof(double));                 // partial buffers: red / black half, last and first sweep
     b += align_up(kRed * sizeof(double));                      // reduction outputs
     b += align_up((size_t)g.N * sizeof(double));               // Simpson weights
     b += 2 * align_up((size_t)g.N * g.N * sizeof(double));     // Nu_local hot / cold
@@ -181,7 +181,7 @@ struct hosc_solver {
     double *u, *v, *w, *T, *p, *u2, *v2, *w2, *eta, *etap, *E[3], *Ep[3], *dbg;
     // colour layout
     double *ms, *ma[3], *mb[3], *md[3], *ta[3], *tb, *td;
-    double *partR, *partB, *red, *wq, *nuh, *nuc, *avh, *avc, *nuout;
+    double *partR, *partB, *partR0, *partB0, *red, *wq, *nuh, *nuc, *avh, *avc, *nuout;
     // BiCGSTAB vectors (4 systems) and scalars
     double *br[4], *brh[4], *bp[4], *bpn[4], *bv[4], *bvn[4], *bt[4];
     double *bsc;
@@ -200,6 +200,7 @@ struct hosc_solver {
     std::vector<hipEvent_t> ev;     // pairs (start, stop)
     std::vector<double> ev_bytes;   // algorithmic bytes of each timed launch
     std::vector<int> ev_kind;       // 0 sweep, 1 assemble, 2 BiCGSTAB phase
+    std::vector<int> ev_count;      // kernel launches between the two events
     int ev_used = 0;
     hosc_perf perf{};
 };
@@ -253,6 +254,8 @@ void carve(hosc_solver *s, char *base)
     const size_t pb = align_up(s->Y.partial * sizeof(double));
     s->partR = take(pb);
     s->partB = take(pb);
+    s->partR0 = take(pb);
+    s->partB0 = take(pb);
     s->red = take(align_up(kRed * sizeof(double)));
     s->wq = take(align_up((size_t)s->g.N * sizeof(double)));
     s->nuh = take(align_up((size_t)s->g.N * s->g.N * sizeof(double)));
@@ -296,7 +299,7 @@ hosc_status harvest_events(hosc_solver *s)
         float ms = 0.0f;
         HIPCHK(s, hipEventElapsedTime(&ms, s->ev[2 * q], s->ev[2 * q + 1]));
         if (s->ev_kind[q] == 0) {
-            s->perf.sweep_launches += 1;
+            s->perf.sweep_launches += s->ev_count[q];
             s->perf.sweep_ms += ms;
             s->perf.sweep_bytes += s->ev_bytes[q];
         } else if (s->ev_kind[q] == 1) {
@@ -324,12 +327,13 @@ hosc_status timed_begin(hosc_solver *s)
     HIPCHK(s, hipEventRecord(s->ev[2 * s->ev_used], s->st));
     return HOSC_OK;
 }
-hosc_status timed_end(hosc_solver *s, int kind, double bytes)
+hosc_status timed_end(hosc_solver *s, int kind, double bytes, int count = 1)
 {
     if (!s->prof) return HOSC_OK;
     HIPCHK(s, hipEventRecord(s->ev[2 * s->ev_used + 1], s->st));
     s->ev_kind[s->ev_used] = kind;
     s->ev_bytes[s->ev_used] = bytes;
+    s->ev_count[s->ev_used] = count;
     s->ev_used += 1;
     return HOSC_OK;
 }
@@ -466,44 +470,47 @@ hosc_status run_sor(hosc_solver *s, int mask, const double bn2[4], SolveOut &o, 
     const double Ct = 1.0 - 6.0 * ct * s->g.invh2;
     const double st = (ct * s->g.invh2) / Ct;
     const bool autom = s->P.solver == HOSC_SOLVER_AUTO;
+    const bool adapt = s->P.omega == 0.0;
     static const unsigned kStore[2] = {0x7u, 0x8u};   // residual components of each group
     SweepArgs<double> a = sweep_args(s);
     int active = mask;
     *failed = 0;
-    double ref[2] = {-1.0, -1.0}, last_res[2] = {-1.0, -1.0};
-    int ref_at[2] = {0, 0}, last_at[2] = {0, 0};
+    double ref[2] = {-1.0, -1.0};
+    int ref_at[2] = {0, 0};
     int plan[2] = {0, 0};
-    for (int grp = 0; grp < 2; ++grp) {
-        const int prev = s->last_sweeps[grp];
-        plan[grp] = s->P.check_every > 0 ? s->P.check_every : (prev > 0 ? std::max(2, (3 * prev + 3) / 4) : 4);
-    }
+    for (int grp = 0; grp < 2; ++grp)
+        plan[grp] = s->P.check_every > 0 ? s->P.check_every : std::max(2, s->last_sweeps[grp] + 1);
     while (active) {
         int nsw = 0;
         for (int grp = 0; grp < 2; ++grp)
             if (active & (1 << grp)) nsw = std::max(nsw, plan[grp]);
+        hosc_status r = timed_begin(s);
+        if (r) return r;
+        double bytes = 0.0;
         for (int q = 0; q < nsw; ++q) {
             int m = 0;
-            unsigned store = 0;
+            unsigned store = 0, store0 = 0;
             for (int grp = 0; grp < 2; ++grp) {
                 if (!(active & (1 << grp)) || q >= plan[grp]) continue;
                 m |= 1 << grp;
                 if (q == plan[grp] - 1) store |= kStore[grp];
+                if (q == 0 && plan[grp] > 1) store0 |= kStore[grp];
             }
-            const double bytes = sweep_bytes(s->g, m);
-            for (int colour = 0; colour < 2; ++colour) {
-                hosc_status r = timed_begin(s);
-                if (r) return r;
-                k_sweep<double, double><<<s->L.grd_sw, s->L.blk_sw, 0, s->st>>>(s->g, colour, m, s->om[0], s->om[1], st,
-                                                                               a, colour ? s->partB : s->partR, store);
-                r = timed_end(s, 0, bytes);
-                if (r) return r;
-            }
+            bytes += 2.0 * sweep_bytes(s->g, m);
+            for (int colour = 0; colour < 2; ++colour)
+                k_sweep<double, double><<<s->L.grd_sw, s->L.blk_sw, 0, s->st>>>(
+                    s->g, colour, m, s->om[0], s->om[1], st, a, colour ? s->partB : s->partR, store,
+                    colour ? s->partB0 : s->partR0, store0);
         }
-        hosc_status r = launch_check(s, "sweep");
+        r = timed_end(s, 0, bytes, 2 * nsw);
         if (r) return r;
-        k_reduce<<<1, 256, 0, s->st>>>(s->partR, (int)s->L.nb_sw, 4, 0, s->red + 4);
-        k_reduce<<<1, 256, 0, s->st>>>(s->partB, (int)s->L.nb_sw, 4, 0, s->red + 8);
-        HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red, 12 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+        r = launch_check(s, "sweep");
+        if (r) return r;
+        k_reduce<<<1, 1024, 0, s->st>>>(s->partR, (int)s->L.nb_sw, 4, 0, s->red + 4);
+        k_reduce<<<1, 1024, 0, s->st>>>(s->partB, (int)s->L.nb_sw, 4, 0, s->red + 8);
+        k_reduce<<<1, 1024, 0, s->st>>>(s->partR0, (int)s->L.nb_sw, 4, 0, s->red + 32);
+        k_reduce<<<1, 1024, 0, s->st>>>(s->partB0, (int)s->L.nb_sw, 4, 0, s->red + 36);
+        HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red, 40 * sizeof(double), hipMemcpyDeviceToHost, s->st));
         HIPCHK(s, hipStreamSynchronize(s->st));
         r = harvest_events(s);
         if (r) return r;
@@ -512,16 +519,29 @@ hosc_status run_sor(hosc_solver *s, int mask, const double bn2[4], SolveOut &o, 
             o.sweeps[grp] += plan[grp];
             const int done = o.sweeps[grp];
             const int f0 = grp == 0 ? 0 : 3, f1 = grp == 0 ? 3 : 4;
-            bool conv = true, finite = true;
-            double worst = 0.0;
             const double om = s->om[grp];
+            bool conv = true, finite = true;
+            double worst = 0.0, worst0 = 0.0;
             for (int f = f0; f < f1; ++f) {
                 const double r2 = s->hbuf[8 + f] + (1.0 - om) * (1.0 - om) * s->hbuf[4 + f];
+                const double r20 = s->hbuf[36 + f] + (1.0 - om) * (1.0 - om) * s->hbuf[32 + f];
                 if (!std::isfinite(r2)) finite = false;
                 const double rel = bn2[f] > 0.0 ? std::sqrt(r2 / bn2[f]) : 0.0;
                 o.relres[f] = rel;
                 worst = std::max(worst, rel);
+                if (bn2[f] > 0.0) worst0 = std::max(worst0, std::sqrt(r20 / bn2[f]));
                 if (!(bn2[f] == 0.0 || std::sqrt(r2) <= rtol * std::sqrt(bn2[f]))) conv = false;
+            }
+            // contraction per sweep inside this batch (first vs last sweep)
+            double rate = -1.0;
+            if (finite && plan[grp] > 1 && worst0 > 0.0 && worst > 0.0 && worst < worst0)
+                rate = std::pow(worst / worst0, 1.0 / (double)(plan[grp] - 1));
+            if (adapt && rate > 0.0 && rate < 1.0 && plan[grp] >= 4) {
+                // past the optimum the contraction is about w - 1: back off
+                const double w = s->om[grp];
+                double wn = rate > 0.97 * (w - 1.0) && w > 1.05 ? w - 0.05 : young_omega(rate, w);
+                wn = std::min(1.9, std::max(1.0, wn));
+                s->om[grp] = w + 0.5 * (wn - w);
             }
             if (finite && conv) {
                 for (int f = f0; f < f1; ++f)
@@ -529,12 +549,17 @@ hosc_status run_sor(hosc_solver *s, int mask, const double bn2[4], SolveOut &o, 
                         const size_t b = 2 * s->g.cs * sizeof(double);
                         HIPCHK(s, hipMemsetAsync(f < 3 ? s->md[f] : s->td, 0, b, s->st));
                     }
+                // sweeps that would have sufficed, for the next step's plan
+                int suff = done;
+                if (rate > 0.0 && rate < 1.0 && worst > 0.0)
+                    suff = done - (int)std::floor(std::log(rtol / worst) / std::log(rate));
+                s->last_sweeps[grp] = std::max(1, std::min(done, suff));
                 active &= ~(1 << grp);
                 continue;
             }
             // divergence: not finite or grown 2x over the reference; stall: less than a
             // 2x reduction over 100 sweeps
-            const bool diverged = !finite || (ref[grp] >= 0.0 && worst > 2.0 * ref[grp]);
+            const bool diverged = !finite || (ref[grp] >= 0.0 && worst > 2.0 * ref[grp]) || (rate < 0.0 && worst > 2.0 * worst0 && worst0 > 0.0);
             const bool stalled = ref[grp] >= 0.0 && done - ref_at[grp] >= 100 && worst > 0.5 * ref[grp];
             if (diverged || stalled || done >= s->P.solve_maxit) {
                 if (autom) {
@@ -550,24 +575,9 @@ hosc_status run_sor(hosc_solver *s, int mask, const double bn2[4], SolveOut &o, 
                 ref[grp] = worst;
                 ref_at[grp] = done;
             }
-            // next plan: from the contraction rate between the last two checks
             int next = std::max(2, std::min(done, 64));
-            if (last_res[grp] > 0.0 && worst > 0.0 && worst < last_res[grp]) {
-                const double rate = std::pow(worst / last_res[grp], 1.0 / (double)(done - last_at[grp]));
-                if (rate > 0.0 && rate < 1.0) {
-                    const double need = std::log(rtol / worst) / std::log(rate);
-                    next = (int)std::min(256.0, std::max(1.0, std::ceil(need) + 1.0));
-                    if (s->P.omega == 0.0 && done - last_at[grp] >= 4) {
-                        // past the optimum the contraction is about w - 1: back off
-                        const double w = s->om[grp];
-                        double wn = rate > 0.97 * (w - 1.0) && w > 1.05 ? w - 0.05 : young_omega(rate, w);
-                        wn = std::min(1.9, std::max(1.0, wn));
-                        s->om[grp] = w + 0.5 * (wn - w);
-                    }
-                }
-            }
-            last_res[grp] = worst;
-            last_at[grp] = done;
+            if (rate > 0.0 && rate < 1.0)
+                next = (int)std::min(256.0, std::max(2.0, std::ceil(std::log(rtol / worst) / std::log(rate)) + 1.0));
             plan[grp] = s->P.check_every > 0 ? s->P.check_every : next;
             plan[grp] = std::min(plan[grp], std::max(1, s->P.solve_maxit - done));
         }
@@ -718,8 +728,6 @@ hosc_status solve(hosc_solver *s, SolveOut &o)
     }
     hosc_status r = run_bicg(s, bicg_mask, bn2, o);
     if (r) return r;
-    s->last_sweeps[0] = o.sweeps[0];
-    s->last_sweeps[1] = o.sweeps[1];
     s->last_bicg[0] = o.bicg[0];
     s->last_bicg[1] = o.bicg[1];
     return HOSC_OK;
@@ -744,7 +752,7 @@ hosc_status one_step(hosc_solver *s, hosc_step_info *info)
                                                          s->Ep[1], s->Ep[2], ca, s->partR);
     r = timed_end(s, 1, assemble_bytes(s->g));
     if (r) return r;
-    k_reduce<<<1, 256, 0, s->st>>>(s->partR, (int)s->L.nb_int, 4, 0, s->red);
+    k_reduce<<<1, 1024, 0, s->st>>>(s->partR, (int)s->L.nb_int, 4, 0, s->red);
     r = launch_check(s, "assemble");
     if (r) return r;
     SolveOut so;
@@ -753,13 +761,13 @@ hosc_status one_step(hosc_solver *s, hosc_step_info *info)
     // update: u, v, w into the level n-1 buffers (which become level n+1)
     k_update<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, s->u, s->v, s->w, s->u2, s->v2, s->w2, s->T, s->md[0],
                                                        s->md[1], s->md[2], s->td, s->partR);
-    k_reduce<<<1, 256, 0, s->st>>>(s->partR, (int)s->L.nb_int, 8, 0, s->red + 12);
+    k_reduce<<<1, 1024, 0, s->st>>>(s->partR, (int)s->L.nb_int, 8, 0, s->red + 12);
     k_theta_walls<<<s->L.grd_face, s->L.blk_face, 0, s->st>>>(s->g, s->ph, s->T, s->partB);
-    k_reduce<<<1, 256, 0, s->st>>>(s->partB, (int)s->L.nb_face, 2, 0, s->red + 20);
+    k_reduce<<<1, 1024, 0, s->st>>>(s->partB, (int)s->L.nb_face, 2, 0, s->red + 20);
     const bool gate = s->P.div_tol > 0.0;
     k_divergence<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, s->ph, s->u2, s->v2, s->w2, s->p,
                                                            gate ? s->dbg : nullptr, gate ? 0 : 1, s->partR);
-    k_reduce<<<1, 256, 0, s->st>>>(s->partR, (int)s->L.nb_int, 1, 1, s->red + 22);
+    k_reduce<<<1, 1024, 0, s->st>>>(s->partR, (int)s->L.nb_int, 1, 1, s->red + 22);
     r = launch_check(s, "update/divergence");
     if (r) return r;
     HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red + 12, 11 * sizeof(double), hipMemcpyDeviceToHost, s->st));
@@ -1011,11 +1019,11 @@ hosc_status hosc_diagnostics(hosc_solver *s, hosc_diag *d, double *nuavg_hot, do
     const Geo &g = s->g;
     dim3 b2(16, 16), g2((g.N + 15) / 16, (g.N + 15) / 16);
     k_nu_local<<<g2, b2, 0, s->st>>>(g, s->T, s->nuh, s->nuc);
-    k_nu_avg<<<(g.N + 63) / 64, 64, 0, s->st>>>(g, s->wq, s->nuh, s->nuc, s->avh, s->avc);
-    k_nu_final<<<1, 64, 0, s->st>>>(g, s->wq, s->avh, s->avc, s->nuh, s->nuout);
+    k_nu_avg<<<g.N, 256, 0, s->st>>>(g, s->wq, s->nuh, s->nuc, s->avh, s->avc);
+    k_nu_final<<<1, 256, 0, s->st>>>(g, s->wq, s->avh, s->avc, s->nuh, s->nuout);
     k_entropy<<<s->L.grd_all, s->L.blk_all, 0, s->st>>>(g, s->ph, s->wq, s->u, s->v, s->w, s->T, nullptr, nullptr,
                                                          s->partR);
-    k_reduce<<<1, 256, 0, s->st>>>(s->partR, (int)s->L.nb_all, 3, 0, s->red + 24);
+    k_reduce<<<1, 1024, 0, s->st>>>(s->partR, (int)s->L.nb_all, 3, 0, s->red + 24);
     hosc_status r = launch_check(s, "diagnostics");
     if (r) return r;
     HIPCHK(s, hipMemcpyAsync(s->hbuf, s->nuout, 5 * sizeof(double), hipMemcpyDeviceToHost, s->st));
@@ -1100,6 +1108,7 @@ hosc_status hosc_perf_enable(hosc_solver *s, int32_t on)
         s->ev.resize(2 * kEvPairs);
         s->ev_bytes.resize(kEvPairs);
         s->ev_kind.resize(kEvPairs);
+        s->ev_count.resize(kEvPairs);
         for (auto &e : s->ev) HIPCHK(s, hipEventCreate(&e));
     }
     s->prof = on != 0;

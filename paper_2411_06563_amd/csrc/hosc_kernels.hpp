@@ -67,6 +67,29 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NV], double *out, un
     }
 }
 
+// Block sums stored to up to two places, each with its own component mask.
+template <int NV>
+__device__ __forceinline__ void block_sum_store2(double (&v)[NV], double *out1, unsigned m1, double *out2, unsigned m2)
+{
+    __shared__ double sh[NV][16];
+    const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+    const int nthr = blockDim.x * blockDim.y * blockDim.z;
+    const int lane = tid & 63, wave = tid >> 6, nwave = (nthr + 63) >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double x = v[q];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+        if (lane == 0) sh[q][wave] = x;
+    }
+    __syncthreads();
+    if (tid < NV) {
+        double s = 0.0;
+        for (int w = 0; w < nwave; ++w) s += sh[tid][w];
+        if ((m1 >> tid) & 1u) out1[tid] = s;
+        if ((m2 >> tid) & 1u) out2[tid] = s;
+    }
+}
+
 // max that propagates NaN
 __device__ __forceinline__ double nanmax(double a, double b) { return (a > b || a != a) ? a : b; }
 
@@ -91,19 +114,19 @@ __device__ __forceinline__ void block_max_store(double (&v)[NV], double *out)
     }
 }
 
-// Reduce nb partial records of nc values (record b at part[b*nc ...]) with one
-// block of 256 threads; op 0 = sum, 1 = max.  Fixed order: deterministic.
-__global__ void __launch_bounds__(256) k_reduce(const double *part, int nb, int nc, int op, double *out)
+// Reduce nb partial records of nc <= 8 values (record b at part[b*nc ...]) with one
+// block of 1024 threads; op 0 = sum, 1 = max.  Fixed order: deterministic.
+__global__ void __launch_bounds__(1024) k_reduce(const double *part, int nb, int nc, int op, double *out)
 {
-    __shared__ double sh[8][256];
+    __shared__ double sh[8][1024];
     const int t = threadIdx.x;
     for (int c = 0; c < nc; ++c) {
         double s = op == 0 ? 0.0 : -HUGE_VAL;
-        for (int b = t; b < nb; b += 256) s = op == 0 ? s + part[(size_t)b * nc + c] : nanmax(s, part[(size_t)b * nc + c]);
+        for (int b = t; b < nb; b += 1024) s = op == 0 ? s + part[(size_t)b * nc + c] : nanmax(s, part[(size_t)b * nc + c]);
         sh[c][t] = s;
     }
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = 512; w > 0; w >>= 1) {
         if (t < w)
             for (int c = 0; c < nc; ++c) sh[c][t] = op == 0 ? sh[c][t] + sh[c][t + w] : nanmax(sh[c][t], sh[c][t + w]);
         __syncthreads();
@@ -534,7 +557,8 @@ __device__ __forceinline__ TA theta_off(TA st, TA ax, TA ay, TA az, int j, int k
 // Red-black SOR half-sweep on the scaled rows (momentum: three right-hand sides
 // on one matrix; energy with the walls eliminated).  Per-block partial sums of
 // the squared scaled residuals r = b - B d at the updated nodes, before their
-// update, are stored for the systems in `store` (bit f = system f; none if 0).
+// update, are stored for the systems in `store` (bit f = system f) to `partial`, and
+// for the systems in `store0` to `partial0` (the first sweep of a batch).
 // ---------------------------------------------------------------------------
 template <typename TM>
 struct SweepArgs {
@@ -546,7 +570,8 @@ struct SweepArgs {
 
 template <typename TM, typename TA>
 __global__ void __launch_bounds__(256) k_sweep(Geo g, int colour, int mask, TA omega_m, TA omega_t, TA st,
-                                               SweepArgs<TM> a, double *__restrict__ partial, unsigned store)
+                                               SweepArgs<TM> a, double *__restrict__ partial, unsigned store,
+                                               double *__restrict__ partial0, unsigned store0)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y, k = 1 + blockIdx.z;
@@ -578,9 +603,9 @@ __global__ void __launch_bounds__(256) k_sweep(Geo g, int colour, int mask, TA o
             r2[3] = rr * rr;
         }
     }
-    if (store) {
+    if (store | store0) {
         const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-        block_sum_store<4>(r2, partial + (size_t)blk * 4, store);
+        block_sum_store2<4>(r2, partial + (size_t)blk * 4, store, partial0 + (size_t)blk * 4, store0);
     }
 }
 
@@ -905,35 +930,62 @@ __global__ void __launch_bounds__(256) k_nu_local(Geo g, const double *__restric
     nuc[j + (size_t)N * k] = -dc;
 }
 
-// Nu_avg(z_k) for both walls (one thread per k, sequential Simpson sum over j).
-__global__ void k_nu_avg(Geo g, const double *__restrict__ wq, const double *__restrict__ nuh,
-                         const double *__restrict__ nuc, double *__restrict__ avh, double *__restrict__ avc)
+// Nu_avg(z_k) for both walls: one block of 256 threads per k, fixed-order tree
+// over the Simpson-weighted values along y.
+__global__ void __launch_bounds__(256) k_nu_avg(Geo g, const double *__restrict__ wq, const double *__restrict__ nuh,
+                                                const double *__restrict__ nuc, double *__restrict__ avh,
+                                                double *__restrict__ avc)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= g.N) return;
-    double sh = 0.0, sc = 0.0;
-    for (int j = 0; j < g.N; ++j) {
-        sh += wq[j] * nuh[j + (size_t)g.N * k];
-        sc += wq[j] * nuc[j + (size_t)g.N * k];
+    __shared__ double sh[2][256];
+    const int k = blockIdx.x, t = threadIdx.x;
+    double a = 0.0, c = 0.0;
+    for (int j = t; j < g.N; j += 256) {
+        a += wq[j] * nuh[j + (size_t)g.N * k];
+        c += wq[j] * nuc[j + (size_t)g.N * k];
     }
-    avh[k] = sh;
-    avc[k] = sc;
+    sh[0][t] = a;
+    sh[1][t] = c;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            sh[0][t] += sh[0][t + w];
+            sh[1][t] += sh[1][t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        avh[k] = sh[0][0];
+        avc[k] = sh[1][0];
+    }
 }
 
-// mean over z, max over z, max of the local hot-wall Nu (single thread).
-__global__ void k_nu_final(Geo g, const double *__restrict__ wq, const double *__restrict__ avh,
-                           const double *__restrict__ avc, const double *__restrict__ nuh, double *__restrict__ out)
+// Means over z (Simpson), maxima over z of Nu_avg, and the max of the local
+// hot-wall Nu: one block of 256 threads, fixed-order trees.
+__global__ void __launch_bounds__(256) k_nu_final(Geo g, const double *__restrict__ wq, const double *__restrict__ avh,
+                                                  const double *__restrict__ avc, const double *__restrict__ nuh,
+                                                  double *__restrict__ out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double sh[5][256];
+    const int t = threadIdx.x;
     double mh = 0.0, mc = 0.0, xh = -HUGE_VAL, xc = -HUGE_VAL, xl = -HUGE_VAL;
-    for (int k = 0; k < g.N; ++k) {
+    for (int k = t; k < g.N; k += 256) {
         mh += wq[k] * avh[k];
         mc += wq[k] * avc[k];
         xh = nanmax(xh, avh[k]);
         xc = nanmax(xc, avc[k]);
     }
-    for (size_t q = 0; q < (size_t)g.N * g.N; ++q) xl = nanmax(xl, nuh[q]);
-    out[0] = mh; out[1] = mc; out[2] = xh; out[3] = xc; out[4] = xl;
+    for (size_t q = t; q < (size_t)g.N * g.N; q += 256) xl = nanmax(xl, nuh[q]);
+    sh[0][t] = mh; sh[1][t] = mc; sh[2][t] = xh; sh[3][t] = xc; sh[4][t] = xl;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            sh[0][t] += sh[0][t + w];
+            sh[1][t] += sh[1][t + w];
+            for (int c = 2; c < 5; ++c) sh[c][t] = nanmax(sh[c][t], sh[c][t + w]);
+        }
+        __syncthreads();
+    }
+    if (t < 5) out[t] = sh[t][0];
 }
 
 // Entropy generation (Sec. 4.3): E_HT = |grad theta|^2, E_FF = phi eta I2 with eta
