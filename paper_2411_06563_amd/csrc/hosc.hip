@@ -463,7 +463,7 @@ double young_omega(double lam, double w)
     return 2.0 / (1.0 + std::sqrt(1.0 - mu2));
 }
 
-hosc_status run_sor(hosc_solver *s, int mask, const double bn2[4], SolveOut &o, int *failed)
+hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *failed)
 {
     const double rtol = s->P.solve_rtol;
     const double ct = s->g.h2 / 12.0 - s->P.dt / 2.0;
@@ -480,6 +480,7 @@ hosc_status run_sor(hosc_solver *s, int mask, const double bn2[4], SolveOut &o, 
     int plan[2] = {0, 0};
     for (int grp = 0; grp < 2; ++grp)
         plan[grp] = s->P.check_every > 0 ? s->P.check_every : std::max(2, s->last_sweeps[grp] + 1);
+    const int first_plan[2] = {plan[0], plan[1]};
     while (active) {
         int nsw = 0;
         for (int grp = 0; grp < 2; ++grp)
@@ -514,6 +515,11 @@ hosc_status run_sor(hosc_solver *s, int mask, const double bn2[4], SolveOut &o, 
         HIPCHK(s, hipStreamSynchronize(s->st));
         r = harvest_events(s);
         if (r) return r;
+        if (bn2[0] < 0.0) {
+            for (int f = 0; f < 4; ++f) bn2[f] = s->hbuf[f];
+            for (int f = 0; f < 4; ++f)
+                if (!std::isfinite(bn2[f])) return fail(s, HOSC_E_NONFINITE, "non-finite right-hand side");
+        }
         for (int grp = 0; grp < 2; ++grp) {
             if (!(active & (1 << grp))) continue;
             o.sweeps[grp] += plan[grp];
@@ -549,8 +555,10 @@ hosc_status run_sor(hosc_solver *s, int mask, const double bn2[4], SolveOut &o, 
                         const size_t b = 2 * s->g.cs * sizeof(double);
                         HIPCHK(s, hipMemsetAsync(f < 3 ? s->md[f] : s->td, 0, b, s->st));
                     }
-                // sweeps that would have sufficed, for the next step's plan
-                int suff = done;
+                // sweeps that would have sufficed, for the next step's plan: from the
+                // measured rate when there is one; a first batch that converged
+                // without a usable rate halves the plan
+                int suff = done == first_plan[grp] ? std::max(1, done / 2) : done;
                 if (rate > 0.0 && rate < 1.0 && worst > 0.0)
                     suff = done - (int)std::floor(std::log(rtol / worst) / std::log(rate));
                 s->last_sweeps[grp] = std::max(1, std::min(done, suff));
@@ -616,9 +624,16 @@ hosc_status bicg_phase(hosc_solver *s, int phase, int mask, double st, const Bic
 
 // BiCGSTAB (the paper's solver) on the groups in `mask`, from the current
 // increments, until the true scaled residual meets the tolerance.
-hosc_status run_bicg(hosc_solver *s, int mask, const double bn2[4], SolveOut &o)
+hosc_status run_bicg(hosc_solver *s, int mask, double bn2[4], SolveOut &o)
 {
     if (!mask) return HOSC_OK;
+    if (bn2[0] < 0.0) {
+        HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red, 4 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+        HIPCHK(s, hipStreamSynchronize(s->st));
+        for (int f = 0; f < 4; ++f) bn2[f] = s->hbuf[f];
+        for (int f = 0; f < 4; ++f)
+            if (!std::isfinite(bn2[f])) return fail(s, HOSC_E_NONFINITE, "non-finite right-hand side");
+    }
     const double rtol = s->P.solve_rtol;
     const double ct = s->g.h2 / 12.0 - s->P.dt / 2.0;
     const double Ct = 1.0 - 6.0 * ct * s->g.invh2;
@@ -700,13 +715,9 @@ hosc_status run_bicg(hosc_solver *s, int mask, const double bn2[4], SolveOut &o)
 // Solve the momentum (3 right-hand sides) and energy systems of the step.
 hosc_status solve(hosc_solver *s, SolveOut &o)
 {
-    // ||b/C||^2 of the four systems (reduced after the assembly)
-    HIPCHK(s, hipMemcpyAsync(s->hbuf + 32, s->red, 4 * sizeof(double), hipMemcpyDeviceToHost, s->st));
-    HIPCHK(s, hipStreamSynchronize(s->st));
-    double bn2[4];
-    for (int f = 0; f < 4; ++f) bn2[f] = s->hbuf[32 + f];
-    for (int f = 0; f < 4; ++f)
-        if (!std::isfinite(bn2[f])) return fail(s, HOSC_E_NONFINITE, "non-finite right-hand side");
+    // ||b/C||^2 of the four systems (reduced after the assembly into red[0..3]) are
+    // read by the solvers together with their first convergence check
+    double bn2[4] = {-1.0, -1.0, -1.0, -1.0};
     int sor_mask = 0, bicg_mask = 0;
     for (int grp = 0; grp < 2; ++grp) {
         const bool use_bicg = s->P.solver == HOSC_SOLVER_BICGSTAB

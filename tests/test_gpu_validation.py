@@ -4,8 +4,8 @@ Pr = 0.71 on the paper's 51^3 grid (Sec. 3.2, Table 2; fixture in
 tests/golden/table2_max_nusselt.json).  The paper reports a deviation of at most
 0.99% from two benchmark solutions; its own time step, quadrature and steady-state
 test are not stated, so the bar is 2% of the printed value.  Each case is marched
-from the seeded initial state to a steady residual of 1e-8 at dt = 8e-5
-(dt/h^2 = 0.2)."""
+from the seeded initial state to a steady residual of 1e-8; in increment form the
+steady state does not depend on dt, so calmer flows use larger steps."""
 import json
 import os
 import sys
@@ -15,6 +15,9 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+DT = {1e3: 4e-4, 1e4: 2e-4, 1e5: 8e-5}
 
 
 def _cases():
@@ -28,10 +31,15 @@ def test_table2_max_nusselt(N, Pr, Ra, expected):
     import torch
     assert torch.cuda.is_available()
     from paper_2411_06563_amd import hosc
-    print(f"[table2] N={N} Pr={Pr} Ra={Ra:g}", flush=True)
-    s = hosc.Solver(hosc.params(N, Ra=Ra, n_pl=1.0, Pr=Pr, dt=8e-5, solve_rtol=1e-10))
+    dt = DT[Ra]
+    print(f"[table2] N={N} Pr={Pr} Ra={Ra:g} dt={dt}", flush=True)
+    s = hosc.Solver(hosc.params(N, Ra=Ra, n_pl=1.0, Pr=Pr, dt=dt, solve_rtol=1e-10))
     s.init_fields(1, 1e-3)
-    info = s.run_to_steady(1e-8, 60000)
+    for _ in range(40):
+        info = s.run_to_steady(1e-8, 1000)
+        print(f"[table2] step {info.step} res {max(info.res):.3e} sweeps {info.sweeps}", flush=True)
+        if max(info.res) < 1e-8:
+            break
     assert max(info.res) < 1e-8, info
     d = s.diagnostics(arrays=False)
     print(f"[table2] Ra={Ra:g}: steps {info.step}, max_z Nu_avg {d['nu_max_hot']:.4f} (paper {expected}), "
