@@ -115,7 +115,9 @@ def main():
         sweeps[1] += info.sweeps[1]
         sweeps[2] += info.bicg_iters[0]
         sweeps[3] += info.bicg_iters[1]
-        print(f"step {info.step}: sweeps {info.sweeps} bicg {info.bicg_iters} res {max(info.res):.3e}",
+        print(f"step {info.step}: sweeps {info.sweeps} bicg {info.bicg_iters} omega "
+              f"{info.omega[0]:.3f}/{info.omega[1]:.3f} dominance {info.dominance[0]:.3f}/{info.dominance[1]:.3f} "
+              f"res {max(info.res):.3e}",
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     el += time.perf_counter() - t0
@@ -156,6 +158,7 @@ def main():
                      "assemble_us": perf["assemble_ms"] * 1e3 / max(perf["assemble_launches"], 1)},
     }
     s.close()
+    out["roofline"]["copy_probe_GBs"] = hosc.copy_bandwidth(1 << 30, 10)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
     print(json.dumps(out), flush=True)

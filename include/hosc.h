@@ -100,6 +100,9 @@ typedef struct hosc_step_info {
     int64_t step;           /* steps taken since the state was set */
     int32_t sweeps[2];      /* red-black sweeps of the momentum and the energy solve (last step) */
     int32_t bicg_iters[2];  /* BiCGSTAB iterations of the momentum and the energy solve (last step) */
+    double omega[2];        /* SOR relaxation of the momentum and the energy sweeps after the last step */
+    double dominance[2];    /* max over rows of (sum |off-diagonal|) / |centre| of the momentum and energy
+                               matrices (> 1: a row is not diagonally dominant); 0 if not measured */
     int32_t corrected;      /* 1 if the pressure correction was applied */
     int32_t status;         /* hosc_status of the step */
 } hosc_step_info;
@@ -199,6 +202,14 @@ hosc_status hosc_perf_enable(hosc_solver *s, int32_t on);
 
 /* Counters accumulated since the last hosc_perf_enable(s, 1). */
 hosc_status hosc_perf_get(hosc_solver *s, hosc_perf *out);
+
+/* Achievable-bandwidth probe (measurement aid, not part of the method): copies
+ * `bytes` (multiple of 16, both device buffers 16-byte aligned, not overlapping)
+ * from d_src to d_dst `reps` times on `stream` with a plain 16-byte-per-lane copy
+ * kernel and returns the mean kernel time per copy (HIP events).  Each copy moves
+ * 2 * bytes through HBM (read + write). */
+hosc_status hosc_copy_bandwidth(const void *d_src, void *d_dst, size_t bytes, int32_t reps, hipStream_t stream,
+                                double *ms_per_copy);
 
 /* Message of the last failing call on the handle ("" if none; NULL handle: last
  * failing create). */

@@ -430,6 +430,7 @@ double bicg_bytes(const Geo &g, int phase, int mask)
 
 struct SolveOut {
     double relres[4] = {0, 0, 0, 0};
+    double dominance[2] = {0, 0};
     int sweeps[2] = {0, 0};
     int bicg[2] = {0, 0};
 };
@@ -479,8 +480,18 @@ hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *f
     int ref_at[2] = {0, 0};
     int plan[2] = {0, 0};
     for (int grp = 0; grp < 2; ++grp)
-        plan[grp] = s->P.check_every > 0 ? s->P.check_every : std::max(2, s->last_sweeps[grp] + 1);
+        plan[grp] = s->P.check_every > 0 ? s->P.check_every : std::max(2, s->last_sweeps[grp]);
     const int first_plan[2] = {plan[0], plan[1]};
+    if (adapt && s->step == 0) {
+        // first step after a state was set: seed the relaxation from the dominance
+        // monitor of the assembly, a Gershgorin bound mu on the Jacobi radius
+        HIPCHK(s, hipMemcpyAsync(s->hbuf + 44, s->red + 44, 2 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+        HIPCHK(s, hipStreamSynchronize(s->st));
+        for (int grp = 0; grp < 2; ++grp) {
+            const double mu = std::min(0.98, s->hbuf[44 + grp]);
+            if (mu > 0.0 && std::isfinite(mu)) s->om[grp] = 2.0 / (1.0 + std::sqrt(1.0 - mu * mu));
+        }
+    }
     while (active) {
         int nsw = 0;
         for (int grp = 0; grp < 2; ++grp)
@@ -511,10 +522,12 @@ hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *f
         k_reduce<<<1, 1024, 0, s->st>>>(s->partB, (int)s->L.nb_sw, 4, 0, s->red + 8);
         k_reduce<<<1, 1024, 0, s->st>>>(s->partR0, (int)s->L.nb_sw, 4, 0, s->red + 32);
         k_reduce<<<1, 1024, 0, s->st>>>(s->partB0, (int)s->L.nb_sw, 4, 0, s->red + 36);
-        HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red, 40 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+        HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red, 48 * sizeof(double), hipMemcpyDeviceToHost, s->st));
         HIPCHK(s, hipStreamSynchronize(s->st));
         r = harvest_events(s);
         if (r) return r;
+        o.dominance[0] = s->hbuf[44];
+        o.dominance[1] = s->hbuf[45];
         if (bn2[0] < 0.0) {
             for (int f = 0; f < 4; ++f) bn2[f] = s->hbuf[f];
             for (int f = 0; f < 4; ++f)
@@ -543,9 +556,10 @@ hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *f
             if (finite && plan[grp] > 1 && worst0 > 0.0 && worst > 0.0 && worst < worst0)
                 rate = std::pow(worst / worst0, 1.0 / (double)(plan[grp] - 1));
             if (adapt && rate > 0.0 && rate < 1.0 && plan[grp] >= 4) {
-                // past the optimum the contraction is about w - 1: back off
+                // below the optimum the contraction exceeds w - 1 and Young's relation
+                // gives the optimum; at or past it the contraction is about w - 1: back off
                 const double w = s->om[grp];
-                double wn = rate > 0.97 * (w - 1.0) && w > 1.05 ? w - 0.05 : young_omega(rate, w);
+                double wn = (w > 1.05 && rate < (w - 1.0) + 0.02) ? w - 0.03 : young_omega(rate, w);
                 wn = std::min(1.9, std::max(1.0, wn));
                 s->om[grp] = w + 0.5 * (wn - w);
             }
@@ -559,8 +573,8 @@ hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *f
                 // measured rate when there is one; a first batch that converged
                 // without a usable rate halves the plan
                 int suff = done == first_plan[grp] ? std::max(1, done / 2) : done;
-                if (rate > 0.0 && rate < 1.0 && worst > 0.0)
-                    suff = done - (int)std::floor(std::log(rtol / worst) / std::log(rate));
+                if (rate > 0.0 && rate < 1.0 && worst > 0.0)    // r_done / r_needed = rate^(done - needed)
+                    suff = done - (int)std::floor(std::log(worst / rtol) / std::log(rate));
                 s->last_sweeps[grp] = std::max(1, std::min(done, suff));
                 active &= ~(1 << grp);
                 continue;
@@ -760,10 +774,11 @@ hosc_status one_step(hosc_solver *s, hosc_step_info *info)
     if (r) return r;
     k_assemble<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, s->ph, s->u, s->v, s->w, s->T, s->eta, s->E[0],
                                                          s->E[1], s->E[2], s->u2, s->v2, s->w2, s->etap, s->Ep[0],
-                                                         s->Ep[1], s->Ep[2], ca, s->partR);
+                                                         s->Ep[1], s->Ep[2], ca, s->partR, s->partB);
     r = timed_end(s, 1, assemble_bytes(s->g));
     if (r) return r;
     k_reduce<<<1, 1024, 0, s->st>>>(s->partR, (int)s->L.nb_int, 4, 0, s->red);
+    k_reduce<<<1, 1024, 0, s->st>>>(s->partB, (int)s->L.nb_int, 2, 1, s->red + 44);
     r = launch_check(s, "assemble");
     if (r) return r;
     SolveOut so;
@@ -825,6 +840,10 @@ hosc_status one_step(hosc_solver *s, hosc_step_info *info)
         info->sweeps[1] = so.sweeps[1];
         info->bicg_iters[0] = so.bicg[0];
         info->bicg_iters[1] = so.bicg[1];
+        info->omega[0] = s->om[0];
+        info->omega[1] = s->om[1];
+        info->dominance[0] = so.dominance[0];
+        info->dominance[1] = so.dominance[1];
         info->corrected = corrected;
         info->status = finite ? HOSC_OK : HOSC_E_NONFINITE;
     }
@@ -1134,6 +1153,34 @@ hosc_status hosc_perf_get(hosc_solver *s, hosc_perf *out)
     hosc_status r = harvest_events(s);
     if (r) return r;
     *out = s->perf;
+    return HOSC_OK;
+}
+
+hosc_status hosc_copy_bandwidth(const void *d_src, void *d_dst, size_t bytes, int32_t reps, hipStream_t stream,
+                                double *ms_per_copy)
+{
+    if (!d_src || !d_dst || !ms_per_copy || reps < 1) return fail(nullptr, HOSC_E_ARG, "invalid copy arguments");
+    if (bytes % 16 || reinterpret_cast<uintptr_t>(d_src) % 16 || reinterpret_cast<uintptr_t>(d_dst) % 16)
+        return fail(nullptr, HOSC_E_ARG, "copy buffers and size must be 16-byte aligned");
+    const size_t n = bytes / 16;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(nullptr, HOSC_E_DEVICE, "hipEventCreate failed");
+    const int blocks = 256 * 8;    // 8 workgroups of 256 threads per compute unit
+    const double2 *src = static_cast<const double2 *>(d_src);
+    double2 *dst = static_cast<double2 *>(d_dst);
+    k_copy<<<blocks, 256, 0, stream>>>(src, dst, n);    // warm-up
+    hipError_t e = hipEventRecord(e0, stream);
+    for (int q = 0; q < reps && e == hipSuccess; ++q) k_copy<<<blocks, 256, 0, stream>>>(src, dst, n);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventRecord(e1, stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(nullptr, HOSC_E_DEVICE, std::string("copy probe: ") + hipGetErrorString(e));
+    *ms_per_copy = ms / reps;
     return HOSC_OK;
 }
 

@@ -426,11 +426,13 @@ __global__ void __launch_bounds__(256) k_assemble(Geo g, Phys P, const double *_
                                                   const double *__restrict__ vp, const double *__restrict__ wp,
                                                   const double *__restrict__ etap, const double *__restrict__ Eup,
                                                   const double *__restrict__ Evp, const double *__restrict__ Ewp,
-                                                  ColourArrays ca, double *__restrict__ partial)
+                                                  ColourArrays ca, double *__restrict__ partial,
+                                                  double *__restrict__ partial_dom)
 {
     const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x, j = 1 + blockIdx.y * blockDim.y + threadIdx.y,
               k = 1 + blockIdx.z;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double dom[2] = {0.0, 0.0};     // off-diagonal sum / |centre| of the momentum and energy rows
     if (i <= g.N - 2 && j <= g.N - 2) {
         NodeAssembly a;
         assemble_node(g, P, i, j, k, u, v, w, T, eta, Eu, Ev, Ew, up, vp, wp, etap, Eup, Evp, Ewp, a);
@@ -448,9 +450,18 @@ __global__ void __launch_bounds__(256) k_assemble(Geo g, Phys P, const double *_
         const double bt = a.b[3] * rt;
         ca.tb[idx] = bt;
         acc[3] = bt * bt;
+        double om = 0.0, ot = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            om += fabs(a.sm - a.am[d]) + fabs(a.sm + a.am[d]);
+            ot += fabs(a.st - a.at[d]) + fabs(a.st + a.at[d]);
+        }
+        dom[0] = om / fabs(a.Cm);
+        dom[1] = ot / fabs(a.Ct);
     }
     const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
     block_sum_store<4>(acc, partial + (size_t)blk * 4);
+    block_max_store<2>(dom, partial_dom + (size_t)blk * 2);
 }
 
 // Parity hook: one selected assembled quantity, unscaled, in the natural layout:
@@ -1019,6 +1030,14 @@ __global__ void __launch_bounds__(256) k_entropy(Geo g, Phys P, const double *__
     }
     const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
     block_sum_store<3>(acc, partial + (size_t)blk * 3);
+}
+
+// STREAM-style copy (16-byte accesses, grid-stride): measures the achievable
+// HBM bandwidth and calibrates hardware traffic counters against known bytes.
+__global__ void __launch_bounds__(256) k_copy(const double2 *__restrict__ src, double2 *__restrict__ dst, size_t n)
+{
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x)
+        dst[q] = src[q];
 }
 
 }  // namespace hosc

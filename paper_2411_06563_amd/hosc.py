@@ -48,7 +48,7 @@ class CParams(ctypes.Structure):
 class CStepInfo(ctypes.Structure):
     _fields_ = [("res", ctypes.c_double * 4), ("relres", ctypes.c_double * 4), ("maxdiv", ctypes.c_double),
                 ("step", ctypes.c_int64), ("sweeps", ctypes.c_int32 * 2), ("bicg_iters", ctypes.c_int32 * 2),
-                ("corrected", ctypes.c_int32),
+                ("omega", ctypes.c_double * 2), ("dominance", ctypes.c_double * 2), ("corrected", ctypes.c_int32),
                 ("status", ctypes.c_int32)]
 
 
@@ -98,6 +98,7 @@ def lib() -> ctypes.CDLL:
     L.hosc_debug_assemble.argtypes = [vp, _dp, _dp, _dp, _dp, _dp]
     L.hosc_perf_enable.argtypes = [vp, ctypes.c_int32]
     L.hosc_perf_get.argtypes = [vp, ctypes.POINTER(CPerf)]
+    L.hosc_copy_bandwidth.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_double)]
     L.hosc_last_error.argtypes = [vp]
     L.hosc_last_error.restype = ctypes.c_char_p
     L.hosc_status_string.argtypes = [ctypes.c_int]
@@ -138,6 +139,20 @@ def workspace_bytes(p: CParams) -> int:
     return n.value
 
 
+def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 10, device: str = "cuda:0") -> float:
+    """Achievable HBM bandwidth (GB/s, read + write) of a plain copy kernel."""
+    import torch
+    with torch.cuda.device(torch.device(device)):
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device=device)
+        dst = torch.empty_like(src)
+        ms = ctypes.c_double(0.0)
+        st = torch.cuda.current_stream().cuda_stream
+        _check(lib().hosc_copy_bandwidth(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nbytes,
+                                         reps, ctypes.c_void_p(st), ctypes.byref(ms)))
+        torch.cuda.synchronize()
+    return 2.0 * nbytes / (ms.value * 1e-3) / 1e9
+
+
 @dataclass
 class StepInfo:
     res: list
@@ -146,13 +161,15 @@ class StepInfo:
     step: int
     sweeps: list
     bicg_iters: list
+    omega: list
+    dominance: list
     corrected: int
     status: int
 
     @classmethod
     def of(cls, c: CStepInfo):
-        return cls(list(c.res), list(c.relres), c.maxdiv, c.step, list(c.sweeps), list(c.bicg_iters), c.corrected,
-                   c.status)
+        return cls(list(c.res), list(c.relres), c.maxdiv, c.step, list(c.sweeps), list(c.bicg_iters), list(c.omega),
+                   list(c.dominance), c.corrected, c.status)
 
 
 class Solver:
