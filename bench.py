@@ -19,6 +19,7 @@ host cores on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -28,9 +29,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM traffic of one k_sweep launch on this workload from FETCH_SIZE / WRITE_SIZE
+# (two rocprofv3 --pmc passes, calibrated against the copy probe), valid for the
+# kernel source with this sha256 prefix; any other source reports null.
+SWEEP_TRAFFIC = {"kernels_sha256_16": "ffbd488779661b3e", "bytes_per_launch": 1.7281e8}
 METRIC = "cell-updates/s + HBM roofline % at 129^3; served solves/s, p50/p99 latency"
 WORKLOAD = dict(N=129, Ra=1e5, n_pl=0.75, Pr=1.0, dt=5e-5, seed=2, noise=1e-3, solve_rtol=1e-10)
 SEGMENT = 12
+
+
+def sweep_traffic():
+    path = os.path.join(ROOT, "paper_2411_06563_amd", "csrc", "hosc_kernels.hpp")
+    with open(path, "rb") as f:
+        h = hashlib.sha256(f.read()).hexdigest()[:16]
+    return SWEEP_TRAFFIC["bytes_per_launch"] if h == SWEEP_TRAFFIC["kernels_sha256_16"] else None
 
 
 def cpu_baseline(budget_s: float = 20.0) -> dict:
@@ -150,7 +162,8 @@ def main():
                    "mean_sor_sweeps_per_step": [sweeps[0] / args.steps, sweeps[1] / args.steps],
                    "mean_bicgstab_iters_per_step": [sweeps[2] / args.steps, sweeps[3] / args.steps]},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": sweep_traffic() if kind == "sweep" else None,
                      "avg_launch_us": avg_ms * 1e3, "launches": perf[f"{kind}_launches"],
                      "bytes_per_launch": avg_bytes,
                      "kernel_time_frac": perf[f"{kind}_ms"] * 1e-3 / el,
