@@ -34,7 +34,16 @@ HBM_PEAK_GBS = 8000.0
 # kernel source with this sha256 prefix; any other source reports null.
 SWEEP_TRAFFIC = {"kernels_sha256_16": "ffbd488779661b3e", "bytes_per_launch": 1.7281e8}
 METRIC = "cell-updates/s + HBM roofline % at 129^3; served solves/s, p50/p99 latency"
-WORKLOAD = dict(N=129, Ra=1e5, n_pl=0.75, Pr=1.0, dt=5e-5, seed=2, noise=1e-3, solve_rtol=1e-10)
+WORKLOADS = {
+    # the benchmark workload: FP64, shear-thinning, Ra = 1e5
+    "fp64": dict(N=129, Ra=1e5, n_pl=0.75, Pr=1.0, dt=5e-5, seed=2, noise=1e-3, solve_rtol=1e-10, precision=0,
+                 label="HOSC cavity 129^3, n=0.75, Ra=1e5, Pr=1, dt=5e-5, FP64, rtol 1e-10, seed 2"),
+    # precision form: shear-thickening, Ra = 1e4, FP32 rows and sweeps with FP64 refinement
+    "fp32r": dict(N=129, Ra=1e4, n_pl=1.25, Pr=1.0, dt=5e-5, seed=3, noise=1e-3, solve_rtol=1e-10, precision=1,
+                  label="HOSC cavity 129^3, n=1.25, Ra=1e4, Pr=1, dt=5e-5, FP32 rows/sweeps + FP64 refinement, "
+                        "rtol 1e-10, seed 3"),
+}
+WORKLOAD = WORKLOADS["fp64"]
 SEGMENT = 12
 
 
@@ -77,6 +86,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--omega", type=float, default=None)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="fp64")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build measures the single-cavity hot path on one MI355X "
@@ -87,8 +97,9 @@ def main():
     from paper_2411_06563_amd import hosc
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    W = WORKLOAD
-    kw = dict(Ra=W["Ra"], n_pl=W["n_pl"], Pr=W["Pr"], dt=W["dt"], solve_rtol=W["solve_rtol"])
+    W = WORKLOADS[args.workload]
+    kw = dict(Ra=W["Ra"], n_pl=W["n_pl"], Pr=W["Pr"], dt=W["dt"], solve_rtol=W["solve_rtol"],
+              precision=W["precision"])
     if args.omega is not None:
         kw["omega"] = args.omega
     s = hosc.Solver(hosc.params(W["N"], **kw), device="cuda:0")
@@ -154,25 +165,26 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if W["precision"] == 0 else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"HOSC cavity 129^3, n=0.75, Ra=1e5, Pr=1, dt=5e-5, FP64, rtol 1e-10, seed 2; "
-                               f"steps 1-{args.segment} from the seeded initial state, repeated",
-                   "grid": W["N"], "interior_nodes": M3, "precision": "fp64", "segment_steps": args.segment,
+        "config": {"workload": f"{W['label']}; steps 1-{args.segment} from the seeded initial state, repeated",
+                   "grid": W["N"], "interior_nodes": M3, "precision": args.workload, "segment_steps": args.segment,
                    "mean_sor_sweeps_per_step": [sweeps[0] / args.steps, sweeps[1] / args.steps],
                    "mean_bicgstab_iters_per_step": [sweeps[2] / args.steps, sweeps[3] / args.steps]},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": sweep_traffic() if kind == "sweep" else None,
+                     "traffic": sweep_traffic() if kind == "sweep" and args.workload == "fp64" else None,
                      "avg_launch_us": avg_ms * 1e3, "launches": perf[f"{kind}_launches"],
                      "bytes_per_launch": avg_bytes,
                      "kernel_time_frac": perf[f"{kind}_ms"] * 1e-3 / el,
                      "assemble_GBs": (perf["assemble_bytes"] / max(perf["assemble_ms"], 1e-12) / 1e6),
-                     "assemble_us": perf["assemble_ms"] * 1e3 / max(perf["assemble_launches"], 1)},
+                     "assemble_us": perf["assemble_ms"] * 1e3 / max(perf["assemble_launches"], 1),
+                     "refine_us": perf["refine_ms"] * 1e3 / max(perf["refine_launches"], 1),
+                     "refine_time_frac": perf["refine_ms"] * 1e-3 / el},
     }
     s.close()
     out["roofline"]["copy_probe_GBs"] = hosc.copy_bandwidth(1 << 30, 10)
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "fp64":
         out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
     print(json.dumps(out), flush=True)
 

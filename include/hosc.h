@@ -135,6 +135,9 @@ typedef struct hosc_perf {
     int64_t bicg_launches;      /* BiCGSTAB vector-phase launches (matrix-vector products and updates) */
     double bicg_ms;
     double bicg_bytes;          /* per launch: rows of the active systems once, each vector read or written once */
+    int64_t refine_launches;    /* precision mode: FP64 refinement-residual launches (one colour each) */
+    double refine_ms;
+    double refine_bytes;
 } hosc_perf;
 
 typedef struct hosc_solver hosc_solver;

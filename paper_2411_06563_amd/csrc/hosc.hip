@@ -44,6 +44,7 @@ struct Layout {
     size_t natural_arrays = 17;   // u v w T p u2 v2 w2 eta etap E3 Ep3 dbg
     size_t colour_arrays = 15;    // ms ma3 mb3 md3 ta3 tb td (each 2 colours)
     size_t bicg_arrays = 0;       // r rh p pn v vn t for 4 systems (BiCGSTAB enabled)
+    size_t fp32_arrays = 0;       // precision mode: FP32 residuals and corrections of 4 systems
     size_t partial;               // partial-sum records
     size_t total_bytes;
 };
@@ -87,9 +88,10 @@ Launch make_launch(const Geo &g)
     return L;
 }
 
-Layout make_layout(const Geo &g, const Launch &L, int solver)
+Layout make_layout(const Geo &g, const Launch &L, int solver, int precision)
 {
     Layout y;
+    y.fp32_arrays = precision == HOSC_FP32_REFINED ? 8 : 0;
     y.n3 = g.n3;
     y.cs = g.cs;
     y.bicg_arrays = solver == HOSC_SOLVER_SOR ? 0 : 28;
@@ -98,6 +100,7 @@ Layout make_layout(const Geo &g, const Launch &L, int solver)
     size_t b = 0;
     b += y.natural_arrays * align_up(g.n3 * sizeof(double));
     b += (y.colour_arrays + y.bicg_arrays) * align_up(2 * g.cs * sizeof(double));
+    b += y.fp32_arrays * align_up(2 * g.cs * sizeof(float));
     b += 4 * align_up(recs * sizeof(double));                 // partial buffers: red / black half, last and first sweep
     b += align_up(kRed * sizeof(double));                      // reduction outputs
     b += align_up((size_t)g.N * sizeof(double));               // Simpson weights
@@ -186,6 +189,11 @@ struct hosc_solver {
     double *br[4], *brh[4], *bp[4], *bpn[4], *bv[4], *bvn[4], *bt[4];
     double *bsc;
     int64_t bicg_until[2] = {-1, -1};   // auto mode: use BiCGSTAB for the group until this step
+    // precision mode: rows stored in FP32 (in the row arrays above), FP32 residuals
+    // and corrections of the inner solves
+    bool fp32 = false;
+    float *fms = nullptr, *fma[3] = {nullptr, nullptr, nullptr}, *fta[3] = {nullptr, nullptr, nullptr};
+    float *fr[4] = {nullptr, nullptr, nullptr, nullptr}, *fe[4] = {nullptr, nullptr, nullptr, nullptr};
     double *hbuf = nullptr;   // pinned host staging for scalars
     int64_t step = 0;
     bool first = true;
@@ -265,6 +273,17 @@ void carve(hosc_solver *s, char *base)
     s->nuout = take(align_up(8 * sizeof(double)));
     s->bsc = take(align_up(32 * sizeof(double)));
     for (int f = 0; f < 4; ++f) s->br[f] = s->brh[f] = s->bp[f] = s->bpn[f] = s->bv[f] = s->bvn[f] = s->bt[f] = nullptr;
+    s->fp32 = s->Y.fp32_arrays > 0;
+    if (s->fp32) {
+        s->fms = reinterpret_cast<float *>(s->ms);
+        for (int d = 0; d < 3; ++d) {
+            s->fma[d] = reinterpret_cast<float *>(s->ma[d]);
+            s->fta[d] = reinterpret_cast<float *>(s->ta[d]);
+        }
+        const size_t fcol = align_up(2 * s->g.cs * sizeof(float));
+        for (int f = 0; f < 4; ++f) s->fr[f] = reinterpret_cast<float *>(take(fcol));
+        for (int f = 0; f < 4; ++f) s->fe[f] = reinterpret_cast<float *>(take(fcol));
+    }
     if (s->Y.bicg_arrays)
         for (int f = 0; f < 4; ++f) {
             s->br[f] = take(col); s->brh[f] = take(col); s->bp[f] = take(col); s->bpn[f] = take(col);
@@ -275,12 +294,24 @@ void carve(hosc_solver *s, char *base)
 constexpr int kEvPairs = 512;
 
 // Algorithmic bytes of one half-sweep launch (see hosc_perf in hosc.h).
-double sweep_bytes(const Geo &g, int mask)
+double sweep_bytes(const Geo &g, int mask, size_t elem = sizeof(double))
 {
     const double nodes = 0.5 * (double)(g.N - 2) * (g.N - 2) * (g.N - 2);
     double per = 0.0;
-    if (mask & 1) per += (7 + 3 + 3 + 3) * sizeof(double);   // row 7, own 3 read + 3 write, other colour 3
-    if (mask & 2) per += (4 + 1 + 1 + 1) * sizeof(double);   // row 4, own 1 + 1, other colour 1
+    if (mask & 1) per += (7 + 3 + 3 + 3) * elem;   // row 4 + rhs 3, own 3 read + 3 write, other colour 3
+    if (mask & 2) per += (4 + 1 + 1 + 1) * elem;   // row 3 + rhs 1, own 1 + 1, other colour 1
+    return nodes * per;
+}
+
+// Algorithmic bytes of one refinement-residual launch (one colour): FP32 rows,
+// FP64 right-hand side, FP64 increment read + written, FP32 correction read + zeroed,
+// FP32 residual written, and the other colour's increment and correction read once.
+double refine_bytes(const Geo &g, int mask)
+{
+    const double nodes = 0.5 * (double)(g.N - 2) * (g.N - 2) * (g.N - 2);
+    double per = 0.0;
+    if (mask & 1) per += 4 * 4 + 3 * (8 + 8 + 8 + 4 + 4 + 4 + 8 + 4);
+    if (mask & 2) per += 3 * 4 + (8 + 8 + 8 + 4 + 4 + 4 + 8 + 4);
     return nodes * per;
 }
 
@@ -306,10 +337,14 @@ hosc_status harvest_events(hosc_solver *s)
             s->perf.assemble_launches += 1;
             s->perf.assemble_ms += ms;
             s->perf.assemble_bytes += s->ev_bytes[q];
-        } else {
-            s->perf.bicg_launches += 1;
+        } else if (s->ev_kind[q] == 2) {
+            s->perf.bicg_launches += s->ev_count[q];
             s->perf.bicg_ms += ms;
             s->perf.bicg_bytes += s->ev_bytes[q];
+        } else {
+            s->perf.refine_launches += s->ev_count[q];
+            s->perf.refine_ms += ms;
+            s->perf.refine_bytes += s->ev_bytes[q];
         }
     }
     s->ev_used = 0;
@@ -350,6 +385,11 @@ hosc_status zero_colour_increments(hosc_solver *s)
         for (int f = 0; f < 4; ++f) {
             double *v[7] = {s->br[f], s->brh[f], s->bp[f], s->bpn[f], s->bv[f], s->bvn[f], s->bt[f]};
             for (double *x : v) HIPCHK(s, hipMemsetAsync(x, 0, b, s->st));
+        }
+    if (s->fp32)
+        for (int f = 0; f < 4; ++f) {
+            HIPCHK(s, hipMemsetAsync(s->fr[f], 0, 2 * s->g.cs * sizeof(float), s->st));
+            HIPCHK(s, hipMemsetAsync(s->fe[f], 0, 2 * s->g.cs * sizeof(float), s->st));
         }
     return HOSC_OK;
 }
@@ -400,6 +440,7 @@ hosc_status stage_sources(hosc_solver *s, bool consume_first)
     return HOSC_OK;
 }
 
+// FP64 solve: the rows, right-hand sides and increments of the step
 SweepArgs<double> sweep_args(hosc_solver *s)
 {
     SweepArgs<double> a;
@@ -412,6 +453,22 @@ SweepArgs<double> sweep_args(hosc_solver *s)
     }
     a.tb = s->tb;
     a.td = s->td;
+    return a;
+}
+
+// FP32 inner solve of the precision mode: FP32 rows, residuals and corrections
+SweepArgs<float> sweep_args_fp32(hosc_solver *s)
+{
+    SweepArgs<float> a;
+    a.ms = s->fms;
+    for (int d = 0; d < 3; ++d) {
+        a.ma[d] = s->fma[d];
+        a.mb[d] = s->fr[d];
+        a.md[d] = s->fe[d];
+        a.ta[d] = s->fta[d];
+    }
+    a.tb = s->fr[3];
+    a.td = s->fe[3];
     return a;
 }
 
@@ -464,16 +521,15 @@ double young_omega(double lam, double w)
     return 2.0 / (1.0 + std::sqrt(1.0 - mu2));
 }
 
-hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *failed)
+template <typename TM>
+hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *failed, SweepArgs<TM> a, double rtol)
 {
-    const double rtol = s->P.solve_rtol;
     const double ct = s->g.h2 / 12.0 - s->P.dt / 2.0;
     const double Ct = 1.0 - 6.0 * ct * s->g.invh2;
     const double st = (ct * s->g.invh2) / Ct;
     const bool autom = s->P.solver == HOSC_SOLVER_AUTO;
     const bool adapt = s->P.omega == 0.0;
     static const unsigned kStore[2] = {0x7u, 0x8u};   // residual components of each group
-    SweepArgs<double> a = sweep_args(s);
     int active = mask;
     *failed = 0;
     double ref[2] = {-1.0, -1.0};
@@ -508,10 +564,10 @@ hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *f
                 if (q == plan[grp] - 1) store |= kStore[grp];
                 if (q == 0 && plan[grp] > 1) store0 |= kStore[grp];
             }
-            bytes += 2.0 * sweep_bytes(s->g, m);
+            bytes += 2.0 * sweep_bytes(s->g, m, sizeof(TM));
             for (int colour = 0; colour < 2; ++colour)
-                k_sweep<double, double><<<s->L.grd_sw, s->L.blk_sw, 0, s->st>>>(
-                    s->g, colour, m, s->om[0], s->om[1], st, a, colour ? s->partB : s->partR, store,
+                k_sweep<TM, TM><<<s->L.grd_sw, s->L.blk_sw, 0, s->st>>>(
+                    s->g, colour, m, (TM)s->om[0], (TM)s->om[1], (TM)st, a, colour ? s->partB : s->partR, store,
                     colour ? s->partB0 : s->partR0, store0);
         }
         r = timed_end(s, 0, bytes, 2 * nsw);
@@ -566,8 +622,8 @@ hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *f
             if (finite && conv) {
                 for (int f = f0; f < f1; ++f)
                     if (bn2[f] == 0.0) {
-                        const size_t b = 2 * s->g.cs * sizeof(double);
-                        HIPCHK(s, hipMemsetAsync(f < 3 ? s->md[f] : s->td, 0, b, s->st));
+                        const size_t b = 2 * s->g.cs * sizeof(TM);
+                        HIPCHK(s, hipMemsetAsync(f < 3 ? a.md[f] : a.td, 0, b, s->st));
                     }
                 // sweeps that would have sufficed, for the next step's plan: from the
                 // measured rate when there is one; a first batch that converged
@@ -607,14 +663,15 @@ hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *f
     return HOSC_OK;
 }
 
-BicgArgs<double> bicg_args(hosc_solver *s)
+template <typename TR>
+BicgArgs<TR, double> bicg_args(hosc_solver *s, const TR *ms, const TR *const ma[3], const TR *const ta[3])
 {
-    BicgArgs<double> a;
-    a.ms = s->ms;
+    BicgArgs<TR, double> a;
+    a.ms = ms;
     for (int d = 0; d < 3; ++d) {
-        a.ma[d] = s->ma[d];
+        a.ma[d] = ma[d];
         a.mb[d] = s->mb[d];
-        a.ta[d] = s->ta[d];
+        a.ta[d] = ta[d];
     }
     a.tb = s->tb;
     for (int f = 0; f < 4; ++f) {
@@ -625,11 +682,12 @@ BicgArgs<double> bicg_args(hosc_solver *s)
     return a;
 }
 
-hosc_status bicg_phase(hosc_solver *s, int phase, int mask, double st, const BicgArgs<double> &a)
+template <typename TR>
+hosc_status bicg_phase(hosc_solver *s, int phase, int mask, double st, const BicgArgs<TR, double> &a)
 {
     hosc_status r = timed_begin(s);
     if (r) return r;
-    k_bicg<double, double><<<s->L.grd_bc, s->L.blk_sw, 0, s->st>>>(s->g, phase, mask, st, a, s->bsc, s->partR);
+    k_bicg<TR, double, double><<<s->L.grd_bc, s->L.blk_sw, 0, s->st>>>(s->g, phase, mask, st, a, s->bsc, s->partR);
     r = timed_end(s, 2, bicg_bytes(s->g, phase, mask));
     if (r) return r;
     k_bicg_scalars<<<1, 256, 0, s->st>>>(phase, mask, s->partR, (int)s->L.nb_bc, s->bsc);
@@ -638,7 +696,8 @@ hosc_status bicg_phase(hosc_solver *s, int phase, int mask, double st, const Bic
 
 // BiCGSTAB (the paper's solver) on the groups in `mask`, from the current
 // increments, until the true scaled residual meets the tolerance.
-hosc_status run_bicg(hosc_solver *s, int mask, double bn2[4], SolveOut &o)
+template <typename TR>
+hosc_status run_bicg(hosc_solver *s, int mask, double bn2[4], SolveOut &o, BicgArgs<TR, double> a)
 {
     if (!mask) return HOSC_OK;
     if (bn2[0] < 0.0) {
@@ -652,7 +711,6 @@ hosc_status run_bicg(hosc_solver *s, int mask, double bn2[4], SolveOut &o)
     const double ct = s->g.h2 / 12.0 - s->P.dt / 2.0;
     const double Ct = 1.0 - 6.0 * ct * s->g.invh2;
     const double st = (ct * s->g.invh2) / Ct;
-    BicgArgs<double> a = bicg_args(s);
     int active = mask;
     for (int grp = 0; grp < 2; ++grp) {     // groups with b = 0 have the zero solution
         if (!(active & (1 << grp))) continue;
@@ -727,6 +785,99 @@ hosc_status run_bicg(hosc_solver *s, int mask, double bn2[4], SolveOut &o)
 }
 
 // Solve the momentum (3 right-hand sides) and energy systems of the step.
+// Precision mode: iterative refinement.  Each outer pass folds the FP32 correction
+// into the FP64 increment and forms the FP64 residual of the scaled rows (one
+// launch per colour); converged groups stop, the others solve B e = r for the FP32
+// correction with FP32 red-black sweeps to a relative 1e-5 or what the tolerance
+// still needs.  Groups whose inner solve fails (auto mode) are returned in *to_bicg.
+hosc_status solve_refined(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *to_bicg)
+{
+    const double rtol = s->P.solve_rtol;
+    const double ct = s->g.h2 / 12.0 - s->P.dt / 2.0;
+    const double Ct = 1.0 - 6.0 * ct * s->g.invh2;
+    const double st = (ct * s->g.invh2) / Ct;
+    RefineArgs<float> ra;
+    ra.ms = s->fms;
+    for (int d = 0; d < 3; ++d) {
+        ra.ma[d] = s->fma[d];
+        ra.ta[d] = s->fta[d];
+        ra.b[d] = s->mb[d];
+        ra.d[d] = s->md[d];
+    }
+    ra.b[3] = s->tb;
+    ra.d[3] = s->td;
+    for (int f = 0; f < 4; ++f) {
+        ra.e[f] = s->fe[f];
+        ra.r[f] = s->fr[f];
+    }
+    int active = mask;
+    *to_bicg = 0;
+    for (int outer = 0; active; ++outer) {
+        if (outer > 50) return fail(s, HOSC_E_NOCONV, "iterative refinement did not converge in 50 passes");
+        hosc_status r = timed_begin(s);
+        if (r) return r;
+        for (int colour = 0; colour < 2; ++colour)
+            k_refine_residual<float><<<s->L.grd_sw, s->L.blk_sw, 0, s->st>>>(s->g, colour, active, st, ra,
+                                                                            colour ? s->partB : s->partR);
+        r = timed_end(s, 3, 2.0 * refine_bytes(s->g, active), 2);
+        if (r) return r;
+        r = launch_check(s, "refine residual");
+        if (r) return r;
+        k_reduce<<<1, 1024, 0, s->st>>>(s->partR, (int)s->L.nb_sw, 4, 0, s->red + 48);
+        k_reduce<<<1, 1024, 0, s->st>>>(s->partB, (int)s->L.nb_sw, 4, 0, s->red + 52);
+        HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red, 56 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+        HIPCHK(s, hipStreamSynchronize(s->st));
+        r = harvest_events(s);
+        if (r) return r;
+        o.dominance[0] = s->hbuf[44];
+        o.dominance[1] = s->hbuf[45];
+        if (bn2[0] < 0.0) {
+            for (int f = 0; f < 4; ++f) bn2[f] = s->hbuf[f];
+            for (int f = 0; f < 4; ++f)
+                if (!std::isfinite(bn2[f])) return fail(s, HOSC_E_NONFINITE, "non-finite right-hand side");
+        }
+        double rr[4], inner_bn2[4] = {0, 0, 0, 0};
+        double target = 0.1;
+        for (int f = 0; f < 4; ++f) rr[f] = s->hbuf[48 + f] + s->hbuf[52 + f];
+        for (int grp = 0; grp < 2; ++grp) {
+            if (!(active & (1 << grp))) continue;
+            const int f0 = grp == 0 ? 0 : 3, f1 = grp == 0 ? 3 : 4;
+            bool conv = true, zero = true;
+            for (int f = f0; f < f1; ++f) {
+                if (!std::isfinite(rr[f])) return fail(s, HOSC_E_NONFINITE, "non-finite residual in refinement");
+                zero = zero && bn2[f] == 0.0;
+                o.relres[f] = bn2[f] > 0.0 ? std::sqrt(rr[f] / bn2[f]) : 0.0;
+                if (!(bn2[f] == 0.0 || std::sqrt(rr[f]) <= rtol * std::sqrt(bn2[f]))) conv = false;
+                inner_bn2[f] = rr[f];
+                if (bn2[f] > 0.0 && rr[f] > 0.0) target = std::min(target, rtol * std::sqrt(bn2[f] / rr[f]));
+            }
+            if (zero) {     // b = 0: the increment is zero
+                r = zero_group(s, grp);
+                if (r) return r;
+            }
+            if (conv || zero) active &= ~(1 << grp);
+        }
+        if (!active) break;
+        int failed = 0;
+        r = run_sor<float>(s, active, inner_bn2, o, &failed, sweep_args_fp32(s), std::max(2e-6, 0.3 * target));
+        if (r) return r;
+        if (failed) {
+            for (int grp = 0; grp < 2; ++grp) {
+                if (!(failed & (1 << grp))) continue;
+                const int f0 = grp == 0 ? 0 : 3, f1 = grp == 0 ? 3 : 4;
+                for (int f = f0; f < f1; ++f) {
+                    HIPCHK(s, hipMemsetAsync(s->fe[f], 0, 2 * s->g.cs * sizeof(float), s->st));
+                    HIPCHK(s, hipMemsetAsync(s->fr[f], 0, 2 * s->g.cs * sizeof(float), s->st));
+                }
+            }
+            *to_bicg |= failed;
+            active &= ~failed;
+        }
+    }
+    return HOSC_OK;
+}
+
+// Solve the momentum (3 right-hand sides) and energy systems of the step.
 hosc_status solve(hosc_solver *s, SolveOut &o)
 {
     // ||b/C||^2 of the four systems (reduced after the assembly into red[0..3]) are
@@ -741,7 +892,8 @@ hosc_status solve(hosc_solver *s, SolveOut &o)
     }
     if (sor_mask) {
         int failed = 0;
-        hosc_status r = run_sor(s, sor_mask, bn2, o, &failed);
+        hosc_status r = s->fp32 ? solve_refined(s, sor_mask, bn2, o, &failed)
+                                : run_sor<double>(s, sor_mask, bn2, o, &failed, sweep_args(s), s->P.solve_rtol);
         if (r) return r;
         for (int grp = 0; grp < 2; ++grp)
             if (failed & (1 << grp)) {
@@ -751,7 +903,8 @@ hosc_status solve(hosc_solver *s, SolveOut &o)
                 bicg_mask |= 1 << grp;
             }
     }
-    hosc_status r = run_bicg(s, bicg_mask, bn2, o);
+    hosc_status r = s->fp32 ? run_bicg<float>(s, bicg_mask, bn2, o, bicg_args<float>(s, s->fms, s->fma, s->fta))
+                            : run_bicg<double>(s, bicg_mask, bn2, o, bicg_args<double>(s, s->ms, s->ma, s->ta));
     if (r) return r;
     s->last_bicg[0] = o.bicg[0];
     s->last_bicg[1] = o.bicg[1];
@@ -762,7 +915,7 @@ hosc_status one_step(hosc_solver *s, hosc_step_info *info)
 {
     hosc_status r = stage_sources(s, true);
     if (r) return r;
-    ColourArrays ca;
+    ColourArrays<double> ca;
     ca.ms = s->ms;
     for (int d = 0; d < 3; ++d) {
         ca.ma[d] = s->ma[d];
@@ -772,9 +925,23 @@ hosc_status one_step(hosc_solver *s, hosc_step_info *info)
     ca.tb = s->tb;
     r = timed_begin(s);
     if (r) return r;
-    k_assemble<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, s->ph, s->u, s->v, s->w, s->T, s->eta, s->E[0],
-                                                         s->E[1], s->E[2], s->u2, s->v2, s->w2, s->etap, s->Ep[0],
-                                                         s->Ep[1], s->Ep[2], ca, s->partR, s->partB);
+    if (s->fp32) {
+        ColourArrays<float> cf;
+        cf.ms = s->fms;
+        for (int d = 0; d < 3; ++d) {
+            cf.ma[d] = s->fma[d];
+            cf.mb[d] = s->mb[d];
+            cf.ta[d] = s->fta[d];
+        }
+        cf.tb = s->tb;
+        k_assemble<float><<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(
+            s->g, s->ph, s->u, s->v, s->w, s->T, s->eta, s->E[0], s->E[1], s->E[2], s->u2, s->v2, s->w2, s->etap,
+            s->Ep[0], s->Ep[1], s->Ep[2], cf, s->partR, s->partB);
+    } else {
+        k_assemble<double><<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(
+            s->g, s->ph, s->u, s->v, s->w, s->T, s->eta, s->E[0], s->E[1], s->E[2], s->u2, s->v2, s->w2, s->etap,
+            s->Ep[0], s->Ep[1], s->Ep[2], ca, s->partR, s->partB);
+    }
     r = timed_end(s, 1, assemble_bytes(s->g));
     if (r) return r;
     k_reduce<<<1, 1024, 0, s->st>>>(s->partR, (int)s->L.nb_int, 4, 0, s->red);
@@ -888,7 +1055,7 @@ hosc_status hosc_workspace_bytes(const hosc_params *p, size_t *bytes)
     if (!bytes) return fail(nullptr, HOSC_E_ARG, "bytes is NULL");
     Geo g = make_geo(p->N);
     Launch L = make_launch(g);
-    *bytes = make_layout(g, L, p->solver).total_bytes;
+    *bytes = make_layout(g, L, p->solver, p->precision).total_bytes;
     return HOSC_OK;
 }
 
@@ -898,7 +1065,6 @@ hosc_status hosc_create(const hosc_params *p, void *d_ws, size_t ws_bytes, hipSt
     *out = nullptr;
     const char *e = check_params(p);
     if (e) return fail(nullptr, HOSC_E_ARG, e);
-    if (p->precision != HOSC_FP64) return fail(nullptr, HOSC_E_ARG, "precision FP32_REFINED is not available in this build");
     if (!d_ws) return fail(nullptr, HOSC_E_ARG, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return fail(nullptr, HOSC_E_ARG, "workspace must be 256-byte aligned");
     hosc_solver *s = new (std::nothrow) hosc_solver();
@@ -906,7 +1072,7 @@ hosc_status hosc_create(const hosc_params *p, void *d_ws, size_t ws_bytes, hipSt
     s->P = *p;
     s->g = make_geo(p->N);
     s->L = make_launch(s->g);
-    s->Y = make_layout(s->g, s->L, p->solver);
+    s->Y = make_layout(s->g, s->L, p->solver, p->precision);
     if (ws_bytes < s->Y.total_bytes) {
         delete s;
         return fail(nullptr, HOSC_E_NOMEM, "workspace smaller than hosc_workspace_bytes()");

@@ -411,13 +411,18 @@ __device__ __forceinline__ void assemble_node(const Geo &g, const Phys &P, int i
     }
 }
 
+template <typename TR>
 struct ColourArrays {
-    double *ms, *ma[3], *mb[3];     // momentum: s/C, a_d/C, b/C (u, v, w)
-    double *ta[3], *tb;             // energy: a_d/C, b/C
+    TR *ms, *ma[3];                 // momentum rows: s/C, a_d/C (FP64, or FP32 in the precision mode)
+    double *mb[3];                  // momentum right-hand sides b/C (u, v, w), always FP64
+    TR *ta[3];                      // energy rows: a_d/C
+    double *tb;                     // energy right-hand side b/C
 };
 
-// Assemble every interior node and write the scaled rows in the colour layout;
-// per-block partial sums of ||b/C||^2 for the four systems.
+// Assemble every interior node and write the scaled rows in the colour layout
+// (rows stored as TR, right-hand sides as FP64); per-block partial sums of
+// ||b/C||^2 for the four systems and the largest off-diagonal/centre ratio.
+template <typename TR>
 __global__ void __launch_bounds__(256) k_assemble(Geo g, Phys P, const double *__restrict__ u,
                                                   const double *__restrict__ v, const double *__restrict__ w,
                                                   const double *__restrict__ T, const double *__restrict__ eta,
@@ -426,7 +431,7 @@ __global__ void __launch_bounds__(256) k_assemble(Geo g, Phys P, const double *_
                                                   const double *__restrict__ vp, const double *__restrict__ wp,
                                                   const double *__restrict__ etap, const double *__restrict__ Eup,
                                                   const double *__restrict__ Evp, const double *__restrict__ Ewp,
-                                                  ColourArrays ca, double *__restrict__ partial,
+                                                  ColourArrays<TR> ca, double *__restrict__ partial,
                                                   double *__restrict__ partial_dom)
 {
     const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x, j = 1 + blockIdx.y * blockDim.y + threadIdx.y,
@@ -438,14 +443,14 @@ __global__ void __launch_bounds__(256) k_assemble(Geo g, Phys P, const double *_
         assemble_node(g, P, i, j, k, u, v, w, T, eta, Eu, Ev, Ew, up, vp, wp, etap, Eup, Evp, Ewp, a);
         const size_t idx = (size_t)((i + j + k) & 1) * g.cs + rowid(g, j, k) + (i >> 1);
         const double rm = 1.0 / a.Cm, rt = 1.0 / a.Ct;
-        ca.ms[idx] = a.sm * rm;
+        ca.ms[idx] = (TR)(a.sm * rm);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            ca.ma[d][idx] = a.am[d] * rm;
+            ca.ma[d][idx] = (TR)(a.am[d] * rm);
             const double bb = a.b[d] * rm;
             ca.mb[d][idx] = bb;
             acc[d] = bb * bb;
-            ca.ta[d][idx] = a.at[d] * rt;
+            ca.ta[d][idx] = (TR)(a.at[d] * rt);
         }
         const double bt = a.b[3] * rt;
         ca.tb[idx] = bt;
@@ -630,10 +635,12 @@ __global__ void __launch_bounds__(256) k_sweep(Geo g, int colour, int mask, TA o
 //   s = r - alpha v',  t = B s                           omega = (t, s) / (t, t)
 //   x += alpha p' + omega s,  r = s - omega t            beta = (rho'/rho)(alpha/omega)
 // ---------------------------------------------------------------------------
-template <typename TM>
+template <typename TR, typename TM>
 struct BicgArgs {
-    const TM *ms, *ma[3], *mb[3];   // momentum rows
-    const TM *ta[3], *tb;           // energy rows
+    const TR *ms, *ma[3];           // momentum rows (FP64, or FP32 in the precision mode)
+    const TM *mb[3];                // momentum right-hand sides
+    const TR *ta[3];                // energy rows
+    const TM *tb;                   // energy right-hand side
     TM *x[4], *r[4], *rh[4], *p[4], *pn[4], *v[4], *vn[4], *t[4];
 };
 
@@ -649,8 +656,8 @@ __device__ __forceinline__ bool bicg_node(const Geo &g, int q, int &j, int &k, i
 // phase 1: p' = r + beta (p - omega v), v' = B p';  partials (rh, v')
 // phase 2: s = r - alpha v', t = B s;  partials (t, s), (t, t)
 // phase 3: x += alpha p' + omega s, r = s - omega t;  partials (rh, r), (r, r)
-template <typename TM, typename TA>
-__global__ void __launch_bounds__(256) k_bicg(Geo g, int phase, int mask, TA st, BicgArgs<TM> a,
+template <typename TR, typename TM, typename TA>
+__global__ void __launch_bounds__(256) k_bicg(Geo g, int phase, int mask, TA st, BicgArgs<TR, TM> a,
                                               const double *__restrict__ sc, double *__restrict__ partial)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -757,6 +764,60 @@ __global__ void __launch_bounds__(256) k_bicg_scalars(int phase, int mask, const
             S[4] = b;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Iterative refinement of the precision mode.  For the nodes of one colour:
+// fold the FP32 correction into the FP64 increment (d <- d + e, e <- 0) and form
+// the FP64 residual r = b - B d of the scaled rows, with B taken from its FP32
+// storage; r goes to FP32 for the next inner solve.  Neighbours contribute d + e:
+// before their colour is folded that is the corrected value, afterwards e = 0.
+// Per-block partial sums of ||r||^2 for the systems in `mask`.
+// ---------------------------------------------------------------------------
+template <typename TR>
+struct RefineArgs {
+    const TR *ms, *ma[3], *ta[3];   // rows (FP32)
+    const double *b[4];             // right-hand sides (u, v, w, theta)
+    double *d[4];                   // increments (FP64)
+    float *e[4];                    // corrections from the inner solve
+    float *r[4];                    // residuals for the inner solve
+};
+
+template <typename TR>
+__global__ void __launch_bounds__(256) k_refine_residual(Geo g, int colour, int mask, double st, RefineArgs<TR> a,
+                                                         double *__restrict__ partial)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y, k = 1 + blockIdx.z;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    RowIdx r;
+    if (row_index(g, colour, q, j, k, r)) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            if (!((f < 3) ? (mask & 1) : (mask & 2))) continue;
+            const double *D = a.d[f];
+            const float *Ec = a.e[f];
+            auto val = [&](size_t i) { return D[i] + (double)Ec[i]; };
+            const double own = val(r.me);
+            double bx;
+            if (f < 3) {
+                bx = own + mom_off<double>((double)a.ms[r.me], (double)a.ma[0][r.me], (double)a.ma[1][r.me],
+                                           (double)a.ma[2][r.me], r, val);
+            } else {
+                double den;
+                const double off = theta_off<double>(st, (double)a.ta[0][r.me], (double)a.ta[1][r.me],
+                                                     (double)a.ta[2][r.me], j, k, g.N, r, val, den);
+                bx = den * own + off;
+            }
+            const double rr = a.b[f][r.me] - bx;
+            a.d[f][r.me] = own;
+            a.e[f][r.me] = 0.0f;
+            a.r[f][r.me] = (float)rr;
+            acc[f] = rr * rr;
+        }
+    }
+    const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    block_sum_store<4>(acc, partial + (size_t)blk * 4);
 }
 
 // ---------------------------------------------------------------------------

@@ -62,7 +62,8 @@ class CPerf(ctypes.Structure):
     _fields_ = [("sweep_launches", ctypes.c_int64), ("sweep_ms", ctypes.c_double), ("sweep_bytes", ctypes.c_double),
                 ("assemble_launches", ctypes.c_int64), ("assemble_ms", ctypes.c_double),
                 ("assemble_bytes", ctypes.c_double), ("bicg_launches", ctypes.c_int64), ("bicg_ms", ctypes.c_double),
-                ("bicg_bytes", ctypes.c_double)]
+                ("bicg_bytes", ctypes.c_double), ("refine_launches", ctypes.c_int64), ("refine_ms", ctypes.c_double),
+                ("refine_bytes", ctypes.c_double)]
 
 
 _lib = None
