@@ -11,6 +11,14 @@ impulsive start (the FP64 oracle diverges at step 16 exactly like the GPU path),
 the timed steps are taken in segments of SEGMENT steps from the seeded initial
 state; the clock is stopped while the state is re-initialised between segments.
 
+`--workload fp32r` is the precision form (n = 1.25, Ra = 1e4, FP32 rows and inner
+sweeps with FP64 residuals and refinement).  Shear-thickening flow cannot start
+from rest under the stated scheme (the second step's rows lose their centre), so
+it starts from a flowing state: the seeded rest state advanced by 20 Newtonian
+FP64 steps at the same Ra and dt.  After the timed run the same segment is run in
+FP64 from the same start and the relative L2 difference of every field and of the
+Nu/Be/entropy scalars is reported.
+
 Prints one JSON line: cell-updates/s (interior nodes x steps / second), the
 roofline of the dominant kernel (the red-black sweep, HIP events around every
 launch, algorithmic bytes per launch), and the FP64 CPU oracle timed on the
@@ -40,8 +48,9 @@ WORKLOADS = {
                  label="HOSC cavity 129^3, n=0.75, Ra=1e5, Pr=1, dt=5e-5, FP64, rtol 1e-10, seed 2"),
     # precision form: shear-thickening, Ra = 1e4, FP32 rows and sweeps with FP64 refinement
     "fp32r": dict(N=129, Ra=1e4, n_pl=1.25, Pr=1.0, dt=5e-5, seed=3, noise=1e-3, solve_rtol=1e-10, precision=1,
+                  newtonian_start=20, segment=60,
                   label="HOSC cavity 129^3, n=1.25, Ra=1e4, Pr=1, dt=5e-5, FP32 rows/sweeps + FP64 refinement, "
-                        "rtol 1e-10, seed 3"),
+                        "rtol 1e-10, seed 3, flowing start (20 Newtonian FP64 steps)"),
 }
 WORKLOAD = WORKLOADS["fp64"]
 SEGMENT = 12
@@ -77,12 +86,42 @@ def cpu_baseline(budget_s: float = 20.0) -> dict:
                       f"({el:.1f} s, FP64, BiCGSTAB tol 1e-13, {cores} OpenMP threads)"}
 
 
+def precision_check(hosc, W, kw, reset, steps):
+    """Relative L2 difference of every field, and relative difference of the Nu, Be
+    and entropy scalars, between the precision form and the FP64 path after `steps`
+    steps from the same start state, with the wall time per step of each run (the
+    first steps of a fresh solver, so a little above the timed figure)."""
+    import numpy as np
+    import torch
+    res, ms = {}, {}
+    for prec in (0, W["precision"]):
+        s = hosc.Solver(hosc.params(W["N"], **dict(kw, precision=prec)), device="cuda:0")
+        reset(s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.step(1)
+            s.diagnostics(arrays=False)
+        torch.cuda.synchronize()
+        ms[prec] = (time.perf_counter() - t0) * 1e3 / steps
+        res[prec] = (s.get_state(), s.diagnostics(arrays=False))
+        s.close()
+    (g0, d0), (g1, d1) = res[0], res[W["precision"]]
+    out = {"steps": steps, "fp64_ms_per_step": ms[0], "this_form_ms_per_step": ms[W["precision"]],
+           "field_rel_l2": {}, "scalar_rel": {}}
+    for f in ("u", "v", "w", "T", "p"):
+        out["field_rel_l2"][f] = float(np.linalg.norm(g1[f] - g0[f]) / np.linalg.norm(g0[f]))
+    for k in ("nu_mean_hot", "nu_mean_cold", "nu_max_hot", "be_global", "e_total"):
+        out["scalar_rel"][k] = float(abs(d1[k] - d0[k]) / abs(d0[k]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=120)
     ap.add_argument("--warmup", type=int, default=12)
-    ap.add_argument("--segment", type=int, default=SEGMENT)
+    ap.add_argument("--segment", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--omega", type=float, default=None)
@@ -98,12 +137,28 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     W = WORKLOADS[args.workload]
+    if args.segment is None:
+        args.segment = W.get("segment", SEGMENT)
     kw = dict(Ra=W["Ra"], n_pl=W["n_pl"], Pr=W["Pr"], dt=W["dt"], solve_rtol=W["solve_rtol"],
               precision=W["precision"])
     if args.omega is not None:
         kw["omega"] = args.omega
+    start = None
+    if W.get("newtonian_start"):
+        w = hosc.Solver(hosc.params(W["N"], **dict(kw, n_pl=1.0, precision=0)), device="cuda:0")
+        w.init_fields(W["seed"], W["noise"])
+        w.step(W["newtonian_start"])
+        start = w.get_state()
+        w.close()
     s = hosc.Solver(hosc.params(W["N"], **kw), device="cuda:0")
-    s.init_fields(W["seed"], W["noise"])
+
+    def reset(solver):
+        if start is None:
+            solver.init_fields(W["seed"], W["noise"])
+        else:
+            solver.set_state(**start, apply_bc=False)
+
+    reset(s)
 
     def one_step():
         info = s.step(1)
@@ -113,11 +168,11 @@ def main():
     in_segment = 0
     for _ in range(args.warmup):
         if in_segment == args.segment:
-            s.init_fields(W["seed"], W["noise"])
+            reset(s)
             in_segment = 0
         one_step()
         in_segment += 1
-    s.init_fields(W["seed"], W["noise"])
+    reset(s)
     in_segment = 0
     s.perf_enable(True)
     torch.cuda.synchronize()
@@ -128,7 +183,7 @@ def main():
         if in_segment == args.segment:
             torch.cuda.synchronize()
             el += time.perf_counter() - t0
-            s.init_fields(W["seed"], W["noise"])
+            reset(s)
             in_segment = 0
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -167,7 +222,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if W["precision"] == 0 else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{W['label']}; steps 1-{args.segment} from the seeded initial state, repeated",
+        "config": {"workload": f"{W['label']}; steps 1-{args.segment} from the start state, repeated",
                    "grid": W["N"], "interior_nodes": M3, "precision": args.workload, "segment_steps": args.segment,
                    "mean_sor_sweeps_per_step": [sweeps[0] / args.steps, sweeps[1] / args.steps],
                    "mean_bicgstab_iters_per_step": [sweeps[2] / args.steps, sweeps[3] / args.steps]},
@@ -183,6 +238,8 @@ def main():
                      "refine_time_frac": perf["refine_ms"] * 1e-3 / el},
     }
     s.close()
+    if W["precision"] != 0:
+        out["precision_check"] = precision_check(hosc, W, kw, reset, args.segment)
     out["roofline"]["copy_probe_GBs"] = hosc.copy_bandwidth(1 << 30, 10)
     if not args.no_cpu_baseline and args.workload == "fp64":
         out["cpu_baseline"] = cpu_baseline(args.cpu_budget)

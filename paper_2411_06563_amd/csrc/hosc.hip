@@ -44,7 +44,7 @@ struct Layout {
     size_t natural_arrays = 17;   // u v w T p u2 v2 w2 eta etap E3 Ep3 dbg
     size_t colour_arrays = 15;    // ms ma3 mb3 md3 ta3 tb td (each 2 colours)
     size_t bicg_arrays = 0;       // r rh p pn v vn t for 4 systems (BiCGSTAB enabled)
-    size_t fp32_arrays = 0;       // precision mode: FP32 residuals and corrections of 4 systems
+    size_t fp32_arrays = 0;       // precision mode: FP32 rows (7), residuals and corrections of 4 systems
     size_t partial;               // partial-sum records
     size_t total_bytes;
 };
@@ -91,7 +91,7 @@ Launch make_launch(const Geo &g)
 Layout make_layout(const Geo &g, const Launch &L, int solver, int precision)
 {
     Layout y;
-    y.fp32_arrays = precision == HOSC_FP32_REFINED ? 8 : 0;
+    y.fp32_arrays = precision == HOSC_FP32_REFINED ? 15 : 0;
     y.n3 = g.n3;
     y.cs = g.cs;
     y.bicg_arrays = solver == HOSC_SOLVER_SOR ? 0 : 28;
@@ -189,8 +189,8 @@ struct hosc_solver {
     double *br[4], *brh[4], *bp[4], *bpn[4], *bv[4], *bvn[4], *bt[4];
     double *bsc;
     int64_t bicg_until[2] = {-1, -1};   // auto mode: use BiCGSTAB for the group until this step
-    // precision mode: rows stored in FP32 (in the row arrays above), FP32 residuals
-    // and corrections of the inner solves
+    // precision mode: FP32 copies of the rows, FP32 residuals and corrections of the
+    // inner solves
     bool fp32 = false;
     float *fms = nullptr, *fma[3] = {nullptr, nullptr, nullptr}, *fta[3] = {nullptr, nullptr, nullptr};
     float *fr[4] = {nullptr, nullptr, nullptr, nullptr}, *fe[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -275,12 +275,10 @@ void carve(hosc_solver *s, char *base)
     for (int f = 0; f < 4; ++f) s->br[f] = s->brh[f] = s->bp[f] = s->bpn[f] = s->bv[f] = s->bvn[f] = s->bt[f] = nullptr;
     s->fp32 = s->Y.fp32_arrays > 0;
     if (s->fp32) {
-        s->fms = reinterpret_cast<float *>(s->ms);
-        for (int d = 0; d < 3; ++d) {
-            s->fma[d] = reinterpret_cast<float *>(s->ma[d]);
-            s->fta[d] = reinterpret_cast<float *>(s->ta[d]);
-        }
         const size_t fcol = align_up(2 * s->g.cs * sizeof(float));
+        s->fms = reinterpret_cast<float *>(take(fcol));
+        for (int d = 0; d < 3; ++d) s->fma[d] = reinterpret_cast<float *>(take(fcol));
+        for (int d = 0; d < 3; ++d) s->fta[d] = reinterpret_cast<float *>(take(fcol));
         for (int f = 0; f < 4; ++f) s->fr[f] = reinterpret_cast<float *>(take(fcol));
         for (int f = 0; f < 4; ++f) s->fe[f] = reinterpret_cast<float *>(take(fcol));
     }
@@ -303,15 +301,15 @@ double sweep_bytes(const Geo &g, int mask, size_t elem = sizeof(double))
     return nodes * per;
 }
 
-// Algorithmic bytes of one refinement-residual launch (one colour): FP32 rows,
+// Algorithmic bytes of one refinement-residual launch (one colour): FP64 rows,
 // FP64 right-hand side, FP64 increment read + written, FP32 correction read + zeroed,
 // FP32 residual written, and the other colour's increment and correction read once.
 double refine_bytes(const Geo &g, int mask)
 {
     const double nodes = 0.5 * (double)(g.N - 2) * (g.N - 2) * (g.N - 2);
     double per = 0.0;
-    if (mask & 1) per += 4 * 4 + 3 * (8 + 8 + 8 + 4 + 4 + 4 + 8 + 4);
-    if (mask & 2) per += 3 * 4 + (8 + 8 + 8 + 4 + 4 + 4 + 8 + 4);
+    if (mask & 1) per += 4 * 8 + 3 * (8 + 8 + 8 + 4 + 4 + 4 + 8 + 4);
+    if (mask & 2) per += 3 * 8 + (8 + 8 + 8 + 4 + 4 + 4 + 8 + 4);
     return nodes * per;
 }
 
@@ -522,8 +520,13 @@ double young_omega(double lam, double w)
 }
 
 template <typename TM>
-hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *failed, SweepArgs<TM> a, double rtol)
+hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *failed, SweepArgs<TM> a, double rtol,
+                    bool inner = false)
 {
+    // inner solves of the refinement: at most 200 sweeps, and no relaxation update
+    // from a first batch (a short batch that starts from zero measures the start-up
+    // transient, not the asymptotic contraction Young's relation needs)
+    const int soft_cap = inner ? 200 : 0;
     const double ct = s->g.h2 / 12.0 - s->P.dt / 2.0;
     const double Ct = 1.0 - 6.0 * ct * s->g.invh2;
     const double st = (ct * s->g.invh2) / Ct;
@@ -535,6 +538,7 @@ hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *f
     double ref[2] = {-1.0, -1.0};
     int ref_at[2] = {0, 0};
     int plan[2] = {0, 0};
+    int swept[2] = {0, 0};      // sweeps of this call (o.sweeps also counts earlier calls of the step)
     for (int grp = 0; grp < 2; ++grp)
         plan[grp] = s->P.check_every > 0 ? s->P.check_every : std::max(2, s->last_sweeps[grp]);
     const int first_plan[2] = {plan[0], plan[1]};
@@ -548,7 +552,7 @@ hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *f
             if (mu > 0.0 && std::isfinite(mu)) s->om[grp] = 2.0 / (1.0 + std::sqrt(1.0 - mu * mu));
         }
     }
-    while (active) {
+    for (int batch = 0; active; ++batch) {
         int nsw = 0;
         for (int grp = 0; grp < 2; ++grp)
             if (active & (1 << grp)) nsw = std::max(nsw, plan[grp]);
@@ -592,7 +596,8 @@ hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *f
         for (int grp = 0; grp < 2; ++grp) {
             if (!(active & (1 << grp))) continue;
             o.sweeps[grp] += plan[grp];
-            const int done = o.sweeps[grp];
+            swept[grp] += plan[grp];
+            const int done = swept[grp];
             const int f0 = grp == 0 ? 0 : 3, f1 = grp == 0 ? 3 : 4;
             const double om = s->om[grp];
             bool conv = true, finite = true;
@@ -611,7 +616,7 @@ hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *f
             double rate = -1.0;
             if (finite && plan[grp] > 1 && worst0 > 0.0 && worst > 0.0 && worst < worst0)
                 rate = std::pow(worst / worst0, 1.0 / (double)(plan[grp] - 1));
-            if (adapt && rate > 0.0 && rate < 1.0 && plan[grp] >= 4) {
+            if (adapt && rate > 0.0 && rate < 1.0 && plan[grp] >= 4 && !(inner && batch == 0)) {
                 // below the optimum the contraction exceeds w - 1 and Young's relation
                 // gives the optimum; at or past it the contraction is about w - 1: back off
                 const double w = s->om[grp];
@@ -639,6 +644,11 @@ hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *f
             // 2x reduction over 100 sweeps
             const bool diverged = !finite || (ref[grp] >= 0.0 && worst > 2.0 * ref[grp]) || (rate < 0.0 && worst > 2.0 * worst0 && worst0 > 0.0);
             const bool stalled = ref[grp] >= 0.0 && done - ref_at[grp] >= 100 && worst > 0.5 * ref[grp];
+            if (soft_cap > 0 && done >= soft_cap && !diverged) {
+                // inner solve of the refinement: stop here, the outer pass takes what it has
+                active &= ~(1 << grp);
+                continue;
+            }
             if (diverged || stalled || done >= s->P.solve_maxit) {
                 if (autom) {
                     *failed |= 1 << grp;
@@ -796,11 +806,11 @@ hosc_status solve_refined(hosc_solver *s, int mask, double bn2[4], SolveOut &o, 
     const double ct = s->g.h2 / 12.0 - s->P.dt / 2.0;
     const double Ct = 1.0 - 6.0 * ct * s->g.invh2;
     const double st = (ct * s->g.invh2) / Ct;
-    RefineArgs<float> ra;
-    ra.ms = s->fms;
+    RefineArgs<double> ra;
+    ra.ms = s->ms;
     for (int d = 0; d < 3; ++d) {
-        ra.ma[d] = s->fma[d];
-        ra.ta[d] = s->fta[d];
+        ra.ma[d] = s->ma[d];
+        ra.ta[d] = s->ta[d];
         ra.b[d] = s->mb[d];
         ra.d[d] = s->md[d];
     }
@@ -817,7 +827,7 @@ hosc_status solve_refined(hosc_solver *s, int mask, double bn2[4], SolveOut &o, 
         hosc_status r = timed_begin(s);
         if (r) return r;
         for (int colour = 0; colour < 2; ++colour)
-            k_refine_residual<float><<<s->L.grd_sw, s->L.blk_sw, 0, s->st>>>(s->g, colour, active, st, ra,
+            k_refine_residual<double><<<s->L.grd_sw, s->L.blk_sw, 0, s->st>>>(s->g, colour, active, st, ra,
                                                                             colour ? s->partB : s->partR);
         r = timed_end(s, 3, 2.0 * refine_bytes(s->g, active), 2);
         if (r) return r;
@@ -859,7 +869,7 @@ hosc_status solve_refined(hosc_solver *s, int mask, double bn2[4], SolveOut &o, 
         }
         if (!active) break;
         int failed = 0;
-        r = run_sor<float>(s, active, inner_bn2, o, &failed, sweep_args_fp32(s), std::max(2e-6, 0.3 * target));
+        r = run_sor<float>(s, active, inner_bn2, o, &failed, sweep_args_fp32(s), std::max(1e-5, 0.3 * target), true);
         if (r) return r;
         if (failed) {
             for (int grp = 0; grp < 2; ++grp) {
@@ -903,8 +913,7 @@ hosc_status solve(hosc_solver *s, SolveOut &o)
                 bicg_mask |= 1 << grp;
             }
     }
-    hosc_status r = s->fp32 ? run_bicg<float>(s, bicg_mask, bn2, o, bicg_args<float>(s, s->fms, s->fma, s->fta))
-                            : run_bicg<double>(s, bicg_mask, bn2, o, bicg_args<double>(s, s->ms, s->ma, s->ta));
+    hosc_status r = run_bicg<double>(s, bicg_mask, bn2, o, bicg_args<double>(s, s->ms, s->ma, s->ta));
     if (r) return r;
     s->last_bicg[0] = o.bicg[0];
     s->last_bicg[1] = o.bicg[1];
@@ -915,7 +924,7 @@ hosc_status one_step(hosc_solver *s, hosc_step_info *info)
 {
     hosc_status r = stage_sources(s, true);
     if (r) return r;
-    ColourArrays<double> ca;
+    ColourArrays ca;
     ca.ms = s->ms;
     for (int d = 0; d < 3; ++d) {
         ca.ma[d] = s->ma[d];
@@ -925,23 +934,14 @@ hosc_status one_step(hosc_solver *s, hosc_step_info *info)
     ca.tb = s->tb;
     r = timed_begin(s);
     if (r) return r;
-    if (s->fp32) {
-        ColourArrays<float> cf;
-        cf.ms = s->fms;
-        for (int d = 0; d < 3; ++d) {
-            cf.ma[d] = s->fma[d];
-            cf.mb[d] = s->mb[d];
-            cf.ta[d] = s->fta[d];
-        }
-        cf.tb = s->tb;
-        k_assemble<float><<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(
-            s->g, s->ph, s->u, s->v, s->w, s->T, s->eta, s->E[0], s->E[1], s->E[2], s->u2, s->v2, s->w2, s->etap,
-            s->Ep[0], s->Ep[1], s->Ep[2], cf, s->partR, s->partB);
-    } else {
-        k_assemble<double><<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(
-            s->g, s->ph, s->u, s->v, s->w, s->T, s->eta, s->E[0], s->E[1], s->E[2], s->u2, s->v2, s->w2, s->etap,
-            s->Ep[0], s->Ep[1], s->Ep[2], ca, s->partR, s->partB);
+    ca.fms = s->fms;
+    for (int d = 0; d < 3; ++d) {
+        ca.fma[d] = s->fma[d];
+        ca.fta[d] = s->fta[d];
     }
+    k_assemble<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, s->ph, s->u, s->v, s->w, s->T, s->eta, s->E[0],
+                                                         s->E[1], s->E[2], s->u2, s->v2, s->w2, s->etap, s->Ep[0],
+                                                         s->Ep[1], s->Ep[2], ca, s->partR, s->partB);
     r = timed_end(s, 1, assemble_bytes(s->g));
     if (r) return r;
     k_reduce<<<1, 1024, 0, s->st>>>(s->partR, (int)s->L.nb_int, 4, 0, s->red);

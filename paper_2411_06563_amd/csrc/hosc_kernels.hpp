@@ -411,18 +411,17 @@ __device__ __forceinline__ void assemble_node(const Geo &g, const Phys &P, int i
     }
 }
 
-template <typename TR>
 struct ColourArrays {
-    TR *ms, *ma[3];                 // momentum rows: s/C, a_d/C (FP64, or FP32 in the precision mode)
-    double *mb[3];                  // momentum right-hand sides b/C (u, v, w), always FP64
-    TR *ta[3];                      // energy rows: a_d/C
+    double *ms, *ma[3];             // momentum rows: s/C, a_d/C
+    double *mb[3];                  // momentum right-hand sides b/C (u, v, w)
+    double *ta[3];                  // energy rows: a_d/C
     double *tb;                     // energy right-hand side b/C
+    float *fms, *fma[3], *fta[3];   // FP32 copies of the rows for the precision mode (null otherwise)
 };
 
 // Assemble every interior node and write the scaled rows in the colour layout
-// (rows stored as TR, right-hand sides as FP64); per-block partial sums of
-// ||b/C||^2 for the four systems and the largest off-diagonal/centre ratio.
-template <typename TR>
+// (FP64, plus FP32 copies of the rows in the precision mode); per-block partial
+// sums of ||b/C||^2 for the four systems and the largest off-diagonal/centre ratio.
 __global__ void __launch_bounds__(256) k_assemble(Geo g, Phys P, const double *__restrict__ u,
                                                   const double *__restrict__ v, const double *__restrict__ w,
                                                   const double *__restrict__ T, const double *__restrict__ eta,
@@ -431,7 +430,7 @@ __global__ void __launch_bounds__(256) k_assemble(Geo g, Phys P, const double *_
                                                   const double *__restrict__ vp, const double *__restrict__ wp,
                                                   const double *__restrict__ etap, const double *__restrict__ Eup,
                                                   const double *__restrict__ Evp, const double *__restrict__ Ewp,
-                                                  ColourArrays<TR> ca, double *__restrict__ partial,
+                                                  ColourArrays ca, double *__restrict__ partial,
                                                   double *__restrict__ partial_dom)
 {
     const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x, j = 1 + blockIdx.y * blockDim.y + threadIdx.y,
@@ -443,14 +442,21 @@ __global__ void __launch_bounds__(256) k_assemble(Geo g, Phys P, const double *_
         assemble_node(g, P, i, j, k, u, v, w, T, eta, Eu, Ev, Ew, up, vp, wp, etap, Eup, Evp, Ewp, a);
         const size_t idx = (size_t)((i + j + k) & 1) * g.cs + rowid(g, j, k) + (i >> 1);
         const double rm = 1.0 / a.Cm, rt = 1.0 / a.Ct;
-        ca.ms[idx] = (TR)(a.sm * rm);
+        const double sm = a.sm * rm;
+        ca.ms[idx] = sm;
+        if (ca.fms) ca.fms[idx] = (float)sm;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            ca.ma[d][idx] = (TR)(a.am[d] * rm);
+            const double am = a.am[d] * rm, at = a.at[d] * rt;
+            ca.ma[d][idx] = am;
+            ca.ta[d][idx] = at;
+            if (ca.fms) {
+                ca.fma[d][idx] = (float)am;
+                ca.fta[d][idx] = (float)at;
+            }
             const double bb = a.b[d] * rm;
             ca.mb[d][idx] = bb;
             acc[d] = bb * bb;
-            ca.ta[d][idx] = (TR)(a.at[d] * rt);
         }
         const double bt = a.b[3] * rt;
         ca.tb[idx] = bt;
@@ -769,14 +775,14 @@ __global__ void __launch_bounds__(256) k_bicg_scalars(int phase, int mask, const
 // ---------------------------------------------------------------------------
 // Iterative refinement of the precision mode.  For the nodes of one colour:
 // fold the FP32 correction into the FP64 increment (d <- d + e, e <- 0) and form
-// the FP64 residual r = b - B d of the scaled rows, with B taken from its FP32
-// storage; r goes to FP32 for the next inner solve.  Neighbours contribute d + e:
+// the FP64 residual r = b - B d of the scaled FP64 rows (so the refinement
+// converges to the FP64 solution); r goes to FP32 for the next inner solve.  Neighbours contribute d + e:
 // before their colour is folded that is the corrected value, afterwards e = 0.
 // Per-block partial sums of ||r||^2 for the systems in `mask`.
 // ---------------------------------------------------------------------------
 template <typename TR>
 struct RefineArgs {
-    const TR *ms, *ma[3], *ta[3];   // rows (FP32)
+    const TR *ms, *ma[3], *ta[3];   // rows (FP64)
     const double *b[4];             // right-hand sides (u, v, w, theta)
     double *d[4];                   // increments (FP64)
     float *e[4];                    // corrections from the inner solve

@@ -1,11 +1,11 @@
-"""Precision mode (FP32 implicit rows and inner red-black sweeps, FP64 right-hand
-sides, residuals, increments, pressure and reductions, with iterative refinement).
+"""Precision mode: the inner red-black sweeps run on FP32 copies of the implicit
+rows; right-hand sides, increments, pressure and reductions stay FP64, and the
+residual of every refinement pass is formed in FP64 with the FP64 rows.
 
-The refined solve converges to the solution of the FP32-stored matrix, which
-differs from the FP64 matrix by about 6e-8 relative, so transient fields differ
-from the FP64 oracle at the 1e-7 level; at steady state the increment b vanishes
-in FP64 arithmetic, so both precisions reach the same discrete steady state.
-Measured errors are printed per field."""
+Iterative refinement with an FP64 residual converges to the solution of the FP64
+system, so the fields must agree with the FP64 oracle to the same solve tolerance
+as the FP64 path (relative residual 1e-12, at which the FP64 path's field error is
+below 1e-10).  The bounds below allow a factor 100 over that."""
 import sys
 
 import numpy as np
@@ -34,26 +34,34 @@ def hosc():
     return h
 
 
-@pytest.mark.parametrize("N,n_pl,Ra,dt", [(17, 1.25, 1e4, 1e-4), (18, 0.75, 1e4, 1e-4), (33, 1.25, 1e4, 5e-5)])
+# Cases whose implicit systems are well conditioned: the oracle's own result moves
+# by less than 1e-10 between solve tolerances 1e-12 and 1e-15.  (At 17^3, n = 1.25,
+# dt = 1e-4 it moves by 2e-7: started from rest, the extrapolated time coefficient
+# (3L^n - L^(n-1))/2 of the second step is negative and the rows nearly singular.)
+@pytest.mark.parametrize("N,n_pl,Ra,dt", [(17, 1.25, 1e4, 5e-4), (18, 0.75, 1e4, 1e-4), (33, 1.25, 1e4, 2e-4)])
 def test_fp32_refined_vs_oracle(hosc, oracle_lib, N, n_pl, Ra, dt):
     say(f"[fp32r] N={N} n={n_pl} Ra={Ra:g} dt={dt}, 20 steps")
     kw = dict(Ra=Ra, n_pl=n_pl, Pr=1.0, dt=dt)
-    s = hosc.Solver(hosc.params(N, precision=hosc.HOSC_FP32_REFINED, solve_rtol=1e-11, **kw))
+    s = hosc.Solver(hosc.params(N, precision=hosc.HOSC_FP32_REFINED, solve_rtol=1e-12, **kw))
     s.init_fields(3, 1e-3)
-    o = oracle_lib.Oracle(oracle_lib.Params(N=N, solve_tol=1e-13, **kw))
+    o = oracle_lib.Oracle(oracle_lib.Params(N=N, solve_tol=1e-15, **kw))
     o.set_state(**initial_state(N, 3, 1e-3))
+    sweeps, bicg = [0, 0], [0, 0]
     for _ in range(20):
         info = s.step(1)
+        sweeps = [a + b for a, b in zip(sweeps, info.sweeps)]
+        bicg = [a + b for a, b in zip(bicg, info.bicg_iters)]
     o.step(20)
     g = s.get_state()
     errs = {f: rel(g[f], o.a[f]) for f in ("u", "v", "w", "T", "p")}
     d, r = s.diagnostics(arrays=False), o.diagnostics()
     derr = {k: abs(d[k] - r[k]) / abs(r[k]) for k in ("nu_mean_hot", "nu_max_hot", "e_total", "be_global")}
-    say(f"[fp32r] field rel L2 {errs}; scalar rel {derr}; sweeps {info.sweeps} relres {max(info.relres):.1e}")
+    say(f"[fp32r] field rel L2 {errs}; scalar rel {derr}; FP32 sweeps {sweeps} BiCGSTAB iterations {bicg} "
+        f"(20 steps) relres {max(info.relres):.1e}")
     for f, e in errs.items():
-        assert e <= 1e-5, (f, e)
+        assert e <= 1e-8, (f, e)
     for k, e in derr.items():
-        assert e <= 1e-7, (k, e)
+        assert e <= 1e-9, (k, e)
     s.close()
 
 
@@ -65,7 +73,9 @@ def test_fp32_refined_reaches_fp64_steady_state(hosc):
         s = hosc.Solver(hosc.params(N, precision=prec, **kw))
         s.init_fields(3, 1e-3)
         for _ in range(40):
-            info = s.run_to_steady(1e-8, 500)
+            info = s.run_to_steady(1e-8, 100)
+            say(f"[fp32r-steady] precision {prec} step {info.step} res {max(info.res):.2e} "
+                f"sweeps {list(info.sweeps)} bicg {list(info.bicg_iters)}")
             if max(info.res) < 1e-8:
                 break
         assert max(info.res) < 1e-8, (prec, info)
