@@ -221,6 +221,62 @@ const char *hosc_last_error(const hosc_solver *s);
 /* Name of a status code. */
 const char *hosc_status_string(hosc_status st);
 
+/* ------------------------------------------------------------------------------
+ * Batches: many cavities (any mix of N, Ra, Pr, n, dt; one precision) advanced
+ * together on one stream.  Each cavity is an hosc_solver carved from the batch
+ * workspace; the implicit solves of all cavities run as fused launches (one
+ * persistent launch per red-black half-sweep and per refinement-residual colour
+ * over every cavity still iterating, one launch for all reductions and one host
+ * copy per convergence check), while each cavity keeps exactly the arithmetic and
+ * solver decisions of its single-cavity run, so a cavity's results do not depend
+ * on the batch it is in.
+ * ------------------------------------------------------------------------------ */
+typedef struct hosc_batch hosc_batch;
+
+/* Device bytes for a batch of `count` cavities with parameters p[0..count). */
+hosc_status hosc_batch_workspace_bytes(const hosc_params *p, int32_t count, size_t *bytes);
+
+/* Create a batch on the current device in d_ws (>= hosc_batch_workspace_bytes,
+ * 256-byte aligned, owned by the caller, untouched until hosc_batch_destroy).
+ * All p[i].precision must be equal (HOSC_E_ARG otherwise).  Allocates only pinned
+ * host staging memory. */
+hosc_status hosc_batch_create(const hosc_params *p, int32_t count, void *d_ws, size_t ws_bytes, hipStream_t stream,
+                              hosc_batch **out);
+
+/* Release the batch and its cavity handles (not the workspace).  Accepts NULL. */
+hosc_status hosc_batch_destroy(hosc_batch *b);
+
+/* Borrow the solver of cavity idx (owned by the batch, valid until
+ * hosc_batch_destroy) for the single-cavity calls: hosc_init_fields,
+ * hosc_set_state, hosc_get_state, hosc_diagnostics, hosc_entropy_fields. */
+hosc_status hosc_batch_cavity(hosc_batch *b, int32_t idx, hosc_solver **out);
+
+/* hosc_init_fields on every cavity, cavity i with seeds[i]. */
+hosc_status hosc_batch_init_fields(hosc_batch *b, const uint64_t *seeds, double noise_amp);
+
+/* Advance every cavity nsteps steps.  info (may be NULL): count entries, the last
+ * step of each cavity.  A cavity that fails is reported by status and message
+ * ("cavity i: ..."); the step of the other cavities completes. */
+hosc_status hosc_batch_step(hosc_batch *b, int32_t nsteps, hosc_step_info *info);
+
+/* Autotuner: time the fused half-sweep at each candidate schedule (persistent
+ * workgroup counts 256 ... 4096, or one workgroup per tile) on this batch and keep
+ * the fastest (returned in *grid, 0 = one per tile).  Needs every cavity on a
+ * freshly set state (step counter 0); leaves the states unchanged. */
+hosc_status hosc_batch_tune(hosc_batch *b, int32_t *grid);
+
+/* Set the schedule by hand (persistent workgroups, 0 = one per tile). */
+hosc_status hosc_batch_set_grid(hosc_batch *b, int32_t grid);
+
+/* Timing of the fused solver launches (sweep_* and refine_* counters, one event
+ * pair per batch of fused launches) plus the cavities' assembly and BiCGSTAB
+ * counters. */
+hosc_status hosc_batch_perf_enable(hosc_batch *b, int32_t on);
+hosc_status hosc_batch_perf_get(hosc_batch *b, hosc_perf *out);
+
+/* Message of the last failing call on the batch (NULL: last failing create). */
+const char *hosc_batch_last_error(const hosc_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

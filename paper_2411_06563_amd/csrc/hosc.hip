@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -519,55 +520,194 @@ double young_omega(double lam, double w)
     return 2.0 / (1.0 + std::sqrt(1.0 - mu2));
 }
 
+// State of one red-black SOR solve between convergence checks.  The same control
+// drives the single-cavity solve and the batched solve of many cavities, so a
+// cavity takes the same decisions (sweep plans, relaxation, stopping) either way.
+struct SorCtl {
+    int active = 0, failed = 0, batch = 0, soft_cap = 0;
+    bool inner = false, adapt = false, autom = false;
+    double rtol = 0.0;
+    double ref[2] = {-1.0, -1.0};
+    int ref_at[2] = {0, 0}, plan[2] = {0, 0}, swept[2] = {0, 0}, first_plan[2] = {0, 0};
+};
+
+// inner solves of the refinement: at most 200 sweeps, and no relaxation update
+// from a first batch (a short batch that starts from zero measures the start-up
+// transient, not the asymptotic contraction Young's relation needs)
+void sor_begin(const hosc_solver *s, SorCtl &c, int mask, double rtol, bool inner)
+{
+    c = SorCtl();
+    c.active = mask;
+    c.rtol = rtol;
+    c.inner = inner;
+    c.soft_cap = inner ? 200 : 0;
+    c.adapt = s->P.omega == 0.0;
+    c.autom = s->P.solver == HOSC_SOLVER_AUTO;
+    for (int grp = 0; grp < 2; ++grp)
+        c.plan[grp] = s->P.check_every > 0 ? s->P.check_every : std::max(2, s->last_sweeps[grp]);
+    c.first_plan[0] = c.plan[0];
+    c.first_plan[1] = c.plan[1];
+}
+
+// first step after a state was set: seed the relaxation from the dominance monitor
+// of the assembly (dom = red[44..45]), a Gershgorin bound mu on the Jacobi radius
+bool sor_wants_seed(const hosc_solver *s, const SorCtl &c) { return c.adapt && s->step == 0; }
+void sor_seed(hosc_solver *s, const double *dom)
+{
+    for (int grp = 0; grp < 2; ++grp) {
+        const double mu = std::min(0.98, dom[grp]);
+        if (mu > 0.0 && std::isfinite(mu)) s->om[grp] = 2.0 / (1.0 + std::sqrt(1.0 - mu * mu));
+    }
+}
+
+// Mask and store flags of sweep q of the current batch.
+void sor_sweep_flags(const SorCtl &c, int q, int &m, unsigned &store, unsigned &store0)
+{
+    static const unsigned kStore[2] = {0x7u, 0x8u};   // residual components of each group
+    m = 0;
+    store = store0 = 0;
+    for (int grp = 0; grp < 2; ++grp) {
+        if (!(c.active & (1 << grp)) || q >= c.plan[grp]) continue;
+        m |= 1 << grp;
+        if (q == c.plan[grp] - 1) store |= kStore[grp];
+        if (q == 0 && c.plan[grp] > 1) store0 |= kStore[grp];
+    }
+}
+int sor_batch_sweeps(const SorCtl &c)
+{
+    int nsw = 0;
+    for (int grp = 0; grp < 2; ++grp)
+        if (c.active & (1 << grp)) nsw = std::max(nsw, c.plan[grp]);
+    return nsw;
+}
+
+// Decisions after a batch of sweeps, from the reduction block hb (the cavity's
+// red[0..47]: ||b/C||^2 at 0..3, last-sweep partial sums red/black at 4..11,
+// first-sweep sums at 32..39, dominance at 44..45).
+template <typename TM>
+hosc_status sor_decide(hosc_solver *s, SorCtl &c, const double *hb, double bn2[4], SolveOut &o,
+                       const SweepArgs<TM> &a)
+{
+    o.dominance[0] = hb[44];
+    o.dominance[1] = hb[45];
+    if (bn2[0] < 0.0) {
+        for (int f = 0; f < 4; ++f) bn2[f] = hb[f];
+        for (int f = 0; f < 4; ++f)
+            if (!std::isfinite(bn2[f])) return fail(s, HOSC_E_NONFINITE, "non-finite right-hand side");
+    }
+    const double rtol = c.rtol;
+    for (int grp = 0; grp < 2; ++grp) {
+        if (!(c.active & (1 << grp))) continue;
+        o.sweeps[grp] += c.plan[grp];
+        c.swept[grp] += c.plan[grp];
+        const int done = c.swept[grp];     // sweeps of this call (o.sweeps also counts earlier calls of the step)
+        const int f0 = grp == 0 ? 0 : 3, f1 = grp == 0 ? 3 : 4;
+        const double om = s->om[grp];
+        bool conv = true, finite = true;
+        double worst = 0.0, worst0 = 0.0;
+        for (int f = f0; f < f1; ++f) {
+            const double r2 = hb[8 + f] + (1.0 - om) * (1.0 - om) * hb[4 + f];
+            const double r20 = hb[36 + f] + (1.0 - om) * (1.0 - om) * hb[32 + f];
+            if (!std::isfinite(r2)) finite = false;
+            const double rel = bn2[f] > 0.0 ? std::sqrt(r2 / bn2[f]) : 0.0;
+            o.relres[f] = rel;
+            worst = std::max(worst, rel);
+            if (bn2[f] > 0.0) worst0 = std::max(worst0, std::sqrt(r20 / bn2[f]));
+            if (!(bn2[f] == 0.0 || std::sqrt(r2) <= rtol * std::sqrt(bn2[f]))) conv = false;
+        }
+        // contraction per sweep inside this batch (first vs last sweep)
+        double rate = -1.0;
+        if (finite && c.plan[grp] > 1 && worst0 > 0.0 && worst > 0.0 && worst < worst0)
+            rate = std::pow(worst / worst0, 1.0 / (double)(c.plan[grp] - 1));
+        if (c.adapt && rate > 0.0 && rate < 1.0 && c.plan[grp] >= 4 && !(c.inner && c.batch == 0)) {
+            // below the optimum the contraction exceeds w - 1 and Young's relation
+            // gives the optimum; at or past it the contraction is about w - 1: back off
+            const double w = s->om[grp];
+            double wn = (w > 1.05 && rate < (w - 1.0) + 0.02) ? w - 0.03 : young_omega(rate, w);
+            wn = std::min(1.9, std::max(1.0, wn));
+            s->om[grp] = w + 0.5 * (wn - w);
+        }
+        if (finite && conv) {
+            for (int f = f0; f < f1; ++f)
+                if (bn2[f] == 0.0) {
+                    const size_t b = 2 * s->g.cs * sizeof(TM);
+                    HIPCHK(s, hipMemsetAsync(f < 3 ? a.md[f] : a.td, 0, b, s->st));
+                }
+            // sweeps that would have sufficed, for the next step's plan: from the
+            // measured rate when there is one; a first batch that converged
+            // without a usable rate halves the plan
+            int suff = done == c.first_plan[grp] ? std::max(1, done / 2) : done;
+            if (rate > 0.0 && rate < 1.0 && worst > 0.0)    // r_done / r_needed = rate^(done - needed)
+                suff = done - (int)std::floor(std::log(worst / rtol) / std::log(rate));
+            s->last_sweeps[grp] = std::max(1, std::min(done, suff));
+            c.active &= ~(1 << grp);
+            continue;
+        }
+        // divergence: not finite or grown 2x over the reference; stall: less than a
+        // 2x reduction over 100 sweeps
+        const bool diverged = !finite || (c.ref[grp] >= 0.0 && worst > 2.0 * c.ref[grp])
+                              || (rate < 0.0 && worst > 2.0 * worst0 && worst0 > 0.0);
+        const bool stalled = c.ref[grp] >= 0.0 && done - c.ref_at[grp] >= 100 && worst > 0.5 * c.ref[grp];
+        if (c.soft_cap > 0 && done >= c.soft_cap && !diverged) {
+            // inner solve of the refinement: stop here, the outer pass takes what it has
+            c.active &= ~(1 << grp);
+            continue;
+        }
+        if (diverged || stalled || done >= s->P.solve_maxit) {
+            if (c.autom) {
+                c.failed |= 1 << grp;
+                c.active &= ~(1 << grp);
+                continue;
+            }
+            if (!finite) return fail(s, HOSC_E_NONFINITE, "non-finite residual in the implicit solve");
+            if (done >= s->P.solve_maxit)
+                return fail(s, HOSC_E_NOCONV, "implicit solve did not converge within solve_maxit sweeps");
+        }
+        if (c.ref[grp] < 0.0 || done - c.ref_at[grp] >= 100) {
+            c.ref[grp] = worst;
+            c.ref_at[grp] = done;
+        }
+        int next = std::max(2, std::min(done, 64));
+        if (rate > 0.0 && rate < 1.0)
+            next = (int)std::min(256.0, std::max(2.0, std::ceil(std::log(rtol / worst) / std::log(rate)) + 1.0));
+        c.plan[grp] = s->P.check_every > 0 ? s->P.check_every : next;
+        c.plan[grp] = std::min(c.plan[grp], std::max(1, s->P.solve_maxit - done));
+    }
+    c.batch += 1;
+    return HOSC_OK;
+}
+
+// the constant s/C of the scaled energy rows
+double theta_st(const hosc_solver *s)
+{
+    const double ct = s->g.h2 / 12.0 - s->P.dt / 2.0;
+    const double Ct = 1.0 - 6.0 * ct * s->g.invh2;
+    return (ct * s->g.invh2) / Ct;
+}
+
+// Single-cavity solve: batches of sweeps on the solver's stream, a host check after each.
 template <typename TM>
 hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *failed, SweepArgs<TM> a, double rtol,
                     bool inner = false)
 {
-    // inner solves of the refinement: at most 200 sweeps, and no relaxation update
-    // from a first batch (a short batch that starts from zero measures the start-up
-    // transient, not the asymptotic contraction Young's relation needs)
-    const int soft_cap = inner ? 200 : 0;
-    const double ct = s->g.h2 / 12.0 - s->P.dt / 2.0;
-    const double Ct = 1.0 - 6.0 * ct * s->g.invh2;
-    const double st = (ct * s->g.invh2) / Ct;
-    const bool autom = s->P.solver == HOSC_SOLVER_AUTO;
-    const bool adapt = s->P.omega == 0.0;
-    static const unsigned kStore[2] = {0x7u, 0x8u};   // residual components of each group
-    int active = mask;
+    const double st = theta_st(s);
+    SorCtl c;
+    sor_begin(s, c, mask, rtol, inner);
     *failed = 0;
-    double ref[2] = {-1.0, -1.0};
-    int ref_at[2] = {0, 0};
-    int plan[2] = {0, 0};
-    int swept[2] = {0, 0};      // sweeps of this call (o.sweeps also counts earlier calls of the step)
-    for (int grp = 0; grp < 2; ++grp)
-        plan[grp] = s->P.check_every > 0 ? s->P.check_every : std::max(2, s->last_sweeps[grp]);
-    const int first_plan[2] = {plan[0], plan[1]};
-    if (adapt && s->step == 0) {
-        // first step after a state was set: seed the relaxation from the dominance
-        // monitor of the assembly, a Gershgorin bound mu on the Jacobi radius
+    if (sor_wants_seed(s, c)) {
         HIPCHK(s, hipMemcpyAsync(s->hbuf + 44, s->red + 44, 2 * sizeof(double), hipMemcpyDeviceToHost, s->st));
         HIPCHK(s, hipStreamSynchronize(s->st));
-        for (int grp = 0; grp < 2; ++grp) {
-            const double mu = std::min(0.98, s->hbuf[44 + grp]);
-            if (mu > 0.0 && std::isfinite(mu)) s->om[grp] = 2.0 / (1.0 + std::sqrt(1.0 - mu * mu));
-        }
+        sor_seed(s, s->hbuf + 44);
     }
-    for (int batch = 0; active; ++batch) {
-        int nsw = 0;
-        for (int grp = 0; grp < 2; ++grp)
-            if (active & (1 << grp)) nsw = std::max(nsw, plan[grp]);
+    while (c.active) {
+        const int nsw = sor_batch_sweeps(c);
         hosc_status r = timed_begin(s);
         if (r) return r;
         double bytes = 0.0;
         for (int q = 0; q < nsw; ++q) {
-            int m = 0;
-            unsigned store = 0, store0 = 0;
-            for (int grp = 0; grp < 2; ++grp) {
-                if (!(active & (1 << grp)) || q >= plan[grp]) continue;
-                m |= 1 << grp;
-                if (q == plan[grp] - 1) store |= kStore[grp];
-                if (q == 0 && plan[grp] > 1) store0 |= kStore[grp];
-            }
+            int m;
+            unsigned store, store0;
+            sor_sweep_flags(c, q, m, store, store0);
             bytes += 2.0 * sweep_bytes(s->g, m, sizeof(TM));
             for (int colour = 0; colour < 2; ++colour)
                 k_sweep<TM, TM><<<s->L.grd_sw, s->L.blk_sw, 0, s->st>>>(
@@ -586,90 +726,10 @@ hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *f
         HIPCHK(s, hipStreamSynchronize(s->st));
         r = harvest_events(s);
         if (r) return r;
-        o.dominance[0] = s->hbuf[44];
-        o.dominance[1] = s->hbuf[45];
-        if (bn2[0] < 0.0) {
-            for (int f = 0; f < 4; ++f) bn2[f] = s->hbuf[f];
-            for (int f = 0; f < 4; ++f)
-                if (!std::isfinite(bn2[f])) return fail(s, HOSC_E_NONFINITE, "non-finite right-hand side");
-        }
-        for (int grp = 0; grp < 2; ++grp) {
-            if (!(active & (1 << grp))) continue;
-            o.sweeps[grp] += plan[grp];
-            swept[grp] += plan[grp];
-            const int done = swept[grp];
-            const int f0 = grp == 0 ? 0 : 3, f1 = grp == 0 ? 3 : 4;
-            const double om = s->om[grp];
-            bool conv = true, finite = true;
-            double worst = 0.0, worst0 = 0.0;
-            for (int f = f0; f < f1; ++f) {
-                const double r2 = s->hbuf[8 + f] + (1.0 - om) * (1.0 - om) * s->hbuf[4 + f];
-                const double r20 = s->hbuf[36 + f] + (1.0 - om) * (1.0 - om) * s->hbuf[32 + f];
-                if (!std::isfinite(r2)) finite = false;
-                const double rel = bn2[f] > 0.0 ? std::sqrt(r2 / bn2[f]) : 0.0;
-                o.relres[f] = rel;
-                worst = std::max(worst, rel);
-                if (bn2[f] > 0.0) worst0 = std::max(worst0, std::sqrt(r20 / bn2[f]));
-                if (!(bn2[f] == 0.0 || std::sqrt(r2) <= rtol * std::sqrt(bn2[f]))) conv = false;
-            }
-            // contraction per sweep inside this batch (first vs last sweep)
-            double rate = -1.0;
-            if (finite && plan[grp] > 1 && worst0 > 0.0 && worst > 0.0 && worst < worst0)
-                rate = std::pow(worst / worst0, 1.0 / (double)(plan[grp] - 1));
-            if (adapt && rate > 0.0 && rate < 1.0 && plan[grp] >= 4 && !(inner && batch == 0)) {
-                // below the optimum the contraction exceeds w - 1 and Young's relation
-                // gives the optimum; at or past it the contraction is about w - 1: back off
-                const double w = s->om[grp];
-                double wn = (w > 1.05 && rate < (w - 1.0) + 0.02) ? w - 0.03 : young_omega(rate, w);
-                wn = std::min(1.9, std::max(1.0, wn));
-                s->om[grp] = w + 0.5 * (wn - w);
-            }
-            if (finite && conv) {
-                for (int f = f0; f < f1; ++f)
-                    if (bn2[f] == 0.0) {
-                        const size_t b = 2 * s->g.cs * sizeof(TM);
-                        HIPCHK(s, hipMemsetAsync(f < 3 ? a.md[f] : a.td, 0, b, s->st));
-                    }
-                // sweeps that would have sufficed, for the next step's plan: from the
-                // measured rate when there is one; a first batch that converged
-                // without a usable rate halves the plan
-                int suff = done == first_plan[grp] ? std::max(1, done / 2) : done;
-                if (rate > 0.0 && rate < 1.0 && worst > 0.0)    // r_done / r_needed = rate^(done - needed)
-                    suff = done - (int)std::floor(std::log(worst / rtol) / std::log(rate));
-                s->last_sweeps[grp] = std::max(1, std::min(done, suff));
-                active &= ~(1 << grp);
-                continue;
-            }
-            // divergence: not finite or grown 2x over the reference; stall: less than a
-            // 2x reduction over 100 sweeps
-            const bool diverged = !finite || (ref[grp] >= 0.0 && worst > 2.0 * ref[grp]) || (rate < 0.0 && worst > 2.0 * worst0 && worst0 > 0.0);
-            const bool stalled = ref[grp] >= 0.0 && done - ref_at[grp] >= 100 && worst > 0.5 * ref[grp];
-            if (soft_cap > 0 && done >= soft_cap && !diverged) {
-                // inner solve of the refinement: stop here, the outer pass takes what it has
-                active &= ~(1 << grp);
-                continue;
-            }
-            if (diverged || stalled || done >= s->P.solve_maxit) {
-                if (autom) {
-                    *failed |= 1 << grp;
-                    active &= ~(1 << grp);
-                    continue;
-                }
-                if (!finite) return fail(s, HOSC_E_NONFINITE, "non-finite residual in the implicit solve");
-                if (done >= s->P.solve_maxit)
-                    return fail(s, HOSC_E_NOCONV, "implicit solve did not converge within solve_maxit sweeps");
-            }
-            if (ref[grp] < 0.0 || done - ref_at[grp] >= 100) {
-                ref[grp] = worst;
-                ref_at[grp] = done;
-            }
-            int next = std::max(2, std::min(done, 64));
-            if (rate > 0.0 && rate < 1.0)
-                next = (int)std::min(256.0, std::max(2.0, std::ceil(std::log(rtol / worst) / std::log(rate)) + 1.0));
-            plan[grp] = s->P.check_every > 0 ? s->P.check_every : next;
-            plan[grp] = std::min(plan[grp], std::max(1, s->P.solve_maxit - done));
-        }
+        r = sor_decide<TM>(s, c, s->hbuf, bn2, o, a);
+        if (r) return r;
     }
+    *failed = c.failed;
     return HOSC_OK;
 }
 
@@ -800,12 +860,14 @@ hosc_status run_bicg(hosc_solver *s, int mask, double bn2[4], SolveOut &o, BicgA
 // launch per colour); converged groups stop, the others solve B e = r for the FP32
 // correction with FP32 red-black sweeps to a relative 1e-5 or what the tolerance
 // still needs.  Groups whose inner solve fails (auto mode) are returned in *to_bicg.
-hosc_status solve_refined(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *to_bicg)
+// Iterative refinement of the precision mode: FP64 residual of the FP64 rows, FP32
+// inner red-black solve of B e = r, fold, until the FP64 residual meets rtol.
+struct RefCtl {
+    int active = 0, outer = 0, to_bicg = 0;
+};
+
+RefineArgs<double> refine_args(hosc_solver *s)
 {
-    const double rtol = s->P.solve_rtol;
-    const double ct = s->g.h2 / 12.0 - s->P.dt / 2.0;
-    const double Ct = 1.0 - 6.0 * ct * s->g.invh2;
-    const double st = (ct * s->g.invh2) / Ct;
     RefineArgs<double> ra;
     ra.ms = s->ms;
     for (int d = 0; d < 3; ++d) {
@@ -820,16 +882,88 @@ hosc_status solve_refined(hosc_solver *s, int mask, double bn2[4], SolveOut &o, 
         ra.e[f] = s->fe[f];
         ra.r[f] = s->fr[f];
     }
-    int active = mask;
+    return ra;
+}
+
+// Decisions after a residual pass, from the reduction block hb (the cavity's
+// red[0..55]: ||b/C||^2 at 0..3, dominance at 44..45, FP64 residual sums of the
+// red and black halves at 48..51 and 52..55).  Leaves in c.active the groups that
+// need another inner solve, with its right-hand-side norms and tolerance.
+hosc_status refine_decide(hosc_solver *s, RefCtl &c, const double *hb, double bn2[4], SolveOut &o, double inner_bn2[4],
+                          double *inner_rtol)
+{
+    if (c.outer > 50) return fail(s, HOSC_E_NOCONV, "iterative refinement did not converge in 50 passes");
+    const double rtol = s->P.solve_rtol;
+    o.dominance[0] = hb[44];
+    o.dominance[1] = hb[45];
+    if (bn2[0] < 0.0) {
+        for (int f = 0; f < 4; ++f) bn2[f] = hb[f];
+        for (int f = 0; f < 4; ++f)
+            if (!std::isfinite(bn2[f])) return fail(s, HOSC_E_NONFINITE, "non-finite right-hand side");
+    }
+    double rr[4], target = 0.1;
+    for (int f = 0; f < 4; ++f) {
+        rr[f] = hb[48 + f] + hb[52 + f];
+        inner_bn2[f] = 0.0;
+    }
+    for (int grp = 0; grp < 2; ++grp) {
+        if (!(c.active & (1 << grp))) continue;
+        const int f0 = grp == 0 ? 0 : 3, f1 = grp == 0 ? 3 : 4;
+        bool conv = true, zero = true;
+        for (int f = f0; f < f1; ++f) {
+            if (!std::isfinite(rr[f])) return fail(s, HOSC_E_NONFINITE, "non-finite residual in refinement");
+            zero = zero && bn2[f] == 0.0;
+            o.relres[f] = bn2[f] > 0.0 ? std::sqrt(rr[f] / bn2[f]) : 0.0;
+            if (!(bn2[f] == 0.0 || std::sqrt(rr[f]) <= rtol * std::sqrt(bn2[f]))) conv = false;
+            inner_bn2[f] = rr[f];
+            if (bn2[f] > 0.0 && rr[f] > 0.0) target = std::min(target, rtol * std::sqrt(bn2[f] / rr[f]));
+        }
+        if (zero) {     // b = 0: the increment is zero
+            hosc_status r = zero_group(s, grp);
+            if (r) return r;
+        }
+        if (conv || zero) c.active &= ~(1 << grp);
+    }
+    // the inner FP32 solve aims at the reduction still needed, but not below 1e-5
+    // (its own rounding floor is near 1e-6)
+    *inner_rtol = std::max(1e-5, 0.3 * target);
+    return HOSC_OK;
+}
+
+// After an inner solve: groups whose FP32 solve failed leave the refinement and go
+// to the BiCGSTAB fallback.
+hosc_status refine_after_inner(hosc_solver *s, RefCtl &c, int failed)
+{
+    if (failed) {
+        for (int grp = 0; grp < 2; ++grp) {
+            if (!(failed & (1 << grp))) continue;
+            const int f0 = grp == 0 ? 0 : 3, f1 = grp == 0 ? 3 : 4;
+            for (int f = f0; f < f1; ++f) {
+                HIPCHK(s, hipMemsetAsync(s->fe[f], 0, 2 * s->g.cs * sizeof(float), s->st));
+                HIPCHK(s, hipMemsetAsync(s->fr[f], 0, 2 * s->g.cs * sizeof(float), s->st));
+            }
+        }
+        c.to_bicg |= failed;
+        c.active &= ~failed;
+    }
+    c.outer += 1;
+    return HOSC_OK;
+}
+
+hosc_status solve_refined(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *to_bicg)
+{
+    const double st = theta_st(s);
+    const RefineArgs<double> ra = refine_args(s);
+    RefCtl c;
+    c.active = mask;
     *to_bicg = 0;
-    for (int outer = 0; active; ++outer) {
-        if (outer > 50) return fail(s, HOSC_E_NOCONV, "iterative refinement did not converge in 50 passes");
+    while (c.active) {
         hosc_status r = timed_begin(s);
         if (r) return r;
         for (int colour = 0; colour < 2; ++colour)
-            k_refine_residual<double><<<s->L.grd_sw, s->L.blk_sw, 0, s->st>>>(s->g, colour, active, st, ra,
+            k_refine_residual<double><<<s->L.grd_sw, s->L.blk_sw, 0, s->st>>>(s->g, colour, c.active, st, ra,
                                                                             colour ? s->partB : s->partR);
-        r = timed_end(s, 3, 2.0 * refine_bytes(s->g, active), 2);
+        r = timed_end(s, 3, 2.0 * refine_bytes(s->g, c.active), 2);
         if (r) return r;
         r = launch_check(s, "refine residual");
         if (r) return r;
@@ -839,80 +973,43 @@ hosc_status solve_refined(hosc_solver *s, int mask, double bn2[4], SolveOut &o, 
         HIPCHK(s, hipStreamSynchronize(s->st));
         r = harvest_events(s);
         if (r) return r;
-        o.dominance[0] = s->hbuf[44];
-        o.dominance[1] = s->hbuf[45];
-        if (bn2[0] < 0.0) {
-            for (int f = 0; f < 4; ++f) bn2[f] = s->hbuf[f];
-            for (int f = 0; f < 4; ++f)
-                if (!std::isfinite(bn2[f])) return fail(s, HOSC_E_NONFINITE, "non-finite right-hand side");
-        }
-        double rr[4], inner_bn2[4] = {0, 0, 0, 0};
-        double target = 0.1;
-        for (int f = 0; f < 4; ++f) rr[f] = s->hbuf[48 + f] + s->hbuf[52 + f];
-        for (int grp = 0; grp < 2; ++grp) {
-            if (!(active & (1 << grp))) continue;
-            const int f0 = grp == 0 ? 0 : 3, f1 = grp == 0 ? 3 : 4;
-            bool conv = true, zero = true;
-            for (int f = f0; f < f1; ++f) {
-                if (!std::isfinite(rr[f])) return fail(s, HOSC_E_NONFINITE, "non-finite residual in refinement");
-                zero = zero && bn2[f] == 0.0;
-                o.relres[f] = bn2[f] > 0.0 ? std::sqrt(rr[f] / bn2[f]) : 0.0;
-                if (!(bn2[f] == 0.0 || std::sqrt(rr[f]) <= rtol * std::sqrt(bn2[f]))) conv = false;
-                inner_bn2[f] = rr[f];
-                if (bn2[f] > 0.0 && rr[f] > 0.0) target = std::min(target, rtol * std::sqrt(bn2[f] / rr[f]));
-            }
-            if (zero) {     // b = 0: the increment is zero
-                r = zero_group(s, grp);
-                if (r) return r;
-            }
-            if (conv || zero) active &= ~(1 << grp);
-        }
-        if (!active) break;
-        int failed = 0;
-        r = run_sor<float>(s, active, inner_bn2, o, &failed, sweep_args_fp32(s), std::max(1e-5, 0.3 * target), true);
+        double inner_bn2[4], inner_rtol;
+        r = refine_decide(s, c, s->hbuf, bn2, o, inner_bn2, &inner_rtol);
         if (r) return r;
-        if (failed) {
-            for (int grp = 0; grp < 2; ++grp) {
-                if (!(failed & (1 << grp))) continue;
-                const int f0 = grp == 0 ? 0 : 3, f1 = grp == 0 ? 3 : 4;
-                for (int f = f0; f < f1; ++f) {
-                    HIPCHK(s, hipMemsetAsync(s->fe[f], 0, 2 * s->g.cs * sizeof(float), s->st));
-                    HIPCHK(s, hipMemsetAsync(s->fr[f], 0, 2 * s->g.cs * sizeof(float), s->st));
-                }
-            }
-            *to_bicg |= failed;
-            active &= ~failed;
-        }
+        if (!c.active) break;
+        int failed = 0;
+        r = run_sor<float>(s, c.active, inner_bn2, o, &failed, sweep_args_fp32(s), inner_rtol, true);
+        if (r) return r;
+        r = refine_after_inner(s, c, failed);
+        if (r) return r;
     }
+    *to_bicg = c.to_bicg;
     return HOSC_OK;
 }
 
-// Solve the momentum (3 right-hand sides) and energy systems of the step.
-hosc_status solve(hosc_solver *s, SolveOut &o)
+// Groups solved by SOR (sor_mask) and by BiCGSTAB (bicg_mask) this step.
+void solve_masks(const hosc_solver *s, int &sor_mask, int &bicg_mask)
 {
-    // ||b/C||^2 of the four systems (reduced after the assembly into red[0..3]) are
-    // read by the solvers together with their first convergence check
-    double bn2[4] = {-1.0, -1.0, -1.0, -1.0};
-    int sor_mask = 0, bicg_mask = 0;
+    sor_mask = bicg_mask = 0;
     for (int grp = 0; grp < 2; ++grp) {
         const bool use_bicg = s->P.solver == HOSC_SOLVER_BICGSTAB
                               || (s->P.solver == HOSC_SOLVER_AUTO && s->step < s->bicg_until[grp]);
         if (use_bicg) bicg_mask |= 1 << grp;
         else sor_mask |= 1 << grp;
     }
-    if (sor_mask) {
-        int failed = 0;
-        hosc_status r = s->fp32 ? solve_refined(s, sor_mask, bn2, o, &failed)
-                                : run_sor<double>(s, sor_mask, bn2, o, &failed, sweep_args(s), s->P.solve_rtol);
-        if (r) return r;
-        for (int grp = 0; grp < 2; ++grp)
-            if (failed & (1 << grp)) {
-                r = zero_group(s, grp);     // restart from zero: the SOR iterate may have diverged
-                if (r) return r;
-                s->bicg_until[grp] = s->step + 50;
-                bicg_mask |= 1 << grp;
-            }
-    }
+}
+
+// Groups whose SOR solve failed restart from zero under BiCGSTAB (sticky for 50
+// steps); then the BiCGSTAB groups are solved.
+hosc_status solve_finish(hosc_solver *s, int failed, int bicg_mask, double bn2[4], SolveOut &o)
+{
+    for (int grp = 0; grp < 2; ++grp)
+        if (failed & (1 << grp)) {
+            hosc_status r = zero_group(s, grp);     // the SOR iterate may have diverged
+            if (r) return r;
+            s->bicg_until[grp] = s->step + 50;
+            bicg_mask |= 1 << grp;
+        }
     hosc_status r = run_bicg<double>(s, bicg_mask, bn2, o, bicg_args<double>(s, s->ms, s->ma, s->ta));
     if (r) return r;
     s->last_bicg[0] = o.bicg[0];
@@ -920,7 +1017,24 @@ hosc_status solve(hosc_solver *s, SolveOut &o)
     return HOSC_OK;
 }
 
-hosc_status one_step(hosc_solver *s, hosc_step_info *info)
+hosc_status solve(hosc_solver *s, SolveOut &o)
+{
+    // ||b/C||^2 of the four systems (reduced after the assembly into red[0..3]) are
+    // read by the solvers together with their first convergence check
+    double bn2[4] = {-1.0, -1.0, -1.0, -1.0};
+    int sor_mask, bicg_mask, failed = 0;
+    solve_masks(s, sor_mask, bicg_mask);
+    if (sor_mask) {
+        hosc_status r = s->fp32 ? solve_refined(s, sor_mask, bn2, o, &failed)
+                                : run_sor<double>(s, sor_mask, bn2, o, &failed, sweep_args(s), s->P.solve_rtol);
+        if (r) return r;
+    }
+    return solve_finish(s, failed, bicg_mask, bn2, o);
+}
+
+// eta, E*, assembly and its reductions (||b/C||^2 into red[0..3], dominance into
+// red[44..45]); launches only.
+hosc_status pre_solve(hosc_solver *s)
 {
     hosc_status r = stage_sources(s, true);
     if (r) return r;
@@ -932,13 +1046,13 @@ hosc_status one_step(hosc_solver *s, hosc_step_info *info)
         ca.ta[d] = s->ta[d];
     }
     ca.tb = s->tb;
-    r = timed_begin(s);
-    if (r) return r;
     ca.fms = s->fms;
     for (int d = 0; d < 3; ++d) {
         ca.fma[d] = s->fma[d];
         ca.fta[d] = s->fta[d];
     }
+    r = timed_begin(s);
+    if (r) return r;
     k_assemble<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, s->ph, s->u, s->v, s->w, s->T, s->eta, s->E[0],
                                                          s->E[1], s->E[2], s->u2, s->v2, s->w2, s->etap, s->Ep[0],
                                                          s->Ep[1], s->Ep[2], ca, s->partR, s->partB);
@@ -946,11 +1060,13 @@ hosc_status one_step(hosc_solver *s, hosc_step_info *info)
     if (r) return r;
     k_reduce<<<1, 1024, 0, s->st>>>(s->partR, (int)s->L.nb_int, 4, 0, s->red);
     k_reduce<<<1, 1024, 0, s->st>>>(s->partB, (int)s->L.nb_int, 2, 1, s->red + 44);
-    r = launch_check(s, "assemble");
-    if (r) return r;
-    SolveOut so;
-    r = solve(s, so);
-    if (r) return r;
+    return launch_check(s, "assemble");
+}
+
+// Update, theta walls, divergence (with the correction when it is not gated) and
+// their reductions into red[12..22]; launches only.
+hosc_status post_launch(hosc_solver *s)
+{
     // update: u, v, w into the level n-1 buffers (which become level n+1)
     k_update<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, s->u, s->v, s->w, s->u2, s->v2, s->w2, s->T, s->md[0],
                                                        s->md[1], s->md[2], s->td, s->partR);
@@ -961,11 +1077,15 @@ hosc_status one_step(hosc_solver *s, hosc_step_info *info)
     k_divergence<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, s->ph, s->u2, s->v2, s->w2, s->p,
                                                            gate ? s->dbg : nullptr, gate ? 0 : 1, s->partR);
     k_reduce<<<1, 1024, 0, s->st>>>(s->partR, (int)s->L.nb_int, 1, 1, s->red + 22);
-    r = launch_check(s, "update/divergence");
-    if (r) return r;
-    HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red + 12, 11 * sizeof(double), hipMemcpyDeviceToHost, s->st));
-    HIPCHK(s, hipStreamSynchronize(s->st));
-    const double maxdiv = s->hbuf[10];
+    return launch_check(s, "update/divergence");
+}
+
+// Finish the step from hb = red[12..22] read back: gated pressure correction,
+// pressure walls, level swap, steady residual and the step report.
+hosc_status post_finish(hosc_solver *s, const double *hb, const SolveOut &so, hosc_step_info *info)
+{
+    const bool gate = s->P.div_tol > 0.0;
+    const double maxdiv = hb[10];
     int corrected = 0;
     if (gate) {
         if (maxdiv > s->P.div_tol) {
@@ -976,7 +1096,7 @@ hosc_status one_step(hosc_solver *s, hosc_step_info *info)
         corrected = 1;
     }
     if (corrected) k_p_walls<<<s->L.grd_face, s->L.blk_face, 0, s->st>>>(s->g, s->p);
-    r = launch_check(s, "pressure");
+    hosc_status r = launch_check(s, "pressure");
     if (r) return r;
     std::swap(s->u, s->u2);
     std::swap(s->v, s->v2);
@@ -984,7 +1104,6 @@ hosc_status one_step(hosc_solver *s, hosc_step_info *info)
     std::swap(s->eta, s->etap);
     for (int d = 0; d < 3; ++d) std::swap(s->E[d], s->Ep[d]);
     s->step += 1;
-    const double *hb = s->hbuf;
     auto ratio = [](double num, double den) {
         if (den > 0.0) return std::sqrt(num) / std::sqrt(den);
         return num == 0.0 ? 0.0 : HUGE_VAL;
@@ -1016,6 +1135,447 @@ hosc_status one_step(hosc_solver *s, hosc_step_info *info)
     }
     if (!finite) return fail(s, HOSC_E_NONFINITE, "non-finite steady residual or divergence");
     return HOSC_OK;
+}
+
+hosc_status one_step(hosc_solver *s, hosc_step_info *info)
+{
+    hosc_status r = pre_solve(s);
+    if (r) return r;
+    SolveOut so;
+    r = solve(s, so);
+    if (r) return r;
+    r = post_launch(s);
+    if (r) return r;
+    HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red + 12, 11 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    return post_finish(s, s->hbuf, so, info);
+}
+
+// ---------------------------------------------------------------------------
+// Fused multi-cavity execution (batches and the server).  The per-cavity phases
+// above are reused unchanged; the solver phases, which dominate, run as fused
+// launches over every cavity that still iterates: one persistent launch per
+// half-sweep, one per refinement-residual colour, one launch for all the
+// reductions and one gather + host copy per convergence check.
+// ---------------------------------------------------------------------------
+constexpr size_t kCavEntry = 512;     // bytes reserved per cavity for a fused-launch descriptor
+
+struct Fused {
+    int cap = 0;                      // cavities the tables hold
+    hipStream_t st = nullptr;
+    int grid = 1024;                  // persistent workgroups per fused launch (0: one per tile)
+    // one contiguous table block, mirrored in pinned host memory: map | cav | jobs | src
+    char *d_tab = nullptr, *h_tab = nullptr;
+    size_t off_cav = 0, off_jobs = 0, off_src = 0, tab_bytes = 0;
+    double *d_gather = nullptr, *h_gather = nullptr;
+    std::string err;
+    bool prof = false;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hosc_perf perf{};
+    TileMap *hmap() { return reinterpret_cast<TileMap *>(h_tab); }
+    template <typename T> T *hcav() { return reinterpret_cast<T *>(h_tab + off_cav); }
+    ReduceJob *hjobs() { return reinterpret_cast<ReduceJob *>(h_tab + off_jobs); }
+    const double **hsrc() { return reinterpret_cast<const double **>(h_tab + off_src); }
+    const TileMap *dmap() const { return reinterpret_cast<const TileMap *>(d_tab); }
+    template <typename T> const T *dcav() const { return reinterpret_cast<const T *>(d_tab + off_cav); }
+    const ReduceJob *djobs() const { return reinterpret_cast<const ReduceJob *>(d_tab + off_jobs); }
+    const double *const *dsrc() const { return reinterpret_cast<const double *const *>(d_tab + off_src); }
+};
+
+size_t fused_table_bytes(int cap)
+{
+    return align_up((size_t)cap * sizeof(TileMap)) + align_up((size_t)cap * kCavEntry)
+           + align_up((size_t)cap * 4 * sizeof(ReduceJob)) + align_up((size_t)cap * sizeof(double *));
+}
+size_t fused_device_bytes(int cap) { return fused_table_bytes(cap) + align_up((size_t)cap * 64 * sizeof(double)); }
+
+hosc_status ffail(Fused &F, hosc_status st, const std::string &msg)
+{
+    F.err = msg;
+    return st;
+}
+#define FHIPCHK(F, call)                                                                           \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return ffail((F), HOSC_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+// d_dev: device block of fused_device_bytes(cap), 256-byte aligned.
+hosc_status fused_init(Fused &F, int cap, char *d_dev, hipStream_t st)
+{
+    static_assert(sizeof(FusedSweepCav<double, double>) <= kCavEntry, "descriptor too large");
+    static_assert(sizeof(FusedSweepCav<float, float>) <= kCavEntry, "descriptor too large");
+    static_assert(sizeof(FusedRefineCav<double>) <= kCavEntry, "descriptor too large");
+    F.cap = cap;
+    F.st = st;
+    F.off_cav = align_up((size_t)cap * sizeof(TileMap));
+    F.off_jobs = F.off_cav + align_up((size_t)cap * kCavEntry);
+    F.off_src = F.off_jobs + align_up((size_t)cap * 4 * sizeof(ReduceJob));
+    F.tab_bytes = fused_table_bytes(cap);
+    F.d_tab = d_dev;
+    F.d_gather = reinterpret_cast<double *>(d_dev + F.tab_bytes);
+    FHIPCHK(F, hipHostMalloc(reinterpret_cast<void **>(&F.h_tab), F.tab_bytes));
+    FHIPCHK(F, hipHostMalloc(reinterpret_cast<void **>(&F.h_gather), (size_t)cap * 64 * sizeof(double)));
+    std::memset(F.h_tab, 0, F.tab_bytes);
+    FHIPCHK(F, hipEventCreate(&F.ev[0]));
+    FHIPCHK(F, hipEventCreate(&F.ev[1]));
+    return HOSC_OK;
+}
+void fused_free(Fused &F)
+{
+    if (F.h_tab) (void)hipHostFree(F.h_tab);
+    if (F.h_gather) (void)hipHostFree(F.h_gather);
+    for (hipEvent_t &e : F.ev)
+        if (e) (void)hipEventDestroy(e);
+    F.h_tab = nullptr;
+    F.h_gather = nullptr;
+}
+
+void tile_map(TileMap &m, const hosc_solver *s, int &total)
+{
+    m.tile0 = total;
+    m.tiles_x = (int)s->L.grd_sw.x;
+    m.tiles_y = (int)s->L.grd_sw.y;
+    m.tiles = m.tiles_x * m.tiles_y * (int)s->L.grd_sw.z;
+    m.tx = (int)s->L.blk_sw.x;
+    m.ty = (int)s->L.blk_sw.y;
+    total += m.tiles;
+}
+
+int fused_grid(const Fused &F, int total) { return F.grid > 0 ? std::min(F.grid, total) : total; }
+
+// Upload the table block and run the reductions in h_jobs[0..njobs), then gather
+// len doubles from each of h_src[0..nsrc) into h_gather (one host copy, synchronised).
+hosc_status fused_reduce_gather(Fused &F, int njobs, int nsrc, int len)
+{
+    if (njobs > 0) k_reduce_jobs<<<njobs, 1024, 0, F.st>>>(F.djobs());
+    k_gather<<<nsrc, 64, 0, F.st>>>(F.dsrc(), len, F.d_gather);
+    FHIPCHK(F, hipGetLastError());
+    FHIPCHK(F, hipMemcpyAsync(F.h_gather, F.d_gather, (size_t)nsrc * len * sizeof(double), hipMemcpyDeviceToHost, F.st));
+    FHIPCHK(F, hipStreamSynchronize(F.st));
+    return HOSC_OK;
+}
+
+void add_job(ReduceJob *jobs, int &n, const double *part, int nb, int nc, int op, double *out)
+{
+    ReduceJob &j = jobs[n++];
+    j.part = part;
+    j.nb = nb;
+    j.nc = nc;
+    j.op = op;
+    j.out = out;
+}
+
+template <typename TM> SweepArgs<TM> cavity_sweep_args(hosc_solver *s);
+template <> SweepArgs<double> cavity_sweep_args<double>(hosc_solver *s) { return sweep_args(s); }
+template <> SweepArgs<float> cavity_sweep_args<float>(hosc_solver *s) { return sweep_args_fp32(s); }
+
+// Batched red-black SOR over cavities cav[0..n): cavity i solves the groups in
+// mask[i] to rtol[i] with exactly the control of run_sor.  A cavity whose control
+// reports an error gets it in err[i] and leaves the solve; the others go on.
+template <typename TM>
+hosc_status fused_sor(Fused &F, hosc_solver *const *cav, int n, const int *mask, double (*bn2)[4], SolveOut *o,
+                      int *failed, const double *rtol, bool inner, hosc_status *err)
+{
+    std::vector<SorCtl> c(n);
+    std::vector<SweepArgs<TM>> args(n);
+    std::vector<int> act(n);
+    bool seed = false;
+    for (int i = 0; i < n; ++i) {
+        failed[i] = 0;
+        if (err[i] || !mask[i]) continue;
+        sor_begin(cav[i], c[i], mask[i], rtol[i], inner);
+        args[i] = cavity_sweep_args<TM>(cav[i]);
+        seed = seed || sor_wants_seed(cav[i], c[i]);
+    }
+    if (seed) {
+        int ns = 0;
+        for (int i = 0; i < n; ++i)
+            if (!err[i] && mask[i]) {
+                F.hsrc()[ns] = cav[i]->red;
+                act[ns++] = i;
+            }
+        FHIPCHK(F, hipMemcpyAsync(F.d_tab, F.h_tab, F.tab_bytes, hipMemcpyHostToDevice, F.st));
+        hosc_status r = fused_reduce_gather(F, 0, ns, 48);
+        if (r) return r;
+        for (int a = 0; a < ns; ++a)
+            if (sor_wants_seed(cav[act[a]], c[act[a]])) sor_seed(cav[act[a]], F.h_gather + 48 * a + 44);
+    }
+    for (;;) {
+        int nact = 0, total = 0, nsw = 0, nj = 0;
+        double bytes = 0.0;
+        for (int i = 0; i < n; ++i) {
+            if (err[i] || !c[i].active) continue;
+            hosc_solver *s = cav[i];
+            tile_map(F.hmap()[nact], s, total);
+            FusedSweepCav<TM, TM> &cv = F.hcav<FusedSweepCav<TM, TM>>()[nact];
+            cv.g = s->g;
+            cv.a = args[i];
+            cv.omega_m = (TM)s->om[0];
+            cv.omega_t = (TM)s->om[1];
+            cv.st = (TM)theta_st(s);
+            cv.plan_m = (c[i].active & 1) ? c[i].plan[0] : 0;
+            cv.plan_t = (c[i].active & 2) ? c[i].plan[1] : 0;
+            cv.part[0] = s->partR;
+            cv.part[1] = s->partB;
+            cv.part0[0] = s->partR0;
+            cv.part0[1] = s->partB0;
+            const int nb = (int)s->L.nb_sw;
+            add_job(F.hjobs(), nj, s->partR, nb, 4, 0, s->red + 4);
+            add_job(F.hjobs(), nj, s->partB, nb, 4, 0, s->red + 8);
+            add_job(F.hjobs(), nj, s->partR0, nb, 4, 0, s->red + 32);
+            add_job(F.hjobs(), nj, s->partB0, nb, 4, 0, s->red + 36);
+            F.hsrc()[nact] = s->red;
+            const int ns = sor_batch_sweeps(c[i]);
+            nsw = std::max(nsw, ns);
+            for (int q = 0; q < ns; ++q) {
+                int m;
+                unsigned a0, a1;
+                sor_sweep_flags(c[i], q, m, a0, a1);
+                bytes += 2.0 * sweep_bytes(s->g, m, sizeof(TM));
+            }
+            act[nact++] = i;
+        }
+        if (!nact) break;
+        FHIPCHK(F, hipMemcpyAsync(F.d_tab, F.h_tab, F.tab_bytes, hipMemcpyHostToDevice, F.st));
+        const int G = fused_grid(F, total);
+        if (F.prof) FHIPCHK(F, hipEventRecord(F.ev[0], F.st));
+        for (int q = 0; q < nsw; ++q)
+            for (int colour = 0; colour < 2; ++colour)
+                k_sweep_fused<TM, TM><<<G, 256, 0, F.st>>>(F.dmap(), F.dcav<FusedSweepCav<TM, TM>>(), nact, total,
+                                                           colour, q);
+        if (F.prof) FHIPCHK(F, hipEventRecord(F.ev[1], F.st));
+        FHIPCHK(F, hipGetLastError());
+        hosc_status r = fused_reduce_gather(F, nj, nact, 48);
+        if (r) return r;
+        if (F.prof) {
+            float ms = 0.0f;
+            FHIPCHK(F, hipEventElapsedTime(&ms, F.ev[0], F.ev[1]));
+            F.perf.sweep_launches += 2 * nsw;
+            F.perf.sweep_ms += ms;
+            F.perf.sweep_bytes += bytes;
+        }
+        for (int a = 0; a < nact; ++a) {
+            const int i = act[a];
+            r = sor_decide<TM>(cav[i], c[i], F.h_gather + 48 * a, bn2[i], o[i], args[i]);
+            if (r) {
+                err[i] = r;
+                c[i].active = 0;
+            }
+        }
+    }
+    for (int i = 0; i < n; ++i) failed[i] = c[i].failed;
+    return HOSC_OK;
+}
+
+// Batched iterative refinement (precision mode), the control of solve_refined.
+hosc_status fused_refined(Fused &F, hosc_solver *const *cav, int n, const int *mask, double (*bn2)[4], SolveOut *o,
+                          int *to_bicg, hosc_status *err)
+{
+    std::vector<RefCtl> rc(n);
+    std::vector<int> act(n), imask(n), ifailed(n);
+    std::vector<double> irtol(n);
+    std::vector<std::array<double, 4>> ibn2(n);
+    for (int i = 0; i < n; ++i) rc[i].active = err[i] ? 0 : mask[i];
+    for (;;) {
+        int nact = 0, total = 0, nj = 0;
+        double bytes = 0.0;
+        for (int i = 0; i < n; ++i) {
+            if (err[i] || !rc[i].active) continue;
+            hosc_solver *s = cav[i];
+            tile_map(F.hmap()[nact], s, total);
+            FusedRefineCav<double> &cv = F.hcav<FusedRefineCav<double>>()[nact];
+            cv.g = s->g;
+            cv.a = refine_args(s);
+            cv.st = theta_st(s);
+            cv.mask = rc[i].active;
+            cv.part[0] = s->partR;
+            cv.part[1] = s->partB;
+            const int nb = (int)s->L.nb_sw;
+            add_job(F.hjobs(), nj, s->partR, nb, 4, 0, s->red + 48);
+            add_job(F.hjobs(), nj, s->partB, nb, 4, 0, s->red + 52);
+            F.hsrc()[nact] = s->red;
+            bytes += 2.0 * refine_bytes(s->g, rc[i].active);
+            act[nact++] = i;
+        }
+        if (!nact) break;
+        FHIPCHK(F, hipMemcpyAsync(F.d_tab, F.h_tab, F.tab_bytes, hipMemcpyHostToDevice, F.st));
+        const int G = fused_grid(F, total);
+        if (F.prof) FHIPCHK(F, hipEventRecord(F.ev[0], F.st));
+        for (int colour = 0; colour < 2; ++colour)
+            k_refine_fused<double><<<G, 256, 0, F.st>>>(F.dmap(), F.dcav<FusedRefineCav<double>>(), nact, total, colour);
+        if (F.prof) FHIPCHK(F, hipEventRecord(F.ev[1], F.st));
+        FHIPCHK(F, hipGetLastError());
+        hosc_status r = fused_reduce_gather(F, nj, nact, 56);
+        if (r) return r;
+        if (F.prof) {
+            float ms = 0.0f;
+            FHIPCHK(F, hipEventElapsedTime(&ms, F.ev[0], F.ev[1]));
+            F.perf.refine_launches += 2;
+            F.perf.refine_ms += ms;
+            F.perf.refine_bytes += bytes;
+        }
+        for (int i = 0; i < n; ++i) imask[i] = 0;
+        for (int a = 0; a < nact; ++a) {
+            const int i = act[a];
+            r = refine_decide(cav[i], rc[i], F.h_gather + 56 * a, bn2[i], o[i], ibn2[i].data(), &irtol[i]);
+            if (r) {
+                err[i] = r;
+                rc[i].active = 0;
+                continue;
+            }
+            imask[i] = rc[i].active;
+        }
+        std::vector<double> flat(4 * (size_t)n);
+        for (int i = 0; i < n; ++i)
+            for (int f = 0; f < 4; ++f) flat[4 * (size_t)i + f] = ibn2[i][f];
+        r = fused_sor<float>(F, cav, n, imask.data(), reinterpret_cast<double(*)[4]>(flat.data()), o, ifailed.data(),
+                             irtol.data(), true, err);
+        if (r) return r;
+        for (int i = 0; i < n; ++i) {
+            if (!imask[i] || err[i]) continue;
+            r = refine_after_inner(cav[i], rc[i], ifailed[i]);
+            if (r) err[i] = r;
+        }
+    }
+    for (int i = 0; i < n; ++i) to_bicg[i] = rc[i].to_bicg;
+    return HOSC_OK;
+}
+
+// One step of every cavity in cav[0..n) (all of one precision).  Per-cavity
+// failures are returned in err[i] (and make that solver sticky, as hosc_step
+// does); the return value reports failures of the fused machinery itself.
+hosc_status fused_step(Fused &F, hosc_solver *const *cav, int n, hosc_step_info *info, hosc_status *err)
+{
+    std::vector<SolveOut> o(n);
+    std::vector<double> bn2(4 * (size_t)n, -1.0);
+    std::vector<int> sor(n), bic(n), failed(n), act(n);
+    std::vector<double> rtol(n);
+    for (int i = 0; i < n; ++i) {
+        err[i] = HOSC_OK;
+        hosc_solver *s = cav[i];
+        if (!s->has_state) err[i] = fail(s, HOSC_E_STATE, "no state set");
+        else if (s->sticky) err[i] = fail(s, HOSC_E_STATE, "solver is in an error state; set a new state");
+        else err[i] = pre_solve(s);
+        solve_masks(s, sor[i], bic[i]);
+        rtol[i] = s->P.solve_rtol;
+        if (err[i]) sor[i] = bic[i] = 0;
+    }
+    double(*b4)[4] = reinterpret_cast<double(*)[4]>(bn2.data());
+    const bool fp32 = n > 0 && cav[0]->fp32;
+    hosc_status r = fp32 ? fused_refined(F, cav, n, sor.data(), b4, o.data(), failed.data(), err)
+                         : fused_sor<double>(F, cav, n, sor.data(), b4, o.data(), failed.data(), rtol.data(), false, err);
+    if (r) return r;
+    int nact = 0;
+    for (int i = 0; i < n; ++i) {
+        if (err[i]) continue;
+        err[i] = solve_finish(cav[i], failed[i], bic[i], b4[i], o[i]);
+        if (!err[i]) err[i] = post_launch(cav[i]);
+        if (err[i]) continue;
+        F.hsrc()[nact] = cav[i]->red + 12;
+        act[nact++] = i;
+    }
+    if (nact) {
+        FHIPCHK(F, hipMemcpyAsync(F.d_tab + F.off_src, F.h_tab + F.off_src, (size_t)nact * sizeof(double *),
+                                  hipMemcpyHostToDevice, F.st));
+        r = fused_reduce_gather(F, 0, nact, 11);
+        if (r) return r;
+    }
+    for (int a = 0; a < nact; ++a) {
+        const int i = act[a];
+        err[i] = post_finish(cav[i], F.h_gather + 11 * a, o[i], info ? &info[i] : nullptr);
+    }
+    for (int i = 0; i < n; ++i)
+        if (err[i]) {
+            if (err[i] == HOSC_E_NOCONV || err[i] == HOSC_E_NONFINITE) cav[i]->sticky = err[i];
+            if (info) info[i].status = err[i];
+        }
+    return HOSC_OK;
+}
+
+// Time a few fused half-sweep pairs at each candidate schedule and keep the
+// fastest.  Sweeps change the increments, so this runs only on fresh states and
+// zeroes the increments afterwards.
+template <typename TM>
+hosc_status fused_tune(Fused &F, hosc_solver *const *cav, int n, int *best_grid)
+{
+    int total = 0;
+    for (int i = 0; i < n; ++i) {
+        hosc_solver *s = cav[i];
+        tile_map(F.hmap()[i], s, total);
+        FusedSweepCav<TM, TM> &cv = F.hcav<FusedSweepCav<TM, TM>>()[i];
+        cv.g = s->g;
+        cv.a = cavity_sweep_args<TM>(s);
+        cv.omega_m = cv.omega_t = (TM)1;
+        cv.st = (TM)theta_st(s);
+        cv.plan_m = cv.plan_t = 1;
+        cv.part[0] = s->partR;
+        cv.part[1] = s->partB;
+        cv.part0[0] = s->partR0;
+        cv.part0[1] = s->partB0;
+    }
+    FHIPCHK(F, hipMemcpyAsync(F.d_tab, F.h_tab, F.tab_bytes, hipMemcpyHostToDevice, F.st));
+    const int cand[] = {256, 512, 1024, 2048, 4096, 0};
+    double best = HUGE_VAL;
+    int bg = F.grid;
+    for (int g : cand) {
+        const int G = g > 0 ? std::min(g, total) : total;
+        float ms = 0.0f;
+        for (int rep = 0; rep < 4; ++rep) {
+            if (rep == 1) FHIPCHK(F, hipEventRecord(F.ev[0], F.st));
+            for (int colour = 0; colour < 2; ++colour)
+                k_sweep_fused<TM, TM><<<G, 256, 0, F.st>>>(F.dmap(), F.dcav<FusedSweepCav<TM, TM>>(), n, total,
+                                                           colour, 0);
+        }
+        FHIPCHK(F, hipEventRecord(F.ev[1], F.st));
+        FHIPCHK(F, hipGetLastError());
+        FHIPCHK(F, hipEventSynchronize(F.ev[1]));
+        FHIPCHK(F, hipEventElapsedTime(&ms, F.ev[0], F.ev[1]));
+        if (ms < best) {
+            best = ms;
+            bg = g;
+        }
+    }
+    F.grid = bg;
+    *best_grid = bg;
+    for (int i = 0; i < n; ++i) {
+        hosc_status r = zero_colour_increments(cav[i]);
+        if (r) return ffail(F, r, cav[i]->err);
+    }
+    return HOSC_OK;
+}
+
+}  // namespace
+
+struct hosc_batch {
+    std::vector<hosc_solver *> cav;
+    Fused F;
+    hipStream_t st = nullptr;
+    bool fp32 = false;
+    std::string err;
+};
+
+namespace {
+
+hosc_status bfail(hosc_batch *b, hosc_status st, const std::string &msg)
+{
+    if (b) b->err = msg;
+    else g_create_error = msg;
+    return st;
+}
+
+size_t batch_layout(const hosc_params *p, int count, std::vector<size_t> *offsets)
+{
+    size_t off = 0;
+    for (int i = 0; i < count; ++i) {
+        Geo g = make_geo(p[i].N);
+        Launch L = make_launch(g);
+        if (offsets) offsets->push_back(off);
+        off += align_up(make_layout(g, L, p[i].solver, p[i].precision).total_bytes);
+    }
+    if (offsets) offsets->push_back(off);
+    return off + fused_device_bytes(count);
 }
 
 }  // namespace
@@ -1370,5 +1930,159 @@ const char *hosc_status_string(hosc_status st)
     }
     return "unknown";
 }
+
+
+hosc_status hosc_batch_workspace_bytes(const hosc_params *p, int32_t count, size_t *bytes)
+{
+    if (!p || !bytes || count < 1) return bfail(nullptr, HOSC_E_ARG, "params, bytes and count >= 1 are required");
+    for (int i = 0; i < count; ++i) {
+        const char *e = check_params(&p[i]);
+        if (e) return bfail(nullptr, HOSC_E_ARG, "cavity " + std::to_string(i) + ": " + e);
+    }
+    *bytes = batch_layout(p, count, nullptr);
+    return HOSC_OK;
+}
+
+hosc_status hosc_batch_create(const hosc_params *p, int32_t count, void *d_ws, size_t ws_bytes, hipStream_t stream,
+                              hosc_batch **out)
+{
+    if (!out) return bfail(nullptr, HOSC_E_ARG, "out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    hosc_status r = hosc_batch_workspace_bytes(p, count, &need);
+    if (r) return r;
+    for (int i = 1; i < count; ++i)
+        if (p[i].precision != p[0].precision)
+            return bfail(nullptr, HOSC_E_ARG, "all cavities of a batch must use one precision");
+    if (!d_ws) return bfail(nullptr, HOSC_E_ARG, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return bfail(nullptr, HOSC_E_ARG, "workspace must be 256-byte aligned");
+    if (ws_bytes < need) return bfail(nullptr, HOSC_E_NOMEM, "workspace smaller than hosc_batch_workspace_bytes()");
+    hosc_batch *b = new (std::nothrow) hosc_batch();
+    if (!b) return bfail(nullptr, HOSC_E_NOMEM, "host allocation failed");
+    b->st = stream;
+    b->fp32 = p[0].precision == HOSC_FP32_REFINED;
+    std::vector<size_t> off;
+    batch_layout(p, count, &off);
+    char *base = static_cast<char *>(d_ws);
+    for (int i = 0; i < count; ++i) {
+        hosc_solver *s = nullptr;
+        r = hosc_create(&p[i], base + off[i], off[i + 1] - off[i], stream, &s);
+        if (r) {
+            const std::string msg = "cavity " + std::to_string(i) + ": " + g_create_error;
+            for (hosc_solver *x : b->cav) hosc_destroy(x);
+            delete b;
+            return bfail(nullptr, r, msg);
+        }
+        b->cav.push_back(s);
+    }
+    r = fused_init(b->F, count, base + off[count], stream);
+    if (r) {
+        const std::string msg = b->F.err;
+        fused_free(b->F);
+        for (hosc_solver *x : b->cav) hosc_destroy(x);
+        delete b;
+        return bfail(nullptr, r, msg);
+    }
+    *out = b;
+    return HOSC_OK;
+}
+
+hosc_status hosc_batch_destroy(hosc_batch *b)
+{
+    if (!b) return HOSC_OK;
+    if (b->st) (void)hipStreamSynchronize(b->st);
+    fused_free(b->F);
+    for (hosc_solver *s : b->cav) hosc_destroy(s);
+    delete b;
+    return HOSC_OK;
+}
+
+hosc_status hosc_batch_cavity(hosc_batch *b, int32_t idx, hosc_solver **out)
+{
+    if (!b || !out) return HOSC_E_ARG;
+    if (idx < 0 || idx >= (int)b->cav.size()) return bfail(b, HOSC_E_ARG, "cavity index out of range");
+    *out = b->cav[idx];
+    return HOSC_OK;
+}
+
+hosc_status hosc_batch_init_fields(hosc_batch *b, const uint64_t *seeds, double noise_amp)
+{
+    if (!b || !seeds) return HOSC_E_ARG;
+    for (size_t i = 0; i < b->cav.size(); ++i) {
+        hosc_status r = hosc_init_fields(b->cav[i], seeds[i], noise_amp);
+        if (r) return bfail(b, r, "cavity " + std::to_string(i) + ": " + b->cav[i]->err);
+    }
+    return HOSC_OK;
+}
+
+hosc_status hosc_batch_step(hosc_batch *b, int32_t nsteps, hosc_step_info *info)
+{
+    if (!b) return HOSC_E_ARG;
+    if (nsteps < 0) return bfail(b, HOSC_E_ARG, "nsteps must be >= 0");
+    const int n = (int)b->cav.size();
+    std::vector<hosc_status> err(n);
+    for (int q = 0; q < nsteps; ++q) {
+        hosc_status r = fused_step(b->F, b->cav.data(), n, info, err.data());
+        if (r) return bfail(b, r, b->F.err);
+        for (int i = 0; i < n; ++i)
+            if (err[i]) return bfail(b, err[i], "cavity " + std::to_string(i) + ": " + b->cav[i]->err);
+    }
+    return HOSC_OK;
+}
+
+hosc_status hosc_batch_tune(hosc_batch *b, int32_t *grid)
+{
+    if (!b || !grid) return HOSC_E_ARG;
+    for (hosc_solver *s : b->cav)
+        if (!s->has_state || s->step != 0)
+            return bfail(b, HOSC_E_STATE, "tuning needs every cavity on a freshly set state");
+    const int n = (int)b->cav.size();
+    int g = 0;
+    hosc_status r = b->fp32 ? fused_tune<float>(b->F, b->cav.data(), n, &g) : fused_tune<double>(b->F, b->cav.data(), n, &g);
+    if (r) return bfail(b, r, b->F.err);
+    *grid = g;
+    return HOSC_OK;
+}
+
+hosc_status hosc_batch_set_grid(hosc_batch *b, int32_t grid)
+{
+    if (!b) return HOSC_E_ARG;
+    if (grid < 0) return bfail(b, HOSC_E_ARG, "grid must be >= 0");
+    b->F.grid = grid;
+    return HOSC_OK;
+}
+
+hosc_status hosc_batch_perf_enable(hosc_batch *b, int32_t on)
+{
+    if (!b) return HOSC_E_ARG;
+    b->F.prof = on != 0;
+    b->F.perf = hosc_perf{};
+    for (hosc_solver *s : b->cav) {
+        hosc_status r = hosc_perf_enable(s, on);
+        if (r) return bfail(b, r, s->err);
+    }
+    return HOSC_OK;
+}
+
+hosc_status hosc_batch_perf_get(hosc_batch *b, hosc_perf *out)
+{
+    if (!b || !out) return HOSC_E_ARG;
+    hosc_perf p = b->F.perf;
+    for (hosc_solver *s : b->cav) {
+        hosc_perf c;
+        hosc_status r = hosc_perf_get(s, &c);
+        if (r) return bfail(b, r, s->err);
+        p.assemble_launches += c.assemble_launches;
+        p.assemble_ms += c.assemble_ms;
+        p.assemble_bytes += c.assemble_bytes;
+        p.bicg_launches += c.bicg_launches;
+        p.bicg_ms += c.bicg_ms;
+        p.bicg_bytes += c.bicg_bytes;
+    }
+    *out = p;
+    return HOSC_OK;
+}
+
+const char *hosc_batch_last_error(const hosc_batch *b) { return b ? b->err.c_str() : g_create_error.c_str(); }
 
 }  // extern "C"

@@ -116,7 +116,7 @@ __device__ __forceinline__ void block_max_store(double (&v)[NV], double *out)
 
 // Reduce nb partial records of nc <= 8 values (record b at part[b*nc ...]) with one
 // block of 1024 threads; op 0 = sum, 1 = max.  Fixed order: deterministic.
-__global__ void __launch_bounds__(1024) k_reduce(const double *part, int nb, int nc, int op, double *out)
+__device__ __forceinline__ void reduce_block(const double *part, int nb, int nc, int op, double *out)
 {
     __shared__ double sh[8][1024];
     const int t = threadIdx.x;
@@ -132,6 +132,32 @@ __global__ void __launch_bounds__(1024) k_reduce(const double *part, int nb, int
         __syncthreads();
     }
     if (t < nc) out[t] = sh[t][0];
+}
+
+__global__ void __launch_bounds__(1024) k_reduce(const double *part, int nb, int nc, int op, double *out)
+{
+    reduce_block(part, nb, nc, op, out);
+}
+
+// Many reductions in one launch (one 1024-thread block per job), each computed
+// exactly as k_reduce computes it.
+struct ReduceJob {
+    const double *part;
+    double *out;
+    int nb, nc, op, pad;
+};
+__global__ void __launch_bounds__(1024) k_reduce_jobs(const ReduceJob *__restrict__ jobs)
+{
+    const ReduceJob jb = jobs[blockIdx.x];
+    reduce_block(jb.part, jb.nb, jb.nc, jb.op, jb.out);
+}
+
+// Gather len doubles from each of gridDim.x device blocks into one contiguous array
+// (one host copy then reads every cavity's reduction outputs).
+__global__ void __launch_bounds__(64) k_gather(const double *const *__restrict__ src, int len, double *__restrict__ dst)
+{
+    const double *s = src[blockIdx.x];
+    for (int t = threadIdx.x; t < len; t += blockDim.x) dst[(size_t)blockIdx.x * len + t] = s[t];
 }
 
 // ---------------------------------------------------------------------------
@@ -590,14 +616,12 @@ struct SweepArgs {
     TM *td;
 };
 
+// One SOR update of the node at colour-row entry q of row (j, k); the squared
+// pre-update residuals go to r2.
 template <typename TM, typename TA>
-__global__ void __launch_bounds__(256) k_sweep(Geo g, int colour, int mask, TA omega_m, TA omega_t, TA st,
-                                               SweepArgs<TM> a, double *__restrict__ partial, unsigned store,
-                                               double *__restrict__ partial0, unsigned store0)
+__device__ __forceinline__ void sweep_node(const Geo &g, int colour, int mask, TA omega_m, TA omega_t, TA st,
+                                           const SweepArgs<TM> &a, int q, int j, int k, double (&r2)[4])
 {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y, k = 1 + blockIdx.z;
-    double r2[4] = {0.0, 0.0, 0.0, 0.0};
     RowIdx r;
     if (row_index(g, colour, q, j, k, r)) {
         if (mask & 1) {
@@ -625,9 +649,93 @@ __global__ void __launch_bounds__(256) k_sweep(Geo g, int colour, int mask, TA o
             r2[3] = rr * rr;
         }
     }
+}
+
+template <typename TM, typename TA>
+__global__ void __launch_bounds__(256) k_sweep(Geo g, int colour, int mask, TA omega_m, TA omega_t, TA st,
+                                               SweepArgs<TM> a, double *__restrict__ partial, unsigned store,
+                                               double *__restrict__ partial0, unsigned store0)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y, k = 1 + blockIdx.z;
+    double r2[4] = {0.0, 0.0, 0.0, 0.0};
+    sweep_node<TM, TA>(g, colour, mask, omega_m, omega_t, st, a, q, j, k, r2);
     if (store | store0) {
         const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
         block_sum_store2<4>(r2, partial + (size_t)blk * 4, store, partial0 + (size_t)blk * 4, store0);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused multi-cavity launches.  The cavities of a batch are cut into the same
+// tiles their single-cavity launches use (tx x ty threads over colour-row entries
+// and rows, one tile per interior plane), numbered cavity after cavity.  A launch
+// of G persistent 256-thread workgroups walks the global tile list; workgroup b
+// takes tiles slot(b) + i*G with slot(b) = (b mod 8)(G/8) + b/8, so the tiles one
+// XCD works on at a time are contiguous (neighbouring rows and planes share its
+// L2).  A tile computes exactly what the block of the single-cavity launch with
+// the same index computes, and stores its partial sums in the same record, so a
+// cavity's results do not depend on the batch it is in.
+// ---------------------------------------------------------------------------
+struct TileMap {
+    int tile0;      // first global tile of the cavity
+    int tiles;      // tiles of the cavity (tiles_x * tiles_y * M)
+    int tiles_x, tiles_y;
+    int tx, ty;     // tile shape in threads (tx * ty = 256)
+    int pad[2];
+};
+
+__device__ __forceinline__ int find_cavity(const TileMap *__restrict__ map, int ncav, int t)
+{
+    int lo = 0, hi = ncav - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (map[mid].tile0 <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int persistent_slot(int b, int G)
+{
+    return (G & 7) ? b : (b & 7) * (G >> 3) + (b >> 3);
+}
+
+template <typename TM, typename TA>
+struct FusedSweepCav {
+    Geo g;
+    SweepArgs<TM> a;
+    TA omega_m, omega_t, st;
+    int plan_m, plan_t;             // sweeps of this batch per group (0: group idle)
+    double *part[2], *part0[2];     // partial records per colour: last sweep, first sweep
+};
+
+// One half-sweep (colour) of sweep q of the current batch, over every cavity.
+template <typename TM, typename TA>
+__global__ void __launch_bounds__(256) k_sweep_fused(const TileMap *__restrict__ map,
+                                                     const FusedSweepCav<TM, TA> *__restrict__ cav, int ncav,
+                                                     int total, int colour, int qs)
+{
+    const int G = gridDim.x;
+    for (int t = persistent_slot(blockIdx.x, G); t < total; t += G) {
+        const int c = find_cavity(map, ncav, t);
+        const TileMap m = map[c];
+        const FusedSweepCav<TM, TA> &cv = cav[c];
+        const int mask = (qs < cv.plan_m ? 1 : 0) | (qs < cv.plan_t ? 2 : 0);
+        if (!mask) continue;    // uniform over the workgroup
+        const unsigned store = (qs == cv.plan_m - 1 ? 0x7u : 0u) | (qs == cv.plan_t - 1 ? 0x8u : 0u);
+        const unsigned store0 = (qs == 0 && cv.plan_m > 1 ? 0x7u : 0u) | (qs == 0 && cv.plan_t > 1 ? 0x8u : 0u);
+        const int lt = t - m.tile0;
+        const int bx = lt % m.tiles_x, rest = lt / m.tiles_x;
+        const int by = rest % m.tiles_y, bz = rest / m.tiles_y;
+        const int tx = threadIdx.x % m.tx, ty = threadIdx.x / m.tx;
+        const int q = bx * m.tx + tx, j = 1 + by * m.ty + ty, k = 1 + bz;
+        double r2[4] = {0.0, 0.0, 0.0, 0.0};
+        sweep_node<TM, TA>(cv.g, colour, mask, cv.omega_m, cv.omega_t, cv.st, cv.a, q, j, k, r2);
+        if (store | store0)
+            block_sum_store2<4>(r2, cv.part[colour] + (size_t)lt * 4, store, cv.part0[colour] + (size_t)lt * 4,
+                                store0);
+        __syncthreads();    // the shared reduction buffer is reused by the next tile
     }
 }
 
@@ -790,12 +898,9 @@ struct RefineArgs {
 };
 
 template <typename TR>
-__global__ void __launch_bounds__(256) k_refine_residual(Geo g, int colour, int mask, double st, RefineArgs<TR> a,
-                                                         double *__restrict__ partial)
+__device__ __forceinline__ void refine_node(const Geo &g, int colour, int mask, double st, const RefineArgs<TR> &a,
+                                            int q, int j, int k, double (&acc)[4])
 {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y, k = 1 + blockIdx.z;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     RowIdx r;
     if (row_index(g, colour, q, j, k, r)) {
 #pragma unroll
@@ -822,8 +927,50 @@ __global__ void __launch_bounds__(256) k_refine_residual(Geo g, int colour, int 
             acc[f] = rr * rr;
         }
     }
+}
+
+template <typename TR>
+__global__ void __launch_bounds__(256) k_refine_residual(Geo g, int colour, int mask, double st, RefineArgs<TR> a,
+                                                         double *__restrict__ partial)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y, k = 1 + blockIdx.z;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    refine_node<TR>(g, colour, mask, st, a, q, j, k, acc);
     const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
     block_sum_store<4>(acc, partial + (size_t)blk * 4);
+}
+
+template <typename TR>
+struct FusedRefineCav {
+    Geo g;
+    RefineArgs<TR> a;
+    double st;
+    int mask;                       // groups refined (0: cavity idle)
+    int pad;
+    double *part[2];                // partial records per colour
+};
+
+template <typename TR>
+__global__ void __launch_bounds__(256) k_refine_fused(const TileMap *__restrict__ map,
+                                                      const FusedRefineCav<TR> *__restrict__ cav, int ncav, int total,
+                                                      int colour)
+{
+    const int G = gridDim.x;
+    for (int t = persistent_slot(blockIdx.x, G); t < total; t += G) {
+        const int c = find_cavity(map, ncav, t);
+        const TileMap m = map[c];
+        const FusedRefineCav<TR> &cv = cav[c];
+        if (!cv.mask) continue;
+        const int lt = t - m.tile0;
+        const int bx = lt % m.tiles_x, rest = lt / m.tiles_x;
+        const int by = rest % m.tiles_y, bz = rest / m.tiles_y;
+        const int tx = threadIdx.x % m.tx, ty = threadIdx.x / m.tx;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        refine_node<TR>(cv.g, colour, cv.mask, cv.st, cv.a, bx * m.tx + tx, 1 + by * m.ty + ty, 1 + bz, acc);
+        block_sum_store<4>(acc, cv.part[colour] + (size_t)lt * 4);
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------

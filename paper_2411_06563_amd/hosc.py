@@ -102,6 +102,18 @@ def lib() -> ctypes.CDLL:
     L.hosc_copy_bandwidth.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_double)]
     L.hosc_last_error.argtypes = [vp]
     L.hosc_last_error.restype = ctypes.c_char_p
+    L.hosc_batch_workspace_bytes.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+    L.hosc_batch_create.argtypes = [P, ctypes.c_int32, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.hosc_batch_destroy.argtypes = [vp]
+    L.hosc_batch_cavity.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(vp)]
+    L.hosc_batch_init_fields.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.c_double]
+    L.hosc_batch_step.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(CStepInfo)]
+    L.hosc_batch_tune.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.hosc_batch_set_grid.argtypes = [vp, ctypes.c_int32]
+    L.hosc_batch_perf_enable.argtypes = [vp, ctypes.c_int32]
+    L.hosc_batch_perf_get.argtypes = [vp, ctypes.POINTER(CPerf)]
+    L.hosc_batch_last_error.argtypes = [vp]
+    L.hosc_batch_last_error.restype = ctypes.c_char_p
     L.hosc_status_string.argtypes = [ctypes.c_int]
     L.hosc_status_string.restype = ctypes.c_char_p
     _lib = L
@@ -115,10 +127,11 @@ def _ptr(a):
     return a.ctypes.data_as(_dp)
 
 
-def _check(st: int, handle=None):
+def _check(st: int, handle=None, batch=None):
     if st != 0:
         L = lib()
-        raise HoscError(st, L.hosc_status_string(st).decode(), (L.hosc_last_error(handle) or b"").decode())
+        msg = L.hosc_batch_last_error(batch) if batch is not None else L.hosc_last_error(handle)
+        raise HoscError(st, L.hosc_status_string(st).decode(), (msg or b"").decode())
 
 
 def params(N: int, **kw) -> CParams:
@@ -192,7 +205,16 @@ class Solver:
                                      ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
         self.h = h
 
+    @classmethod
+    def borrowed(cls, handle, p: CParams, owner):
+        """A view of a solver owned by a batch (closing it does nothing)."""
+        s = cls.__new__(cls)
+        s.p, s.N, s.h, s._owner = p, p.N, handle, owner
+        return s
+
     def close(self):
+        if getattr(self, "_owner", None) is not None:
+            return
         if getattr(self, "h", None):
             lib().hosc_destroy(self.h)
             self.h = None
@@ -272,3 +294,70 @@ class Solver:
         Bt = np.empty((7, N, N, N))
         _check(lib().hosc_debug_assemble(self.h, _ptr(eta), _ptr(E), _ptr(b), _ptr(Bm), _ptr(Bt)), self.h)
         return dict(eta=eta, E=E, b=b, Bmom=Bm, Btheta=Bt)
+
+
+class Batch:
+    """Many cavities advanced together with fused solver launches (hosc_batch_*)."""
+
+    def __init__(self, plist, device: str = "cuda:0", stream=None):
+        import torch
+        self.plist = list(plist)
+        n = len(self.plist)
+        arr = (CParams * n)(*self.plist)
+        self._arr = arr
+        nbytes = ctypes.c_size_t(0)
+        _check(lib().hosc_batch_workspace_bytes(arr, n, ctypes.byref(nbytes)), batch=None)
+        self.device = torch.device(device)
+        with torch.cuda.device(self.device):
+            self.ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            base = self.ws.data_ptr()
+            off = (-base) % 256
+            h = ctypes.c_void_p()
+            _check(lib().hosc_batch_create(arr, n, ctypes.c_void_p(base + off), nbytes.value,
+                                           ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), batch=None)
+        self.b = h
+        self.cavities = []
+        for i in range(n):
+            ch = ctypes.c_void_p()
+            _check(lib().hosc_batch_cavity(self.b, i, ctypes.byref(ch)), batch=self.b)
+            self.cavities.append(Solver.borrowed(ch, self.plist[i], self))
+
+    def __len__(self):
+        return len(self.cavities)
+
+    def close(self):
+        if getattr(self, "b", None):
+            lib().hosc_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_fields(self, seeds, noise: float = 1e-3):
+        arr = (ctypes.c_uint64 * len(self.cavities))(*seeds)
+        _check(lib().hosc_batch_init_fields(self.b, arr, noise), batch=self.b)
+
+    def step(self, n: int = 1) -> list:
+        infos = (CStepInfo * len(self.cavities))()
+        _check(lib().hosc_batch_step(self.b, n, infos), batch=self.b)
+        return [StepInfo.of(c) for c in infos]
+
+    def tune(self) -> int:
+        g = ctypes.c_int32(0)
+        _check(lib().hosc_batch_tune(self.b, ctypes.byref(g)), batch=self.b)
+        return g.value
+
+    def set_grid(self, grid: int):
+        _check(lib().hosc_batch_set_grid(self.b, grid), batch=self.b)
+
+    def perf_enable(self, on: bool = True):
+        _check(lib().hosc_batch_perf_enable(self.b, int(on)), batch=self.b)
+
+    def perf(self) -> dict:
+        c = CPerf()
+        _check(lib().hosc_batch_perf_get(self.b, ctypes.byref(c)), batch=self.b)
+        return {n: getattr(c, n) for n, _ in CPerf._fields_}
