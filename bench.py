@@ -47,6 +47,20 @@ WORKLOADS = {
     "fp64": dict(N=129, Ra=1e5, n_pl=0.75, Pr=1.0, dt=5e-5, seed=2, noise=1e-3, solve_rtol=1e-10, precision=0,
                  label="HOSC cavity 129^3, n=0.75, Ra=1e5, Pr=1, dt=5e-5, FP64, rtol 1e-10, seed 2"),
     # precision form: shear-thickening, Ra = 1e4, FP32 rows and sweeps with FP64 refinement
+    # batched form: dt = max(5e-5, 0.2 h^2) per cavity.  At 5e-5 the 33^3 shear-
+    # thickening cavities lose their implicit rows within a few steps (on the oracle as
+    # on the GPU), and 0.2 h^2 everywhere does the same to the 97^3 ones at Ra = 1e5.
+    "batch12": dict(kind="batch", Pr=1.0, dt=5e-5, dt_over_h2=0.2, noise=1e-3, solve_rtol=1e-10, precision=1, segment=30,
+                    label="12 HOSC cavities, (Ra, n) in {1e2,1e3,1e4,1e5} x {0.75,1,1.25}, sizes 33^3/65^3/97^3 "
+                          "(4 each, seeded shuffle, seed 4), Pr=1, dt=max(5e-5, 0.2 h^2), FP32 rows/sweeps + FP64 refinement, "
+                          "rtol 1e-10, cavity seeds 100+i, seeded rest start"),
+    # serving form: the seeded Poisson trace (rate 2/s); each request runs to res 1e-8 or
+    # max_steps steps with dt = 0.4 h^2; a 4 GiB HBM budget forces queueing
+    "serve": dict(kind="serve", requests=120, rate=2.0, trace_seed=5, dt_over_h2=0.4, res_tol=1e-8, max_steps=200,
+                  budget=4 << 30, max_resident=64, precision=1, solve_rtol=1e-10, noise=1e-3, sample=20,
+                  label="serving trace: Poisson arrivals at 2/s (seed 5), N uniform over {33,49,65,97,129}, "
+                        "Ra log-uniform in [1e2,1e5], n uniform in [0.7,1.3], Pr=1, dt=0.4 h^2, FP32 rows/sweeps + "
+                        "FP64 refinement, rtol 1e-10, each request to res < 1e-8 or 200 steps, HBM budget 4 GiB"),
     "fp32r": dict(N=129, Ra=1e4, n_pl=1.25, Pr=1.0, dt=5e-5, seed=3, noise=1e-3, solve_rtol=1e-10, precision=1,
                   newtonian_start=20, segment=60,
                   label="HOSC cavity 129^3, n=1.25, Ra=1e4, Pr=1, dt=5e-5, FP32 rows/sweeps + FP64 refinement, "
@@ -116,6 +130,193 @@ def precision_check(hosc, W, kw, reset, steps):
     return out
 
 
+def bench_batch(args, W, hosc, torch):
+    """Batched form: all cavities advanced together (fused persistent solver
+    launches, graph-captured phases, autotuned schedule).  Reports the aggregate
+    cell-updates/s, the same segment stepped cavity by cavity with the
+    single-cavity path (serial baseline), and the largest difference between each
+    cavity's batched and single-cavity results (0 = bitwise equal)."""
+    import numpy as np
+    from paper_2411_06563_amd.inputs import batched_cavities
+    cavs = batched_cavities(4)
+    seg = args.segment if args.segment is not None else W["segment"]
+    plist = [hosc.params(c["N"], Ra=c["Ra"], n_pl=c["n_pl"], Pr=W["Pr"], dt=max(W["dt"], W["dt_over_h2"] / (c["N"] - 1) ** 2),
+                         solve_rtol=W["solve_rtol"], precision=W["precision"]) for c in cavs]
+    seeds = [c["seed"] for c in cavs]
+    b = hosc.Batch(plist)
+
+    def reset():
+        b.init_fields(seeds, W["noise"])
+
+    reset()
+    grid = b.tune()
+    M3 = sum((c["N"] - 2) ** 3 for c in cavs)
+    in_seg = 0
+    for _ in range(args.warmup):
+        if in_seg == seg:
+            reset()
+            in_seg = 0
+        b.step(1)
+        in_seg += 1
+    reset()
+    in_seg = 0
+    b.perf_enable(True)
+    torch.cuda.synchronize()
+    el = 0.0
+    t0 = time.perf_counter()
+    sweeps = np.zeros(2)
+    for q in range(args.steps):
+        if in_seg == seg:
+            torch.cuda.synchronize()
+            el += time.perf_counter() - t0
+            reset()
+            in_seg = 0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        infos = b.step(1)
+        in_seg += 1
+        sweeps += np.array([sum(i.sweeps[0] for i in infos), sum(i.sweeps[1] for i in infos)])
+        if q % 10 == 0:
+            print(f"batch step {q}: sweeps {[i.sweeps for i in infos]}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    el += time.perf_counter() - t0
+    perf = b.perf()
+    b.perf_enable(False)
+    graphs = b.graph_launches()
+    # one segment batched vs cavity by cavity (single-cavity path, same stream kind)
+    reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(seg)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    got = [cv.get_state() for cv in b.cavities]
+    t_serial = 0.0
+    worst = 0.0
+    for i, p in enumerate(plist):
+        s = hosc.Solver(p)
+        s.init_fields(seeds[i], W["noise"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(seg)
+        torch.cuda.synchronize()
+        t_serial += time.perf_counter() - t0
+        g = s.get_state()
+        s.close()
+        worst = max(worst, max(float(np.max(np.abs(g[f] - got[i][f]))) for f in ("u", "v", "w", "T", "p")))
+    b.close()
+    avg_ms = perf["sweep_ms"] / max(perf["sweep_launches"], 1)
+    avg_bytes = perf["sweep_bytes"] / max(perf["sweep_launches"], 1)
+    achieved = avg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    out = {
+        "metric": METRIC,
+        "value": M3 * args.steps / el,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{W['label']}; steps 1-{seg} from the start states, repeated",
+                   "cavities": [(c["N"], c["Ra"], c["n_pl"]) for c in cavs], "interior_nodes": M3,
+                   "cavity_steps_per_s": len(cavs) * args.steps / el, "tuned_grid": grid,
+                   "graph_launches": graphs,
+                   "mean_sor_sweeps_per_cavity_step": (sweeps / (args.steps * len(cavs))).tolist()},
+        "roofline": {"bound": "hbm", "kernel": "k_sweep_fused (all cavities, one half-sweep)", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_us": avg_ms * 1e3, "launches": perf["sweep_launches"],
+                     "bytes_per_launch": avg_bytes, "kernel_time_frac": perf["sweep_ms"] * 1e-3 / el,
+                     "refine_time_frac": perf["refine_ms"] * 1e-3 / el},
+        "batch_check": {"segment_steps": seg, "batched_s": t_batch, "cavity_by_cavity_s": t_serial,
+                        "speedup": t_serial / t_batch, "max_abs_diff_vs_single_cavity": worst},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args, W, hosc, torch):
+    """Serving form: replay the first `requests` arrivals of the seeded trace in real
+    time against the server (admission by HBM budget, continuous fused batching).
+    Reports completed solves/s, p50/p99 of completion - arrival (and of the service
+    time), and a mix-vs-alone check: sampled requests rerun as single cavities for
+    the same number of steps must reproduce the served diagnostics bitwise."""
+    import numpy as np
+    from paper_2411_06563_amd.inputs import serving_trace
+    nreq = args.requests if args.requests is not None else W["requests"]
+    trace = serving_trace(500, W["rate"], W["trace_seed"])[:nreq]
+    plist = [hosc.params(r["N"], Ra=r["Ra"], n_pl=r["n_pl"], Pr=r["Pr"], dt=W["dt_over_h2"] / (r["N"] - 1) ** 2,
+                         solve_rtol=W["solve_rtol"], precision=W["precision"]) for r in trace]
+    srv = hosc.Server(W["budget"], max_resident=W["max_resident"])
+    t0 = srv.now()
+    ids, results = {}, {}
+    nxt = 0
+    max_queued = 0
+    while len(results) < nreq:
+        now = srv.now() - t0
+        while nxt < nreq and trace[nxt]["arrival"] <= now:
+            r = trace[nxt]
+            ids[srv.submit(plist[nxt], r["seed"], W["noise"], W["res_tol"], W["max_steps"], t0 + r["arrival"])] = nxt
+            nxt += 1
+        st = srv.stats()
+        max_queued = max(max_queued, st["queued"])
+        if st["resident"] or st["queued"]:
+            srv.step()
+        elif nxt < nreq:
+            time.sleep(min(0.005, max(0.0, trace[nxt]["arrival"] - (srv.now() - t0))))
+        for r in srv.poll():
+            results[ids[r["id"]]] = r
+            if len(results) % 20 == 0:
+                print(f"serve: {len(results)}/{nreq} done", file=sys.stderr, flush=True)
+    st = srv.stats()
+    srv.close()
+    ok = [i for i in range(nreq) if results[i]["status"] == 0]
+    lat = np.array([results[i]["t_done"] - results[i]["t_arrival"] for i in ok])
+    svc = np.array([results[i]["t_done"] - results[i]["t_admit"] for i in ok])
+    span = max(results[i]["t_done"] for i in range(nreq)) - (t0 + trace[0]["arrival"])
+    # mix vs alone on sampled successful requests
+    sample = ok[:: max(1, len(ok) // W["sample"])][: W["sample"]]
+    same = 0
+    for i in sample:
+        s = hosc.Solver(plist[i])
+        s.init_fields(trace[i]["seed"], W["noise"])
+        s.step(results[i]["steps"])
+        d = s.diagnostics(arrays=False)
+        s.close()
+        same += int(d == results[i]["diag"])
+    M3 = np.array([(trace[i]["N"] - 2) ** 3 for i in range(nreq)], dtype=float)
+    cell_updates = float(sum(M3[i] * results[i]["steps"] for i in range(nreq)))
+    out = {
+        "metric": METRIC,
+        "value": len(ok) / span,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": int(st["server_steps"]),
+        "warmup": 0,
+        "ms_per_step": st["busy_s"] * 1e3 / max(st["server_steps"], 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{W['label']}; first {nreq} requests of the 500-request trace"},
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "mean": float(lat.mean())},
+        "service_s": {"p50": float(np.percentile(svc, 50)), "p99": float(np.percentile(svc, 99))},
+        "requests": {"completed": nreq, "ok": len(ok), "failed": nreq - len(ok),
+                     "steady": sum(1 for i in ok if results[i]["steady"]),
+                     "failed_status": sorted({results[i]["status"] for i in range(nreq)} - {0})},
+        "server": {"cavity_steps": int(st["cavity_steps"]), "server_steps": int(st["server_steps"]),
+                   "busy_s": st["busy_s"], "span_s": span, "peak_bytes": int(st["peak"]),
+                   "budget_bytes": int(st["budget"]), "max_queued": int(max_queued),
+                   "cell_updates_per_busy_s": cell_updates / max(st["busy_s"], 1e-9)},
+        "mix_vs_alone": {"sampled": len(sample), "bitwise_equal": same},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +327,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--omega", type=float, default=None)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="fp64")
+    ap.add_argument("--requests", type=int, default=None)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build measures the single-cavity hot path on one MI355X "
@@ -137,6 +339,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     W = WORKLOADS[args.workload]
+    if W.get("kind") == "batch":
+        return bench_batch(args, W, hosc, torch)
+    if W.get("kind") == "serve":
+        return bench_serve(args, W, hosc, torch)
     if args.segment is None:
         args.segment = W.get("segment", SEGMENT)
     kw = dict(Ra=W["Ra"], n_pl=W["n_pl"], Pr=W["Pr"], dt=W["dt"], solve_rtol=W["solve_rtol"],

@@ -268,14 +268,87 @@ hosc_status hosc_batch_tune(hosc_batch *b, int32_t *grid);
 /* Set the schedule by hand (persistent workgroups, 0 = one per tile). */
 hosc_status hosc_batch_set_grid(hosc_batch *b, int32_t grid);
 
-/* Timing of the fused solver launches (sweep_* and refine_* counters, one event
- * pair per batch of fused launches) plus the cavities' assembly and BiCGSTAB
- * counters. */
+/* Timing of the fused solver launches: sweep_* and refine_* counters, one event
+ * pair around each batch of fused launches (the other counters stay 0; the phases
+ * around the solves keep running as captured graphs). */
 hosc_status hosc_batch_perf_enable(hosc_batch *b, int32_t on);
 hosc_status hosc_batch_perf_get(hosc_batch *b, hosc_perf *out);
 
+/* Launches of captured graphs so far.  On a stream other than the null stream,
+ * the per-cavity phases around the solves (viscosity, sources, assembly and their
+ * reductions before; update, walls, divergence, pressure correction and the
+ * gather of the step report after) are captured once per level parity and
+ * replayed as one graph launch each. */
+hosc_status hosc_batch_graph_launches(const hosc_batch *b, int64_t *count);
+
 /* Message of the last failing call on the batch (NULL: last failing create). */
 const char *hosc_batch_last_error(const hosc_batch *b);
+
+/* ------------------------------------------------------------------------------
+ * Server: cavity solves submitted as they arrive, admitted first-come first-served
+ * while their workspace fits an HBM budget (and a resident-count limit), kept
+ * resident on the device, and advanced together by fused steps (continuous
+ * batching: every hosc_server_step admits what fits, advances each resident cavity
+ * one time step, and retires the cavities that reached res_tol or max_steps).  A
+ * request's arithmetic is that of its single-cavity run, whatever else is resident.
+ * The server owns one device arena of the budget (allocated at create, the only
+ * device allocation the library makes) and small fused-launch tables.
+ * ------------------------------------------------------------------------------ */
+typedef struct hosc_server hosc_server;
+
+typedef struct hosc_request {
+    hosc_params params;
+    uint64_t seed;          /* hosc_init_fields seed and noise amplitude */
+    double noise_amp;
+    double res_tol;         /* done when max_f res[f] < res_tol ... */
+    int64_t max_steps;      /* ... or after max_steps steps */
+    double t_arrival;       /* server clock (hosc_server_now), seconds; < 0: now */
+} hosc_request;
+
+typedef struct hosc_result {
+    uint64_t id;
+    int32_t status;         /* HOSC_OK, or the error the request ended with */
+    int32_t steady;         /* 1 if res_tol was reached */
+    int64_t steps;
+    double res;             /* max_f res[f] of the last step */
+    double t_arrival, t_admit, t_done;   /* server clock, seconds */
+    hosc_diag diag;         /* diagnostics of the final state (zeros on error) */
+} hosc_result;
+
+typedef struct hosc_server_stats {
+    int64_t queued, resident, completed;
+    int64_t server_steps;   /* hosc_server_step calls that advanced cavities */
+    int64_t cavity_steps;   /* cavity time steps taken */
+    size_t budget, in_use, peak;   /* arena bytes */
+    double busy_s;          /* time spent inside hosc_server_step */
+} hosc_server_stats;
+
+/* Create a server on the current device with an arena of hbm_budget_bytes and at
+ * most max_resident resident cavities (1..1024). */
+hosc_status hosc_server_create(size_t hbm_budget_bytes, int32_t max_resident, hipStream_t stream, hosc_server **out);
+
+/* Finish nothing further, release every resident cavity and the arena. */
+hosc_status hosc_server_destroy(hosc_server *srv);
+
+/* Seconds since the server was created (steady clock). */
+hosc_status hosc_server_now(const hosc_server *srv, double *t);
+
+/* Queue a request (copied).  HOSC_E_ARG for invalid parameters; HOSC_E_BUDGET if
+ * its workspace exceeds the whole budget. */
+hosc_status hosc_server_submit(hosc_server *srv, const hosc_request *rq, uint64_t *id);
+
+/* Admit, advance every resident cavity one step, retire finished ones.  *resident
+ * (may be NULL): cavities resident after the call.  A failing request is retired
+ * with its status; the return value reports failures of the server itself. */
+hosc_status hosc_server_step(hosc_server *srv, int32_t *resident);
+
+/* Move up to max completed results (completion order) into out. */
+hosc_status hosc_server_poll(hosc_server *srv, hosc_result *out, int32_t max, int32_t *n_out);
+
+hosc_status hosc_server_stats_get(const hosc_server *srv, hosc_server_stats *st);
+
+/* Message of the last failing call on the server (NULL: last failing create). */
+const char *hosc_server_last_error(const hosc_server *srv);
 
 #ifdef __cplusplus
 }

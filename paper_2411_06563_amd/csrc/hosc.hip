@@ -11,6 +11,9 @@
 
 #include <algorithm>
 #include <array>
+#include <chrono>
+#include <deque>
+#include <map>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -183,6 +186,7 @@ struct hosc_solver {
     int device = 0;
     // natural layout
     double *u, *v, *w, *T, *p, *u2, *v2, *w2, *eta, *etap, *E[3], *Ep[3], *dbg;
+    double *u_first = nullptr;      // the buffer u had at creation (level parity of the swapped pointers)
     // colour layout
     double *ms, *ma[3], *mb[3], *md[3], *ta[3], *tb, *td;
     double *partR, *partB, *partR0, *partB0, *red, *wq, *nuh, *nuc, *avh, *avc, *nuout;
@@ -248,6 +252,7 @@ void carve(hosc_solver *s, char *base)
         return r;
     };
     s->u = take(nat); s->v = take(nat); s->w = take(nat); s->T = take(nat); s->p = take(nat);
+    s->u_first = s->u;
     s->u2 = take(nat); s->v2 = take(nat); s->w2 = take(nat);
     s->eta = take(nat); s->etap = take(nat);
     for (int d = 0; d < 3; ++d) s->E[d] = take(nat);
@@ -1063,8 +1068,8 @@ hosc_status pre_solve(hosc_solver *s)
     return launch_check(s, "assemble");
 }
 
-// Update, theta walls, divergence (with the correction when it is not gated) and
-// their reductions into red[12..22]; launches only.
+// Update, theta walls, divergence (with the correction and the pressure walls when
+// the correction is not gated) and their reductions into red[12..22]; launches only.
 hosc_status post_launch(hosc_solver *s)
 {
     // update: u, v, w into the level n-1 buffers (which become level n+1)
@@ -1077,6 +1082,7 @@ hosc_status post_launch(hosc_solver *s)
     k_divergence<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, s->ph, s->u2, s->v2, s->w2, s->p,
                                                            gate ? s->dbg : nullptr, gate ? 0 : 1, s->partR);
     k_reduce<<<1, 1024, 0, s->st>>>(s->partR, (int)s->L.nb_int, 1, 1, s->red + 22);
+    if (!gate) k_p_walls<<<s->L.grd_face, s->L.blk_face, 0, s->st>>>(s->g, s->p);
     return launch_check(s, "update/divergence");
 }
 
@@ -1086,16 +1092,14 @@ hosc_status post_finish(hosc_solver *s, const double *hb, const SolveOut &so, ho
 {
     const bool gate = s->P.div_tol > 0.0;
     const double maxdiv = hb[10];
-    int corrected = 0;
+    int corrected = 1;      // ungated: applied (with its walls) by post_launch
     if (gate) {
-        if (maxdiv > s->P.div_tol) {
+        corrected = maxdiv > s->P.div_tol;
+        if (corrected) {
             k_pressure_apply<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, s->ph, s->dbg, s->p);
-            corrected = 1;
+            k_p_walls<<<s->L.grd_face, s->L.blk_face, 0, s->st>>>(s->g, s->p);
         }
-    } else {
-        corrected = 1;
     }
-    if (corrected) k_p_walls<<<s->L.grd_face, s->L.blk_face, 0, s->st>>>(s->g, s->p);
     hosc_status r = launch_check(s, "pressure");
     if (r) return r;
     std::swap(s->u, s->u2);
@@ -1164,9 +1168,20 @@ struct Fused {
     int cap = 0;                      // cavities the tables hold
     hipStream_t st = nullptr;
     int grid = 1024;                  // persistent workgroups per fused launch (0: one per tile)
-    // one contiguous table block, mirrored in pinned host memory: map | cav | jobs | src
+    // one contiguous table block, mirrored in pinned host memory: map | cav | jobs | src,
+    // then the fixed gather list of the captured post-solve phase
     char *d_tab = nullptr, *h_tab = nullptr;
-    size_t off_cav = 0, off_jobs = 0, off_src = 0, tab_bytes = 0;
+    size_t off_cav = 0, off_jobs = 0, off_src = 0, tab_bytes = 0, off_src2 = 0;
+    // captured pre- and post-solve phases (kind 0 / 1), keyed by the level parity
+    // of every cavity; used when the stream is not the null stream
+    struct GraphEntry {
+        uint64_t sig;
+        int kind;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
+    bool use_graphs = false;
+    int64_t graph_launches = 0;
     double *d_gather = nullptr, *h_gather = nullptr;
     std::string err;
     bool prof = false;
@@ -1180,12 +1195,14 @@ struct Fused {
     template <typename T> const T *dcav() const { return reinterpret_cast<const T *>(d_tab + off_cav); }
     const ReduceJob *djobs() const { return reinterpret_cast<const ReduceJob *>(d_tab + off_jobs); }
     const double *const *dsrc() const { return reinterpret_cast<const double *const *>(d_tab + off_src); }
+    const double **hsrc2() { return reinterpret_cast<const double **>(h_tab + off_src2); }
+    const double *const *dsrc2() const { return reinterpret_cast<const double *const *>(d_tab + off_src2); }
 };
 
 size_t fused_table_bytes(int cap)
 {
     return align_up((size_t)cap * sizeof(TileMap)) + align_up((size_t)cap * kCavEntry)
-           + align_up((size_t)cap * 4 * sizeof(ReduceJob)) + align_up((size_t)cap * sizeof(double *));
+           + align_up((size_t)cap * 4 * sizeof(ReduceJob)) + 2 * align_up((size_t)cap * sizeof(double *));
 }
 size_t fused_device_bytes(int cap) { return fused_table_bytes(cap) + align_up((size_t)cap * 64 * sizeof(double)); }
 
@@ -1212,7 +1229,9 @@ hosc_status fused_init(Fused &F, int cap, char *d_dev, hipStream_t st)
     F.off_cav = align_up((size_t)cap * sizeof(TileMap));
     F.off_jobs = F.off_cav + align_up((size_t)cap * kCavEntry);
     F.off_src = F.off_jobs + align_up((size_t)cap * 4 * sizeof(ReduceJob));
+    F.off_src2 = F.off_src + align_up((size_t)cap * sizeof(double *));
     F.tab_bytes = fused_table_bytes(cap);
+    F.use_graphs = st != nullptr;
     F.d_tab = d_dev;
     F.d_gather = reinterpret_cast<double *>(d_dev + F.tab_bytes);
     FHIPCHK(F, hipHostMalloc(reinterpret_cast<void **>(&F.h_tab), F.tab_bytes));
@@ -1224,6 +1243,8 @@ hosc_status fused_init(Fused &F, int cap, char *d_dev, hipStream_t st)
 }
 void fused_free(Fused &F)
 {
+    for (auto &e : F.graphs) (void)hipGraphExecDestroy(e.exec);
+    F.graphs.clear();
     if (F.h_tab) (void)hipHostFree(F.h_tab);
     if (F.h_gather) (void)hipHostFree(F.h_gather);
     for (hipEvent_t &e : F.ev)
@@ -1443,6 +1464,49 @@ hosc_status fused_refined(Fused &F, hosc_solver *const *cav, int n, const int *m
     return HOSC_OK;
 }
 
+// Level-parity signature of the cavities (bit i: cavity i's level-n buffers are
+// swapped); a captured phase bakes the buffer addresses in.
+uint64_t parity_sig(hosc_solver *const *cav, int n)
+{
+    uint64_t sig = 0;
+    for (int i = 0; i < n; ++i)
+        if (cav[i]->u != cav[i]->u_first) sig |= 1ull << i;
+    return sig;
+}
+
+// Replay the captured phase (kind, sig), capturing it first with record() if needed.
+template <typename Fn>
+hosc_status graph_run(Fused &F, int kind, uint64_t sig, Fn &&record)
+{
+    for (auto &e : F.graphs)
+        if (e.kind == kind && e.sig == sig) {
+            FHIPCHK(F, hipGraphLaunch(e.exec, F.st));
+            F.graph_launches += 1;
+            return HOSC_OK;
+        }
+    if (F.graphs.size() >= 8) {
+        (void)hipGraphExecDestroy(F.graphs.front().exec);
+        F.graphs.erase(F.graphs.begin());
+    }
+    FHIPCHK(F, hipStreamBeginCapture(F.st, hipStreamCaptureModeThreadLocal));
+    const hosc_status r = record();
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(F.st, &graph);
+    if (r || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        if (r) return r;
+        return ffail(F, HOSC_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return ffail(F, HOSC_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    F.graphs.push_back({sig, kind, exec});
+    FHIPCHK(F, hipGraphLaunch(exec, F.st));
+    F.graph_launches += 1;
+    return HOSC_OK;
+}
+
 // One step of every cavity in cav[0..n) (all of one precision).  Per-cavity
 // failures are returned in err[i] (and make that solver sticky, as hosc_step
 // does); the return value reports failures of the fused machinery itself.
@@ -1452,12 +1516,29 @@ hosc_status fused_step(Fused &F, hosc_solver *const *cav, int n, hosc_step_info 
     std::vector<double> bn2(4 * (size_t)n, -1.0);
     std::vector<int> sor(n), bic(n), failed(n), act(n);
     std::vector<double> rtol(n);
+    // the pre- and post-solve phases of steady-going batches run as captured graphs
+    bool graphed = F.use_graphs && n <= 64;
+    for (int i = 0; i < n; ++i) {
+        const hosc_solver *s = cav[i];
+        graphed = graphed && s->has_state && !s->sticky && !s->first && !s->prof;
+    }
+    const uint64_t sig = graphed ? parity_sig(cav, n) : 0;
+    if (graphed) {
+        hosc_status r = graph_run(F, 0, sig, [&]() {
+            for (int i = 0; i < n; ++i) {
+                hosc_status q = pre_solve(cav[i]);
+                if (q) return ffail(F, q, "cavity " + std::to_string(i) + ": " + cav[i]->err);
+            }
+            return HOSC_OK;
+        });
+        if (r) return r;
+    }
     for (int i = 0; i < n; ++i) {
         err[i] = HOSC_OK;
         hosc_solver *s = cav[i];
         if (!s->has_state) err[i] = fail(s, HOSC_E_STATE, "no state set");
         else if (s->sticky) err[i] = fail(s, HOSC_E_STATE, "solver is in an error state; set a new state");
-        else err[i] = pre_solve(s);
+        else if (!graphed) err[i] = pre_solve(s);
         solve_masks(s, sor[i], bic[i]);
         rtol[i] = s->P.solve_rtol;
         if (err[i]) sor[i] = bic[i] = 0;
@@ -1471,16 +1552,48 @@ hosc_status fused_step(Fused &F, hosc_solver *const *cav, int n, hosc_step_info 
     for (int i = 0; i < n; ++i) {
         if (err[i]) continue;
         err[i] = solve_finish(cav[i], failed[i], bic[i], b4[i], o[i]);
-        if (!err[i]) err[i] = post_launch(cav[i]);
         if (err[i]) continue;
-        F.hsrc()[nact] = cav[i]->red + 12;
         act[nact++] = i;
     }
-    if (nact) {
-        FHIPCHK(F, hipMemcpyAsync(F.d_tab + F.off_src, F.h_tab + F.off_src, (size_t)nact * sizeof(double *),
-                                  hipMemcpyHostToDevice, F.st));
-        r = fused_reduce_gather(F, 0, nact, 11);
+    if (graphed && nact == n) {
+        // fixed gather list of the captured phase: red[12..22] of every cavity in order
+        bool fresh = false;
+        for (int i = 0; i < n; ++i)
+            if (F.hsrc2()[i] != cav[i]->red + 12) {
+                F.hsrc2()[i] = cav[i]->red + 12;
+                fresh = true;
+            }
+        if (fresh)
+            FHIPCHK(F, hipMemcpyAsync(F.d_tab + F.off_src2, F.h_tab + F.off_src2, (size_t)n * sizeof(double *),
+                                      hipMemcpyHostToDevice, F.st));
+        r = graph_run(F, 1, sig, [&]() {
+            for (int i = 0; i < n; ++i) {
+                hosc_status q = post_launch(cav[i]);
+                if (q) return ffail(F, q, "cavity " + std::to_string(i) + ": " + cav[i]->err);
+            }
+            k_gather<<<n, 64, 0, F.st>>>(F.dsrc2(), 11, F.d_gather);
+            return HOSC_OK;
+        });
         if (r) return r;
+        FHIPCHK(F, hipMemcpyAsync(F.h_gather, F.d_gather, (size_t)n * 11 * sizeof(double), hipMemcpyDeviceToHost, F.st));
+        FHIPCHK(F, hipStreamSynchronize(F.st));
+    } else if (nact) {
+        int ng = 0;
+        for (int a = 0; a < nact; ++a) {
+            const int i = act[a];
+            err[i] = post_launch(cav[i]);
+            if (!err[i]) {
+                F.hsrc()[ng] = cav[i]->red + 12;
+                act[ng++] = i;
+            }
+        }
+        nact = ng;
+        if (nact) {
+            FHIPCHK(F, hipMemcpyAsync(F.d_tab + F.off_src, F.h_tab + F.off_src, (size_t)nact * sizeof(double *),
+                                      hipMemcpyHostToDevice, F.st));
+            r = fused_reduce_gather(F, 0, nact, 11);
+            if (r) return r;
+        }
     }
     for (int a = 0; a < nact; ++a) {
         const int i = act[a];
@@ -1555,6 +1668,106 @@ struct hosc_batch {
     bool fp32 = false;
     std::string err;
 };
+
+struct hosc_server {
+    struct Req {
+        uint64_t id;
+        hosc_request rq;
+        size_t bytes;
+    };
+    struct Res {
+        Req q;
+        hosc_solver *s;
+        size_t off;
+        double t_admit;
+        int64_t steps;
+        double res;
+    };
+    char *arena = nullptr;
+    size_t budget = 0, in_use = 0, peak = 0;
+    std::map<size_t, size_t> free_;     // offset -> bytes, coalesced
+    int max_resident = 0;
+    char *d_fused = nullptr;
+    Fused F;
+    hipStream_t st = nullptr;
+    std::deque<Req> queue;
+    std::vector<Res> res;
+    std::deque<hosc_result> done;
+    uint64_t next_id = 1;
+    int64_t server_steps = 0, cavity_steps = 0, completed = 0;
+    double busy_s = 0.0;
+    std::chrono::steady_clock::time_point t0;
+    std::string err;
+    double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+};
+
+namespace {
+
+hosc_status sfail(hosc_server *v, hosc_status st, const std::string &msg)
+{
+    if (v) v->err = msg;
+    else g_create_error = msg;
+    return st;
+}
+
+// First fit in the arena (sizes 256-byte multiples); SIZE_MAX when nothing fits.
+size_t arena_alloc(hosc_server *v, size_t bytes)
+{
+    for (auto it = v->free_.begin(); it != v->free_.end(); ++it)
+        if (it->second >= bytes) {
+            const size_t off = it->first, rest = it->second - bytes;
+            v->free_.erase(it);
+            if (rest) v->free_[off + bytes] = rest;
+            v->in_use += bytes;
+            v->peak = std::max(v->peak, v->in_use);
+            return off;
+        }
+    return SIZE_MAX;
+}
+void arena_free(hosc_server *v, size_t off, size_t bytes)
+{
+    v->in_use -= bytes;
+    auto it = v->free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != v->free_.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        v->free_.erase(nx);
+    }
+    if (it != v->free_.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            v->free_.erase(it);
+        }
+    }
+}
+
+// Retire resident cavity k (swap-removed) with status st.
+void server_retire(hosc_server *v, size_t k, hosc_status st, bool steady)
+{
+    hosc_server::Res &r = v->res[k];
+    hosc_result out{};
+    out.id = r.q.id;
+    out.status = st;
+    out.steady = steady ? 1 : 0;
+    out.steps = r.steps;
+    out.res = r.res;
+    out.t_arrival = r.q.rq.t_arrival;
+    out.t_admit = r.t_admit;
+    if (st == HOSC_OK) {
+        const hosc_status d = hosc_diagnostics(r.s, &out.diag, nullptr, nullptr, nullptr, nullptr);
+        if (d) out.status = d;
+    }
+    out.t_done = v->now();
+    v->done.push_back(out);
+    hosc_destroy(r.s);
+    arena_free(v, r.off, r.q.bytes);
+    v->completed += 1;
+    v->res[k] = v->res.back();
+    v->res.pop_back();
+}
+
+}  // namespace
 
 namespace {
 
@@ -2057,32 +2270,197 @@ hosc_status hosc_batch_perf_enable(hosc_batch *b, int32_t on)
     if (!b) return HOSC_E_ARG;
     b->F.prof = on != 0;
     b->F.perf = hosc_perf{};
-    for (hosc_solver *s : b->cav) {
-        hosc_status r = hosc_perf_enable(s, on);
-        if (r) return bfail(b, r, s->err);
-    }
     return HOSC_OK;
 }
 
 hosc_status hosc_batch_perf_get(hosc_batch *b, hosc_perf *out)
 {
     if (!b || !out) return HOSC_E_ARG;
-    hosc_perf p = b->F.perf;
-    for (hosc_solver *s : b->cav) {
-        hosc_perf c;
-        hosc_status r = hosc_perf_get(s, &c);
-        if (r) return bfail(b, r, s->err);
-        p.assemble_launches += c.assemble_launches;
-        p.assemble_ms += c.assemble_ms;
-        p.assemble_bytes += c.assemble_bytes;
-        p.bicg_launches += c.bicg_launches;
-        p.bicg_ms += c.bicg_ms;
-        p.bicg_bytes += c.bicg_bytes;
-    }
-    *out = p;
+    *out = b->F.perf;
+    return HOSC_OK;
+}
+
+hosc_status hosc_batch_graph_launches(const hosc_batch *b, int64_t *count)
+{
+    if (!b || !count) return HOSC_E_ARG;
+    *count = b->F.graph_launches;
     return HOSC_OK;
 }
 
 const char *hosc_batch_last_error(const hosc_batch *b) { return b ? b->err.c_str() : g_create_error.c_str(); }
+
+
+hosc_status hosc_server_create(size_t hbm_budget_bytes, int32_t max_resident, hipStream_t stream, hosc_server **out)
+{
+    if (!out) return sfail(nullptr, HOSC_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (max_resident < 1 || max_resident > 1024) return sfail(nullptr, HOSC_E_ARG, "max_resident must be in [1, 1024]");
+    if (hbm_budget_bytes < kAlign) return sfail(nullptr, HOSC_E_ARG, "budget too small");
+    hosc_server *v = new (std::nothrow) hosc_server();
+    if (!v) return sfail(nullptr, HOSC_E_NOMEM, "host allocation failed");
+    v->budget = hbm_budget_bytes / kAlign * kAlign;
+    v->max_resident = max_resident;
+    v->st = stream;
+    v->t0 = std::chrono::steady_clock::now();
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&v->arena), v->budget);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&v->d_fused), fused_device_bytes(max_resident));
+    if (e != hipSuccess) {
+        if (v->arena) (void)hipFree(v->arena);
+        delete v;
+        return sfail(nullptr, HOSC_E_NOMEM, std::string("device allocation of the server arena: ") + hipGetErrorString(e));
+    }
+    v->free_[0] = v->budget;
+    hosc_status r = fused_init(v->F, max_resident, v->d_fused, stream);
+    v->F.use_graphs = false;    // membership changes every few steps
+    if (r) {
+        const std::string msg = v->F.err;
+        fused_free(v->F);
+        (void)hipFree(v->d_fused);
+        (void)hipFree(v->arena);
+        delete v;
+        return sfail(nullptr, r, msg);
+    }
+    *out = v;
+    return HOSC_OK;
+}
+
+hosc_status hosc_server_destroy(hosc_server *v)
+{
+    if (!v) return HOSC_OK;
+    if (v->st) (void)hipStreamSynchronize(v->st);
+    for (auto &r : v->res) hosc_destroy(r.s);
+    fused_free(v->F);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(v->d_fused);
+    (void)hipFree(v->arena);
+    delete v;
+    return HOSC_OK;
+}
+
+hosc_status hosc_server_now(const hosc_server *v, double *t)
+{
+    if (!v || !t) return HOSC_E_ARG;
+    *t = v->now();
+    return HOSC_OK;
+}
+
+hosc_status hosc_server_submit(hosc_server *v, const hosc_request *rq, uint64_t *id)
+{
+    if (!v || !rq) return HOSC_E_ARG;
+    const char *e = check_params(&rq->params);
+    if (e) return sfail(v, HOSC_E_ARG, e);
+    if (!(rq->res_tol > 0.0) || rq->max_steps < 1) return sfail(v, HOSC_E_ARG, "res_tol > 0 and max_steps >= 1 required");
+    if (!std::isfinite(rq->noise_amp)) return sfail(v, HOSC_E_ARG, "noise_amp must be finite");
+    size_t bytes = 0;
+    hosc_status r = hosc_workspace_bytes(&rq->params, &bytes);
+    if (r) return sfail(v, r, g_create_error);
+    bytes = align_up(bytes);
+    if (bytes > v->budget) return sfail(v, HOSC_E_BUDGET, "request workspace exceeds the whole budget");
+    hosc_server::Req q;
+    q.id = v->next_id++;
+    q.rq = *rq;
+    if (q.rq.t_arrival < 0.0) q.rq.t_arrival = v->now();
+    q.bytes = bytes;
+    v->queue.push_back(q);
+    if (id) *id = q.id;
+    return HOSC_OK;
+}
+
+hosc_status hosc_server_step(hosc_server *v, int32_t *resident)
+{
+    if (!v) return HOSC_E_ARG;
+    const double t_in = v->now();
+    // admission: first come first served while the head fits
+    while (!v->queue.empty() && (int)v->res.size() < v->max_resident) {
+        const hosc_server::Req &q = v->queue.front();
+        const size_t off = arena_alloc(v, q.bytes);
+        if (off == SIZE_MAX) break;
+        hosc_solver *s = nullptr;
+        hosc_status r = hosc_create(&q.rq.params, v->arena + off, q.bytes, v->st, &s);
+        if (!r) r = hosc_init_fields(s, q.rq.seed, q.rq.noise_amp);
+        hosc_server::Res rs{q, s, off, v->now(), 0, 0.0};
+        v->queue.pop_front();
+        v->res.push_back(rs);
+        if (r) {
+            if (!s) {   // not created: report and release here
+                hosc_result out{};
+                out.id = rs.q.id;
+                out.status = r;
+                out.t_arrival = rs.q.rq.t_arrival;
+                out.t_admit = out.t_done = v->now();
+                v->done.push_back(out);
+                arena_free(v, off, rs.q.bytes);
+                v->completed += 1;
+                v->res.pop_back();
+            } else {
+                server_retire(v, v->res.size() - 1, r, false);
+            }
+        }
+    }
+    if (!v->res.empty()) {
+        // one fused step per precision
+        for (int prec = 0; prec < 2; ++prec) {
+            std::vector<size_t> idx;
+            std::vector<hosc_solver *> cav;
+            for (size_t k = 0; k < v->res.size(); ++k)
+                if ((int)v->res[k].s->fp32 == prec) {
+                    idx.push_back(k);
+                    cav.push_back(v->res[k].s);
+                }
+            if (cav.empty()) continue;
+            std::vector<hosc_step_info> info(cav.size());
+            std::vector<hosc_status> err(cav.size());
+            hosc_status r = fused_step(v->F, cav.data(), (int)cav.size(), info.data(), err.data());
+            if (r) return sfail(v, r, v->F.err);
+            for (size_t a = 0; a < cav.size(); ++a) {
+                hosc_server::Res &rs = v->res[idx[a]];
+                if (err[a]) continue;
+                rs.steps += 1;
+                rs.res = std::max(std::max(info[a].res[0], info[a].res[1]), std::max(info[a].res[2], info[a].res[3]));
+            }
+            v->cavity_steps += (int64_t)cav.size();
+            // retire in descending index order (swap-removal keeps lower indices valid)
+            for (size_t a = cav.size(); a-- > 0;) {
+                hosc_server::Res &rs = v->res[idx[a]];
+                if (err[a]) server_retire(v, idx[a], err[a], false);
+                else if (rs.res < rs.q.rq.res_tol) server_retire(v, idx[a], HOSC_OK, true);
+                else if (rs.steps >= rs.q.rq.max_steps) server_retire(v, idx[a], HOSC_OK, false);
+            }
+        }
+        v->server_steps += 1;
+    }
+    if (resident) *resident = (int32_t)v->res.size();
+    v->busy_s += v->now() - t_in;
+    return HOSC_OK;
+}
+
+hosc_status hosc_server_poll(hosc_server *v, hosc_result *out, int32_t max, int32_t *n_out)
+{
+    if (!v || !n_out || (max > 0 && !out)) return HOSC_E_ARG;
+    int n = 0;
+    while (n < max && !v->done.empty()) {
+        out[n++] = v->done.front();
+        v->done.pop_front();
+    }
+    *n_out = n;
+    return HOSC_OK;
+}
+
+hosc_status hosc_server_stats_get(const hosc_server *v, hosc_server_stats *st)
+{
+    if (!v || !st) return HOSC_E_ARG;
+    st->queued = (int64_t)v->queue.size();
+    st->resident = (int64_t)v->res.size();
+    st->completed = v->completed;
+    st->server_steps = v->server_steps;
+    st->cavity_steps = v->cavity_steps;
+    st->budget = v->budget;
+    st->in_use = v->in_use;
+    st->peak = v->peak;
+    st->busy_s = v->busy_s;
+    return HOSC_OK;
+}
+
+const char *hosc_server_last_error(const hosc_server *v) { return v ? v->err.c_str() : g_create_error.c_str(); }
 
 }  // extern "C"

@@ -66,6 +66,23 @@ class CPerf(ctypes.Structure):
                 ("refine_bytes", ctypes.c_double)]
 
 
+class CRequest(ctypes.Structure):
+    _fields_ = [("params", CParams), ("seed", ctypes.c_uint64), ("noise_amp", ctypes.c_double),
+                ("res_tol", ctypes.c_double), ("max_steps", ctypes.c_int64), ("t_arrival", ctypes.c_double)]
+
+
+class CResult(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("status", ctypes.c_int32), ("steady", ctypes.c_int32),
+                ("steps", ctypes.c_int64), ("res", ctypes.c_double), ("t_arrival", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double), ("diag", CDiag)]
+
+
+class CServerStats(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int64), ("resident", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("server_steps", ctypes.c_int64), ("cavity_steps", ctypes.c_int64), ("budget", ctypes.c_size_t),
+                ("in_use", ctypes.c_size_t), ("peak", ctypes.c_size_t), ("busy_s", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -112,6 +129,16 @@ def lib() -> ctypes.CDLL:
     L.hosc_batch_set_grid.argtypes = [vp, ctypes.c_int32]
     L.hosc_batch_perf_enable.argtypes = [vp, ctypes.c_int32]
     L.hosc_batch_perf_get.argtypes = [vp, ctypes.POINTER(CPerf)]
+    L.hosc_batch_graph_launches.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    L.hosc_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, vp, ctypes.POINTER(vp)]
+    L.hosc_server_destroy.argtypes = [vp]
+    L.hosc_server_now.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.hosc_server_submit.argtypes = [vp, ctypes.POINTER(CRequest), ctypes.POINTER(ctypes.c_uint64)]
+    L.hosc_server_step.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.hosc_server_poll.argtypes = [vp, ctypes.POINTER(CResult), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    L.hosc_server_stats_get.argtypes = [vp, ctypes.POINTER(CServerStats)]
+    L.hosc_server_last_error.argtypes = [vp]
+    L.hosc_server_last_error.restype = ctypes.c_char_p
     L.hosc_batch_last_error.argtypes = [vp]
     L.hosc_batch_last_error.restype = ctypes.c_char_p
     L.hosc_status_string.argtypes = [ctypes.c_int]
@@ -127,10 +154,15 @@ def _ptr(a):
     return a.ctypes.data_as(_dp)
 
 
-def _check(st: int, handle=None, batch=None):
+def _check(st: int, handle=None, batch=None, server=None):
     if st != 0:
         L = lib()
-        msg = L.hosc_batch_last_error(batch) if batch is not None else L.hosc_last_error(handle)
+        if server is not None:
+            msg = L.hosc_server_last_error(server)
+        elif batch is not None:
+            msg = L.hosc_batch_last_error(batch)
+        else:
+            msg = L.hosc_last_error(handle)
         raise HoscError(st, L.hosc_status_string(st).decode(), (msg or b"").decode())
 
 
@@ -310,7 +342,9 @@ class Batch:
         self.device = torch.device(device)
         with torch.cuda.device(self.device):
             self.ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
-            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            # a stream of its own (default priority): the per-step phases are captured
+            # as graphs, which the null stream does not allow
+            self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
             base = self.ws.data_ptr()
             off = (-base) % 256
             h = ctypes.c_void_p()
@@ -354,6 +388,14 @@ class Batch:
     def set_grid(self, grid: int):
         _check(lib().hosc_batch_set_grid(self.b, grid), batch=self.b)
 
+    def graph_launches(self) -> int:
+        c = ctypes.c_int64(0)
+        _check(lib().hosc_batch_graph_launches(self.b, ctypes.byref(c)), batch=self.b)
+        return c.value
+
+    def synchronize(self):
+        self.stream.synchronize()
+
     def perf_enable(self, on: bool = True):
         _check(lib().hosc_batch_perf_enable(self.b, int(on)), batch=self.b)
 
@@ -361,3 +403,63 @@ class Batch:
         c = CPerf()
         _check(lib().hosc_batch_perf_get(self.b, ctypes.byref(c)), batch=self.b)
         return {n: getattr(c, n) for n, _ in CPerf._fields_}
+
+
+class Server:
+    """Request loop over resident cavities (hosc_server_*): admission by HBM budget,
+    continuous fused batching, results with their arrival/admission/completion times."""
+
+    def __init__(self, budget_bytes: int, max_resident: int = 64, device: str = "cuda:0", stream=None):
+        import torch
+        self.device = torch.device(device)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+            h = ctypes.c_void_p()
+            _check(lib().hosc_server_create(budget_bytes, max_resident, ctypes.c_void_p(self.stream.cuda_stream),
+                                            ctypes.byref(h)), server=None)
+        self.v = h
+
+    def close(self):
+        if getattr(self, "v", None):
+            lib().hosc_server_destroy(self.v)
+            self.v = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def now(self) -> float:
+        t = ctypes.c_double(0.0)
+        _check(lib().hosc_server_now(self.v, ctypes.byref(t)), server=self.v)
+        return t.value
+
+    def submit(self, p: CParams, seed: int, noise: float = 1e-3, res_tol: float = 1e-8, max_steps: int = 1000,
+               t_arrival: float = -1.0) -> int:
+        rq = CRequest(p, seed, noise, res_tol, max_steps, t_arrival)
+        rid = ctypes.c_uint64(0)
+        _check(lib().hosc_server_submit(self.v, ctypes.byref(rq), ctypes.byref(rid)), server=self.v)
+        return rid.value
+
+    def step(self) -> int:
+        n = ctypes.c_int32(0)
+        _check(lib().hosc_server_step(self.v, ctypes.byref(n)), server=self.v)
+        return n.value
+
+    def poll(self, max_results: int = 256) -> list:
+        out = (CResult * max_results)()
+        n = ctypes.c_int32(0)
+        _check(lib().hosc_server_poll(self.v, out, max_results, ctypes.byref(n)), server=self.v)
+        res = []
+        for q in range(n.value):
+            c = out[q]
+            res.append(dict(id=c.id, status=c.status, steady=bool(c.steady), steps=c.steps, res=c.res,
+                            t_arrival=c.t_arrival, t_admit=c.t_admit, t_done=c.t_done,
+                            diag={f: getattr(c.diag, f) for f, _ in CDiag._fields_}))
+        return res
+
+    def stats(self) -> dict:
+        c = CServerStats()
+        _check(lib().hosc_server_stats_get(self.v, ctypes.byref(c)), server=self.v)
+        return {f: getattr(c, f) for f, _ in CServerStats._fields_}

@@ -2,7 +2,10 @@
 by fused solver launches (hosc_batch_*).  Every cavity must give the same result
 as its single-cavity run: the fused kernels compute each tile exactly as the
 single-cavity launch computes the block with the same index, and the solver
-control is shared, so the comparison is bitwise."""
+control is shared, so the comparison is bitwise.  From the second step on, the
+phases around the solves replay captured graphs, with the eager fused solves and
+host synchronisations between the replays; the sweep counts of every step and the
+final fields and diagnostics are compared."""
 import sys
 
 import numpy as np
@@ -55,6 +58,9 @@ def _compare(hosc, precision, grid, steps=12, tune=False):
     elif grid is not None:
         b.set_grid(grid)
     binfo = [b.step(1) for _ in range(steps)]
+    # steps 2..12 replay the captured pre- and post-solve phases (two each per step)
+    say(f"[batch] graph launches {b.graph_launches()}")
+    assert b.graph_launches() == 2 * (steps - 1)
     for i, p in enumerate(plist):
         g, d, infos = _solo(hosc, p, SEEDS[i], steps)
         gb = b.cavities[i].get_state()
