@@ -45,3 +45,41 @@ def test_create_rejects_bad_workspace():
     st = L.hosc_create(ctypes.byref(p), ctypes.c_void_p(256), 10, None, ctypes.byref(h))
     assert hosc.lib().hosc_status_string(st).decode() == "HOSC_E_NOMEM"
     assert b"workspace" in L.hosc_last_error(None)
+
+
+C_NAMES = {"lam": "lambda"}     # binding field names that differ from the C names (Python keywords)
+
+
+def _c_layout(structs):
+    """sizeof and every field offset of the ABI structs as a C compiler lays them
+    out from include/hosc.h."""
+    import os
+    import subprocess
+    import tempfile
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hosc.h"', "int main(void) {"]
+    for cname, ct in structs:
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in ct._fields_:
+            cf = C_NAMES.get(f, f)
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {cf}));')
+    lines.append("return 0; }")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "l.c"), os.path.join(d, "l")
+        with open(src, "w") as f:
+            f.write("\n".join(lines))
+        subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(root, "include"), "-I",
+                        "/opt/rocm/include", src, "-o", exe], check=True, capture_output=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
+    return dict((k, int(v)) for k, v in (ln.split() for ln in out.splitlines()))
+
+
+def test_binding_structs_match_the_c_layout():
+    structs = [("hosc_params", hosc.CParams), ("hosc_step_info", hosc.CStepInfo), ("hosc_diag", hosc.CDiag),
+               ("hosc_perf", hosc.CPerf), ("hosc_request", hosc.CRequest), ("hosc_result", hosc.CResult),
+               ("hosc_server_stats", hosc.CServerStats)]
+    c = _c_layout(structs)
+    for cname, ct in structs:
+        assert c[cname] == ctypes.sizeof(ct), cname
+        for f, _ in ct._fields_:
+            assert c[f"{cname}.{f}"] == getattr(ct, f).offset, (cname, f)
