@@ -161,6 +161,34 @@ __global__ void __launch_bounds__(64) k_gather(const double *const *__restrict__
 }
 
 // ---------------------------------------------------------------------------
+// XCD-aware tile order.  Workgroups reach the eight XCDs round-robin by linear id;
+// slot(b) = (b mod 8)(G/8) + b/8 (when 8 divides G) hands each XCD a contiguous
+// run of tiles, so the rows and planes that neighbouring tiles share are read
+// into the same L2.  Tile ids (and the partial-sum records indexed by them) are
+// the plain linear order, so reductions see the same records in the same order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int persistent_slot(int b, int G)
+{
+    return (G & 7) ? b : (b & 7) * (G >> 3) + (b >> 3);
+}
+
+struct Tile {
+    int x, y, z, id;
+};
+__device__ __forceinline__ Tile xcd_tile()
+{
+    const int G = gridDim.x * gridDim.y * gridDim.z;
+    const int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    Tile t;
+    t.id = persistent_slot(b, G);
+    t.x = t.id % gridDim.x;
+    const int rest = t.id / gridDim.x;
+    t.y = rest % gridDim.y;
+    t.z = rest / gridDim.y;
+    return t;
+}
+
+// ---------------------------------------------------------------------------
 // Derivatives at any node: central inside, 2nd-order one-sided on a wall normal to
 // the axis (velocity, eta, theta); the wall-normal pressure derivative is zero.
 // ---------------------------------------------------------------------------
@@ -208,7 +236,8 @@ __device__ __forceinline__ double strain_I2(const VelGrad &d)
 __global__ void __launch_bounds__(256) k_eta(Geo g, Phys P, const double *__restrict__ u, const double *__restrict__ v,
                                              const double *__restrict__ w, double *__restrict__ eta)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y * blockDim.y + threadIdx.y, k = blockIdx.z;
+    const Tile tl = xcd_tile();
+    const int i = tl.x * blockDim.x + threadIdx.x, j = tl.y * blockDim.y + threadIdx.y, k = tl.z;
     if (i >= g.N || j >= g.N) return;
     const VelGrad d = vel_grad(g, u, v, w, i, j, k);
     eta[nid(g, i, j, k)] = pow(fmax(strain_I2(d), P.i2_floor), P.ex);
@@ -223,7 +252,8 @@ __global__ void __launch_bounds__(256) k_estar(Geo g, Phys P, const double *__re
                                                const double *__restrict__ eta, double *__restrict__ Eu,
                                                double *__restrict__ Ev, double *__restrict__ Ew)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y * blockDim.y + threadIdx.y, k = blockIdx.z;
+    const Tile tl = xcd_tile();
+    const int i = tl.x * blockDim.x + threadIdx.x, j = tl.y * blockDim.y + threadIdx.y, k = tl.z;
     if (i >= g.N || j >= g.N) return;
     const size_t c = nid(g, i, j, k), sy = (size_t)g.N, sz = (size_t)g.N * g.N;
     const VelGrad d = vel_grad(g, u, v, w, i, j, k);
@@ -459,8 +489,8 @@ __global__ void __launch_bounds__(256) k_assemble(Geo g, Phys P, const double *_
                                                   ColourArrays ca, double *__restrict__ partial,
                                                   double *__restrict__ partial_dom)
 {
-    const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x, j = 1 + blockIdx.y * blockDim.y + threadIdx.y,
-              k = 1 + blockIdx.z;
+    const Tile tl = xcd_tile();
+    const int i = 1 + tl.x * blockDim.x + threadIdx.x, j = 1 + tl.y * blockDim.y + threadIdx.y, k = 1 + tl.z;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     double dom[2] = {0.0, 0.0};     // off-diagonal sum / |centre| of the momentum and energy rows
     if (i <= g.N - 2 && j <= g.N - 2) {
@@ -496,7 +526,7 @@ __global__ void __launch_bounds__(256) k_assemble(Geo g, Phys P, const double *_
         dom[0] = om / fabs(a.Cm);
         dom[1] = ot / fabs(a.Ct);
     }
-    const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const int blk = tl.id;
     block_sum_store<4>(acc, partial + (size_t)blk * 4);
     block_max_store<2>(dom, partial_dom + (size_t)blk * 2);
 }
@@ -511,8 +541,8 @@ __global__ void __launch_bounds__(256) k_assemble_debug(Geo g, Phys P, const dou
                                                         const double *etap, const double *Eup, const double *Evp,
                                                         const double *Ewp, int what, double *out)
 {
-    const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x, j = 1 + blockIdx.y * blockDim.y + threadIdx.y,
-              k = 1 + blockIdx.z;
+    const Tile tl = xcd_tile();
+    const int i = 1 + tl.x * blockDim.x + threadIdx.x, j = 1 + tl.y * blockDim.y + threadIdx.y, k = 1 + tl.z;
     if (i > g.N - 2 || j > g.N - 2) return;
     NodeAssembly a;
     assemble_node(g, P, i, j, k, u, v, w, T, eta, Eu, Ev, Ew, up, vp, wp, etap, Eup, Evp, Ewp, a);
@@ -656,12 +686,13 @@ __global__ void __launch_bounds__(256) k_sweep(Geo g, int colour, int mask, TA o
                                                SweepArgs<TM> a, double *__restrict__ partial, unsigned store,
                                                double *__restrict__ partial0, unsigned store0)
 {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y, k = 1 + blockIdx.z;
+    const Tile tl = xcd_tile();
+    const int q = tl.x * blockDim.x + threadIdx.x;
+    const int j = 1 + tl.y * blockDim.y + threadIdx.y, k = 1 + tl.z;
     double r2[4] = {0.0, 0.0, 0.0, 0.0};
     sweep_node<TM, TA>(g, colour, mask, omega_m, omega_t, st, a, q, j, k, r2);
     if (store | store0) {
-        const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+        const int blk = tl.id;
         block_sum_store2<4>(r2, partial + (size_t)blk * 4, store, partial0 + (size_t)blk * 4, store0);
     }
 }
@@ -696,10 +727,6 @@ __device__ __forceinline__ int find_cavity(const TileMap *__restrict__ map, int 
     return lo;
 }
 
-__device__ __forceinline__ int persistent_slot(int b, int G)
-{
-    return (G & 7) ? b : (b & 7) * (G >> 3) + (b >> 3);
-}
 
 template <typename TM, typename TA>
 struct FusedSweepCav {
@@ -758,11 +785,12 @@ struct BicgArgs {
     TM *x[4], *r[4], *rh[4], *p[4], *pn[4], *v[4], *vn[4], *t[4];
 };
 
-__device__ __forceinline__ bool bicg_node(const Geo &g, int q, int &j, int &k, int &colour, RowIdx &r)
+__device__ __forceinline__ bool bicg_node(const Geo &g, const Tile &tl, int q, int &j, int &k, int &colour,
+                                          RowIdx &r)
 {
-    j = 1 + blockIdx.y * blockDim.y + threadIdx.y;
-    k = 1 + (blockIdx.z >> 1);
-    colour = blockIdx.z & 1;
+    j = 1 + tl.y * blockDim.y + threadIdx.y;
+    k = 1 + (tl.z >> 1);
+    colour = tl.z & 1;
     return row_index(g, colour, q, j, k, r);
 }
 
@@ -774,11 +802,12 @@ template <typename TR, typename TM, typename TA>
 __global__ void __launch_bounds__(256) k_bicg(Geo g, int phase, int mask, TA st, BicgArgs<TR, TM> a,
                                               const double *__restrict__ sc, double *__restrict__ partial)
 {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const Tile tl = xcd_tile();
+    const int q = tl.x * blockDim.x + threadIdx.x;
     int j, k, colour;
     RowIdx r;
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (bicg_node(g, q, j, k, colour, r)) {
+    if (bicg_node(g, tl, q, j, k, colour, r)) {
         TA ms = 0, max = 0, may = 0, maz = 0, tax = 0, tay = 0, taz = 0;
         if (mask & 1) {
             ms = (TA)a.ms[r.me]; max = (TA)a.ma[0][r.me]; may = (TA)a.ma[1][r.me]; maz = (TA)a.ma[2][r.me];
@@ -836,7 +865,7 @@ __global__ void __launch_bounds__(256) k_bicg(Geo g, int phase, int mask, TA st,
             }
         }
     }
-    const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const int blk = tl.id;
     block_sum_store<8>(acc, partial + (size_t)blk * 8);
 }
 
@@ -933,11 +962,12 @@ template <typename TR>
 __global__ void __launch_bounds__(256) k_refine_residual(Geo g, int colour, int mask, double st, RefineArgs<TR> a,
                                                          double *__restrict__ partial)
 {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y, k = 1 + blockIdx.z;
+    const Tile tl = xcd_tile();
+    const int q = tl.x * blockDim.x + threadIdx.x;
+    const int j = 1 + tl.y * blockDim.y + threadIdx.y, k = 1 + tl.z;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     refine_node<TR>(g, colour, mask, st, a, q, j, k, acc);
-    const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const int blk = tl.id;
     block_sum_store<4>(acc, partial + (size_t)blk * 4);
 }
 
@@ -985,8 +1015,8 @@ __global__ void __launch_bounds__(256) k_update(Geo g, const double *__restrict_
                                                 const double *__restrict__ dv, const double *__restrict__ dw,
                                                 const double *__restrict__ dT, double *__restrict__ partial)
 {
-    const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x, j = 1 + blockIdx.y * blockDim.y + threadIdx.y,
-              k = 1 + blockIdx.z;
+    const Tile tl = xcd_tile();
+    const int i = 1 + tl.x * blockDim.x + threadIdx.x, j = 1 + tl.y * blockDim.y + threadIdx.y, k = 1 + tl.z;
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (i <= g.N - 2 && j <= g.N - 2) {
         const size_t c = nid(g, i, j, k);
@@ -1000,7 +1030,7 @@ __global__ void __launch_bounds__(256) k_update(Geo g, const double *__restrict_
         acc[0] = a * a; acc[1] = b * b; acc[2] = e * e; acc[3] = t * t;
         acc[4] = nu * nu; acc[5] = nv * nv; acc[6] = nw * nw; acc[7] = nt * nt;
     }
-    const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const int blk = tl.id;
     block_sum_store<8>(acc, partial + (size_t)blk * 8);
 }
 
@@ -1107,8 +1137,8 @@ __global__ void __launch_bounds__(256) k_divergence(Geo g, Phys P, const double 
                                                     double *__restrict__ p, double *__restrict__ dstore, int apply,
                                                     double *__restrict__ partial)
 {
-    const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x, j = 1 + blockIdx.y * blockDim.y + threadIdx.y,
-              k = 1 + blockIdx.z;
+    const Tile tl = xcd_tile();
+    const int i = 1 + tl.x * blockDim.x + threadIdx.x, j = 1 + tl.y * blockDim.y + threadIdx.y, k = 1 + tl.z;
     double acc[1] = {0.0};
     if (i <= g.N - 2 && j <= g.N - 2) {
         const size_t c = nid(g, i, j, k), sy = (size_t)g.N, sz = (size_t)g.N * g.N;
@@ -1118,7 +1148,7 @@ __global__ void __launch_bounds__(256) k_divergence(Geo g, Phys P, const double 
         if (apply) p[c] -= P.lambda * D;
         if (dstore) dstore[c] = D;
     }
-    const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const int blk = tl.id;
     block_max_store<1>(acc, partial + blk);
 }
 
@@ -1127,8 +1157,8 @@ __global__ void __launch_bounds__(256) k_divergence(Geo g, Phys P, const double 
 __global__ void __launch_bounds__(256) k_pressure_apply(Geo g, Phys P, const double *__restrict__ dstore,
                                                         double *__restrict__ p)
 {
-    const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x, j = 1 + blockIdx.y * blockDim.y + threadIdx.y,
-              k = 1 + blockIdx.z;
+    const Tile tl = xcd_tile();
+    const int i = 1 + tl.x * blockDim.x + threadIdx.x, j = 1 + tl.y * blockDim.y + threadIdx.y, k = 1 + tl.z;
     if (i <= g.N - 2 && j <= g.N - 2) {
         const size_t c = nid(g, i, j, k);
         p[c] -= P.lambda * dstore[c];
@@ -1222,7 +1252,8 @@ __global__ void __launch_bounds__(256) k_entropy(Geo g, Phys P, const double *__
                                                  double *__restrict__ el, double *__restrict__ bl,
                                                  double *__restrict__ partial)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y * blockDim.y + threadIdx.y, k = blockIdx.z;
+    const Tile tl = xcd_tile();
+    const int i = tl.x * blockDim.x + threadIdx.x, j = tl.y * blockDim.y + threadIdx.y, k = tl.z;
     double acc[3] = {0.0, 0.0, 0.0};
     if (i < g.N && j < g.N) {
         const size_t c = nid(g, i, j, k), sy = (size_t)g.N, sz = (size_t)g.N * g.N;
@@ -1242,7 +1273,7 @@ __global__ void __launch_bounds__(256) k_entropy(Geo g, Phys P, const double *__
         if (el) el[c] = e;
         if (bl) bl[c] = be;
     }
-    const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const int blk = tl.id;
     block_sum_store<3>(acc, partial + (size_t)blk * 3);
 }
 
