@@ -627,10 +627,17 @@ hosc_status sor_decide(hosc_solver *s, SorCtl &c, const double *hb, double bn2[4
         if (c.adapt && rate > 0.0 && rate < 1.0 && c.plan[grp] >= 4 && !(c.inner && c.batch == 0)) {
             // below the optimum the contraction exceeds w - 1 and Young's relation
             // gives the optimum; at or past it the contraction is about w - 1: back off
+            // by a fraction of the over-relaxation
             const double w = s->om[grp];
-            double wn = (w > 1.05 && rate < (w - 1.0) + 0.02) ? w - 0.03 : young_omega(rate, w);
+            double wn = (w > 1.05 && rate < (w - 1.0) + 0.02) ? 1.0 + 0.7 * (w - 1.0) : young_omega(rate, w);
             wn = std::min(1.9, std::max(1.0, wn));
             s->om[grp] = w + 0.5 * (wn - w);
+        }
+        if (c.adapt && c.batch == 0 && finite) {
+            // this step's dominance monitor bounds the Jacobi radius (Gershgorin): the
+            // relaxation it implies is the most this step's rows can use
+            const double mu = std::min(0.98, hb[44 + grp]);
+            if (mu > 0.0 && std::isfinite(mu)) s->om[grp] = std::min(s->om[grp], 2.0 / (1.0 + std::sqrt(1.0 - mu * mu)));
         }
         if (finite && conv) {
             for (int f = f0; f < f1; ++f)
@@ -1058,9 +1065,14 @@ hosc_status pre_solve(hosc_solver *s)
     }
     r = timed_begin(s);
     if (r) return r;
-    k_assemble<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, s->ph, s->u, s->v, s->w, s->T, s->eta, s->E[0],
-                                                         s->E[1], s->E[2], s->u2, s->v2, s->w2, s->etap, s->Ep[0],
-                                                         s->Ep[1], s->Ep[2], ca, s->partR, s->partB);
+    if (s->fp32)
+        k_assemble<true><<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(
+            s->g, s->ph, s->u, s->v, s->w, s->T, s->eta, s->E[0], s->E[1], s->E[2], s->u2, s->v2, s->w2, s->etap,
+            s->Ep[0], s->Ep[1], s->Ep[2], ca, s->partR, s->partB);
+    else
+        k_assemble<false><<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(
+            s->g, s->ph, s->u, s->v, s->w, s->T, s->eta, s->E[0], s->E[1], s->E[2], s->u2, s->v2, s->w2, s->etap,
+            s->Ep[0], s->Ep[1], s->Ep[2], ca, s->partR, s->partB);
     r = timed_end(s, 1, assemble_bytes(s->g));
     if (r) return r;
     k_reduce<<<1, 1024, 0, s->st>>>(s->partR, (int)s->L.nb_int, 4, 0, s->red);

@@ -476,8 +476,11 @@ struct ColourArrays {
 };
 
 // Assemble every interior node and write the scaled rows in the colour layout
-// (FP64, plus FP32 copies of the rows in the precision mode); per-block partial
-// sums of ||b/C||^2 for the four systems and the largest off-diagonal/centre ratio.
+// (FP64, plus FP32 copies of the rows when F32: the precision mode); per-block
+// partial sums of ||b/C||^2 for the four systems and the largest
+// off-diagonal/centre ratio.  (The FP32 stores are a separate instantiation: they
+// push the FP64 kernel past the register budget of two waves per SIMD.)
+template <bool F32>
 __global__ void __launch_bounds__(256) k_assemble(Geo g, Phys P, const double *__restrict__ u,
                                                   const double *__restrict__ v, const double *__restrict__ w,
                                                   const double *__restrict__ T, const double *__restrict__ eta,
@@ -500,13 +503,13 @@ __global__ void __launch_bounds__(256) k_assemble(Geo g, Phys P, const double *_
         const double rm = 1.0 / a.Cm, rt = 1.0 / a.Ct;
         const double sm = a.sm * rm;
         ca.ms[idx] = sm;
-        if (ca.fms) ca.fms[idx] = (float)sm;
+        if (F32) ca.fms[idx] = (float)sm;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             const double am = a.am[d] * rm, at = a.at[d] * rt;
             ca.ma[d][idx] = am;
             ca.ta[d][idx] = at;
-            if (ca.fms) {
+            if (F32) {
                 ca.fma[d][idx] = (float)am;
                 ca.fta[d][idx] = (float)at;
             }
