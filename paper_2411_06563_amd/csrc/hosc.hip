@@ -207,6 +207,7 @@ struct hosc_solver {
     int last_sweeps[2] = {0, 0};
     int last_bicg[2] = {0, 0};
     double om[2] = {1.0, 1.0};          // SOR relaxation of each group (adaptive when P.omega == 0)
+    int64_t seeded_at = -1;             // step whose dominance bound was last applied to om
     std::string err;
     // kernel timing
     bool prof = false;
@@ -419,6 +420,7 @@ hosc_status reset_state(hosc_solver *s)
     s->last_bicg[0] = s->last_bicg[1] = 0;
     s->bicg_until[0] = s->bicg_until[1] = -1;
     s->om[0] = s->om[1] = s->P.omega > 0.0 ? s->P.omega : 1.0;
+    s->seeded_at = -1;
     HIPCHK(s, hipStreamSynchronize(s->st));
     return HOSC_OK;
 }
@@ -554,14 +556,29 @@ void sor_begin(const hosc_solver *s, SorCtl &c, int mask, double rtol, bool inne
     c.first_plan[1] = c.plan[1];
 }
 
-// first step after a state was set: seed the relaxation from the dominance monitor
-// of the assembly (dom = red[44..45]), a Gershgorin bound mu on the Jacobi radius
-bool sor_wants_seed(const hosc_solver *s, const SorCtl &c) { return c.adapt && s->step == 0; }
-void sor_seed(hosc_solver *s, const double *dom)
+// The dominance monitor of this step's assembly (dom = red[44..45]) is a
+// Gershgorin bound mu on the Jacobi radius; the relaxation it implies,
+// 2 / (1 + sqrt(1 - mu^2)), seeds the first step after a state was set and caps
+// the adapted relaxation at every later step, before the first sweep.
+// A group whose relaxation the cap lowers by more than 0.05 halves its first batch:
+// the sweep count it inherited was measured at the old relaxation.
+bool sor_wants_seed(const hosc_solver *s, const SorCtl &c) { return c.adapt && s->seeded_at != s->step; }
+void sor_seed(hosc_solver *s, SorCtl &c, const double *dom)
 {
+    s->seeded_at = s->step;
     for (int grp = 0; grp < 2; ++grp) {
         const double mu = std::min(0.98, dom[grp]);
-        if (mu > 0.0 && std::isfinite(mu)) s->om[grp] = 2.0 / (1.0 + std::sqrt(1.0 - mu * mu));
+        if (!(mu > 0.0 && std::isfinite(mu))) continue;
+        const double w = 2.0 / (1.0 + std::sqrt(1.0 - mu * mu));
+        if (s->step == 0) {
+            s->om[grp] = w;
+        } else if (w < s->om[grp]) {
+            if (s->om[grp] - w > 0.05 && s->P.check_every == 0) {
+                c.plan[grp] = std::max(2, c.plan[grp] / 2);
+                c.first_plan[grp] = c.plan[grp];
+            }
+            s->om[grp] = w;
+        }
     }
 }
 
@@ -633,12 +650,6 @@ hosc_status sor_decide(hosc_solver *s, SorCtl &c, const double *hb, double bn2[4
             wn = std::min(1.9, std::max(1.0, wn));
             s->om[grp] = w + 0.5 * (wn - w);
         }
-        if (c.adapt && c.batch == 0 && finite) {
-            // this step's dominance monitor bounds the Jacobi radius (Gershgorin): the
-            // relaxation it implies is the most this step's rows can use
-            const double mu = std::min(0.98, hb[44 + grp]);
-            if (mu > 0.0 && std::isfinite(mu)) s->om[grp] = std::min(s->om[grp], 2.0 / (1.0 + std::sqrt(1.0 - mu * mu)));
-        }
         if (finite && conv) {
             for (int f = f0; f < f1; ++f)
                 if (bn2[f] == 0.0) {
@@ -709,7 +720,7 @@ hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *f
     if (sor_wants_seed(s, c)) {
         HIPCHK(s, hipMemcpyAsync(s->hbuf + 44, s->red + 44, 2 * sizeof(double), hipMemcpyDeviceToHost, s->st));
         HIPCHK(s, hipStreamSynchronize(s->st));
-        sor_seed(s, s->hbuf + 44);
+        sor_seed(s, c, s->hbuf + 44);
     }
     while (c.active) {
         const int nsw = sor_batch_sweeps(c);
@@ -1333,7 +1344,7 @@ hosc_status fused_sor(Fused &F, hosc_solver *const *cav, int n, const int *mask,
         hosc_status r = fused_reduce_gather(F, 0, ns, 48);
         if (r) return r;
         for (int a = 0; a < ns; ++a)
-            if (sor_wants_seed(cav[act[a]], c[act[a]])) sor_seed(cav[act[a]], F.h_gather + 48 * a + 44);
+            if (sor_wants_seed(cav[act[a]], c[act[a]])) sor_seed(cav[act[a]], c[act[a]], F.h_gather + 48 * a + 44);
     }
     for (;;) {
         int nact = 0, total = 0, nsw = 0, nj = 0;
