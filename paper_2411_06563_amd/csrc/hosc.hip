@@ -303,7 +303,9 @@ double sweep_bytes(const Geo &g, int mask, size_t elem = sizeof(double))
 {
     const double nodes = 0.5 * (double)(g.N - 2) * (g.N - 2) * (g.N - 2);
     double per = 0.0;
-    if (mask & 1) per += (7 + 3 + 3 + 3) * elem;   // row 4 + rhs 3, own 3 read + 3 write, other colour 3
+    int nf = 0;     // momentum fields swept
+    for (int f = 0; f < 3; ++f) nf += ((mask >> (2 + f)) & 1) ? 0 : 1;
+    if (mask & 1) per += (4 + 4 * nf) * elem;   // row 4; per field rhs 1, own 1 read + 1 write, other colour 1
     if (mask & 2) per += (4 + 1 + 1 + 1) * elem;   // row 3 + rhs 1, own 1 + 1, other colour 1
     return nodes * per;
 }
@@ -478,6 +480,24 @@ SweepArgs<float> sweep_args_fp32(hosc_solver *s)
     return a;
 }
 
+// Launch up to four reductions in one kernel (jobs in order; n <= 4).
+struct Reductions {
+    ReduceJobs4 r{};
+    int n = 0;
+    Reductions &add(const double *part, size_t nb, int nc, int op, double *out)
+    {
+        ReduceJob &j = r.j[n++];
+        j.part = part;
+        j.nb = (int)nb;
+        j.nc = nc;
+        j.op = op;
+        j.out = out;
+        j.pad = 0;
+        return *this;
+    }
+    void launch(hipStream_t st) const { k_reduce4<<<n, 1024, 0, st>>>(r); }
+};
+
 // Algorithmic bytes of one BiCGSTAB phase launch over both colours.
 double bicg_bytes(const Geo &g, int phase, int mask)
 {
@@ -532,6 +552,7 @@ double young_omega(double lam, double w)
 // cavity takes the same decisions (sweep plans, relaxation, stopping) either way.
 struct SorCtl {
     int active = 0, failed = 0, batch = 0, soft_cap = 0;
+    int skip = 0;       // momentum fields with a zero right-hand side (bits 0..2): not swept
     bool inner = false, adapt = false, autom = false;
     double rtol = 0.0;
     double ref[2] = {-1.0, -1.0};
@@ -541,6 +562,16 @@ struct SorCtl {
 // inner solves of the refinement: at most 200 sweeps, and no relaxation update
 // from a first batch (a short batch that starts from zero measures the start-up
 // transient, not the asymptotic contraction Young's relation needs)
+// Momentum fields with ||b|| = 0 have the zero increment: the sweeps leave them
+// out (their increments are zeroed when the group converges).
+void sor_skip(SorCtl &c, const double bn2[4])
+{
+    c.skip = 0;
+    if (bn2[0] >= 0.0)
+        for (int f = 0; f < 3; ++f)
+            if (bn2[f] == 0.0) c.skip |= 1 << f;
+}
+
 void sor_begin(const hosc_solver *s, SorCtl &c, int mask, double rtol, bool inner)
 {
     c = SorCtl();
@@ -590,7 +621,7 @@ void sor_sweep_flags(const SorCtl &c, int q, int &m, unsigned &store, unsigned &
     store = store0 = 0;
     for (int grp = 0; grp < 2; ++grp) {
         if (!(c.active & (1 << grp)) || q >= c.plan[grp]) continue;
-        m |= 1 << grp;
+        m |= grp == 0 ? 1 | (c.skip << 2) : 2;
         if (q == c.plan[grp] - 1) store |= kStore[grp];
         if (q == 0 && c.plan[grp] > 1) store0 |= kStore[grp];
     }
@@ -718,10 +749,16 @@ hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *f
     sor_begin(s, c, mask, rtol, inner);
     *failed = 0;
     if (sor_wants_seed(s, c)) {
-        HIPCHK(s, hipMemcpyAsync(s->hbuf + 44, s->red + 44, 2 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+        HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red, 48 * sizeof(double), hipMemcpyDeviceToHost, s->st));
         HIPCHK(s, hipStreamSynchronize(s->st));
         sor_seed(s, c, s->hbuf + 44);
+        if (bn2[0] < 0.0) {
+            for (int f = 0; f < 4; ++f) bn2[f] = s->hbuf[f];
+            for (int f = 0; f < 4; ++f)
+                if (!std::isfinite(bn2[f])) return fail(s, HOSC_E_NONFINITE, "non-finite right-hand side");
+        }
     }
+    sor_skip(c, bn2);
     while (c.active) {
         const int nsw = sor_batch_sweeps(c);
         hosc_status r = timed_begin(s);
@@ -741,10 +778,12 @@ hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *f
         if (r) return r;
         r = launch_check(s, "sweep");
         if (r) return r;
-        k_reduce<<<1, 1024, 0, s->st>>>(s->partR, (int)s->L.nb_sw, 4, 0, s->red + 4);
-        k_reduce<<<1, 1024, 0, s->st>>>(s->partB, (int)s->L.nb_sw, 4, 0, s->red + 8);
-        k_reduce<<<1, 1024, 0, s->st>>>(s->partR0, (int)s->L.nb_sw, 4, 0, s->red + 32);
-        k_reduce<<<1, 1024, 0, s->st>>>(s->partB0, (int)s->L.nb_sw, 4, 0, s->red + 36);
+        Reductions()
+            .add(s->partR, s->L.nb_sw, 4, 0, s->red + 4)
+            .add(s->partB, s->L.nb_sw, 4, 0, s->red + 8)
+            .add(s->partR0, s->L.nb_sw, 4, 0, s->red + 32)
+            .add(s->partB0, s->L.nb_sw, 4, 0, s->red + 36)
+            .launch(s->st);
         HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red, 48 * sizeof(double), hipMemcpyDeviceToHost, s->st));
         HIPCHK(s, hipStreamSynchronize(s->st));
         r = harvest_events(s);
@@ -990,8 +1029,7 @@ hosc_status solve_refined(hosc_solver *s, int mask, double bn2[4], SolveOut &o, 
         if (r) return r;
         r = launch_check(s, "refine residual");
         if (r) return r;
-        k_reduce<<<1, 1024, 0, s->st>>>(s->partR, (int)s->L.nb_sw, 4, 0, s->red + 48);
-        k_reduce<<<1, 1024, 0, s->st>>>(s->partB, (int)s->L.nb_sw, 4, 0, s->red + 52);
+        Reductions().add(s->partR, s->L.nb_sw, 4, 0, s->red + 48).add(s->partB, s->L.nb_sw, 4, 0, s->red + 52).launch(s->st);
         HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red, 56 * sizeof(double), hipMemcpyDeviceToHost, s->st));
         HIPCHK(s, hipStreamSynchronize(s->st));
         r = harvest_events(s);
@@ -1086,8 +1124,7 @@ hosc_status pre_solve(hosc_solver *s)
             s->Ep[0], s->Ep[1], s->Ep[2], ca, s->partR, s->partB);
     r = timed_end(s, 1, assemble_bytes(s->g));
     if (r) return r;
-    k_reduce<<<1, 1024, 0, s->st>>>(s->partR, (int)s->L.nb_int, 4, 0, s->red);
-    k_reduce<<<1, 1024, 0, s->st>>>(s->partB, (int)s->L.nb_int, 2, 1, s->red + 44);
+    Reductions().add(s->partR, s->L.nb_int, 4, 0, s->red).add(s->partB, s->L.nb_int, 2, 1, s->red + 44).launch(s->st);
     return launch_check(s, "assemble");
 }
 
@@ -1098,13 +1135,15 @@ hosc_status post_launch(hosc_solver *s)
     // update: u, v, w into the level n-1 buffers (which become level n+1)
     k_update<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, s->u, s->v, s->w, s->u2, s->v2, s->w2, s->T, s->md[0],
                                                        s->md[1], s->md[2], s->td, s->partR);
-    k_reduce<<<1, 1024, 0, s->st>>>(s->partR, (int)s->L.nb_int, 8, 0, s->red + 12);
     k_theta_walls<<<s->L.grd_face, s->L.blk_face, 0, s->st>>>(s->g, s->ph, s->T, s->partB);
-    k_reduce<<<1, 1024, 0, s->st>>>(s->partB, (int)s->L.nb_face, 2, 0, s->red + 20);
     const bool gate = s->P.div_tol > 0.0;
     k_divergence<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, s->ph, s->u2, s->v2, s->w2, s->p,
-                                                           gate ? s->dbg : nullptr, gate ? 0 : 1, s->partR);
-    k_reduce<<<1, 1024, 0, s->st>>>(s->partR, (int)s->L.nb_int, 1, 1, s->red + 22);
+                                                           gate ? s->dbg : nullptr, gate ? 0 : 1, s->partR0);
+    Reductions()
+        .add(s->partR, s->L.nb_int, 8, 0, s->red + 12)
+        .add(s->partB, s->L.nb_face, 2, 0, s->red + 20)
+        .add(s->partR0, s->L.nb_int, 1, 1, s->red + 22)
+        .launch(s->st);
     if (!gate) k_p_walls<<<s->L.grd_face, s->L.blk_face, 0, s->st>>>(s->g, s->p);
     return launch_check(s, "update/divergence");
 }
@@ -1343,9 +1382,21 @@ hosc_status fused_sor(Fused &F, hosc_solver *const *cav, int n, const int *mask,
         FHIPCHK(F, hipMemcpyAsync(F.d_tab, F.h_tab, F.tab_bytes, hipMemcpyHostToDevice, F.st));
         hosc_status r = fused_reduce_gather(F, 0, ns, 48);
         if (r) return r;
-        for (int a = 0; a < ns; ++a)
-            if (sor_wants_seed(cav[act[a]], c[act[a]])) sor_seed(cav[act[a]], c[act[a]], F.h_gather + 48 * a + 44);
+        for (int a = 0; a < ns; ++a) {
+            const int i = act[a];
+            if (sor_wants_seed(cav[i], c[i])) sor_seed(cav[i], c[i], F.h_gather + 48 * a + 44);
+            if (bn2[i][0] < 0.0) {
+                for (int f = 0; f < 4; ++f) bn2[i][f] = F.h_gather[48 * a + f];
+                for (int f = 0; f < 4; ++f)
+                    if (!std::isfinite(bn2[i][f])) {
+                        err[i] = fail(cav[i], HOSC_E_NONFINITE, "non-finite right-hand side");
+                        c[i].active = 0;
+                    }
+            }
+        }
     }
+    for (int i = 0; i < n; ++i)
+        if (!err[i] && mask[i]) sor_skip(c[i], bn2[i]);
     for (;;) {
         int nact = 0, total = 0, nsw = 0, nj = 0;
         double bytes = 0.0;
@@ -1361,6 +1412,7 @@ hosc_status fused_sor(Fused &F, hosc_solver *const *cav, int n, const int *mask,
             cv.st = (TM)theta_st(s);
             cv.plan_m = (c[i].active & 1) ? c[i].plan[0] : 0;
             cv.plan_t = (c[i].active & 2) ? c[i].plan[1] : 0;
+            cv.skip = c[i].skip;
             cv.part[0] = s->partR;
             cv.part[1] = s->partB;
             cv.part0[0] = s->partR0;
@@ -1646,6 +1698,7 @@ hosc_status fused_tune(Fused &F, hosc_solver *const *cav, int n, int *best_grid)
         cv.omega_m = cv.omega_t = (TM)1;
         cv.st = (TM)theta_st(s);
         cv.plan_m = cv.plan_t = 1;
+        cv.skip = 0;
         cv.part[0] = s->partR;
         cv.part[1] = s->partB;
         cv.part0[0] = s->partR0;

@@ -115,23 +115,31 @@ __device__ __forceinline__ void block_max_store(double (&v)[NV], double *out)
 }
 
 // Reduce nb partial records of nc <= 8 values (record b at part[b*nc ...]) with one
-// block of 1024 threads; op 0 = sum, 1 = max.  Fixed order: deterministic.
+// block of 1024 threads; op 0 = sum, 1 = max.  Thread t folds records t, t+1024, ...
+// in order, then a fixed shuffle tree inside each wavefront and a fixed-order pass
+// over the 16 wavefronts: deterministic.
 __device__ __forceinline__ void reduce_block(const double *part, int nb, int nc, int op, double *out)
 {
-    __shared__ double sh[8][1024];
-    const int t = threadIdx.x;
+    __shared__ double sh[8][16];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     for (int c = 0; c < nc; ++c) {
         double s = op == 0 ? 0.0 : -HUGE_VAL;
-        for (int b = t; b < nb; b += 1024) s = op == 0 ? s + part[(size_t)b * nc + c] : nanmax(s, part[(size_t)b * nc + c]);
-        sh[c][t] = s;
+        for (int b = t; b < nb; b += 1024) {
+            const double x = part[(size_t)b * nc + c];
+            s = op == 0 ? s + x : nanmax(s, x);
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const double y = __shfl_down(s, off, 64);
+            s = op == 0 ? s + y : nanmax(s, y);
+        }
+        if (lane == 0) sh[c][wave] = s;
     }
     __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        if (t < w)
-            for (int c = 0; c < nc; ++c) sh[c][t] = op == 0 ? sh[c][t] + sh[c][t + w] : nanmax(sh[c][t], sh[c][t + w]);
-        __syncthreads();
+    if (t < nc) {
+        double s = sh[t][0];
+        for (int w = 1; w < 16; ++w) s = op == 0 ? s + sh[t][w] : nanmax(s, sh[t][w]);
+        out[t] = s;
     }
-    if (t < nc) out[t] = sh[t][0];
 }
 
 __global__ void __launch_bounds__(1024) k_reduce(const double *part, int nb, int nc, int op, double *out)
@@ -149,6 +157,16 @@ struct ReduceJob {
 __global__ void __launch_bounds__(1024) k_reduce_jobs(const ReduceJob *__restrict__ jobs)
 {
     const ReduceJob jb = jobs[blockIdx.x];
+    reduce_block(jb.part, jb.nb, jb.nc, jb.op, jb.out);
+}
+
+// Up to four reductions passed by value (no table upload), one block each.
+struct ReduceJobs4 {
+    ReduceJob j[4];
+};
+__global__ void __launch_bounds__(1024) k_reduce4(ReduceJobs4 jobs)
+{
+    const ReduceJob &jb = jobs.j[blockIdx.x];
     reduce_block(jb.part, jb.nb, jb.nc, jb.op, jb.out);
 }
 
@@ -650,7 +668,8 @@ struct SweepArgs {
 };
 
 // One SOR update of the node at colour-row entry q of row (j, k); the squared
-// pre-update residuals go to r2.
+// pre-update residuals go to r2.  mask: bit 0 momentum, bit 1 energy, bits 2..4
+// momentum fields u, v, w to leave alone (a zero right-hand side: zero increment).
 template <typename TM, typename TA>
 __device__ __forceinline__ void sweep_node(const Geo &g, int colour, int mask, TA omega_m, TA omega_t, TA st,
                                            const SweepArgs<TM> &a, int q, int j, int k, double (&r2)[4])
@@ -661,6 +680,7 @@ __device__ __forceinline__ void sweep_node(const Geo &g, int colour, int mask, T
             const TA s = (TA)a.ms[r.me], ax = (TA)a.ma[0][r.me], ay = (TA)a.ma[1][r.me], az = (TA)a.ma[2][r.me];
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
+                if ((mask >> (2 + f)) & 1) continue;
                 TM *d = a.md[f];
                 const TA sum = mom_off<TA>(s, ax, ay, az, r, [&](size_t x) { return (TA)d[x]; });
                 const TA old = (TA)d[r.me];
@@ -737,6 +757,7 @@ struct FusedSweepCav {
     SweepArgs<TM> a;
     TA omega_m, omega_t, st;
     int plan_m, plan_t;             // sweeps of this batch per group (0: group idle)
+    int skip, pad;                  // momentum fields left alone (bits 0..2)
     double *part[2], *part0[2];     // partial records per colour: last sweep, first sweep
 };
 
@@ -751,8 +772,8 @@ __global__ void __launch_bounds__(256) k_sweep_fused(const TileMap *__restrict__
         const int c = find_cavity(map, ncav, t);
         const TileMap m = map[c];
         const FusedSweepCav<TM, TA> &cv = cav[c];
-        const int mask = (qs < cv.plan_m ? 1 : 0) | (qs < cv.plan_t ? 2 : 0);
-        if (!mask) continue;    // uniform over the workgroup
+        const int mask = (qs < cv.plan_m ? 1 | (cv.skip << 2) : 0) | (qs < cv.plan_t ? 2 : 0);
+        if (!(mask & 3)) continue;    // uniform over the workgroup
         const unsigned store = (qs == cv.plan_m - 1 ? 0x7u : 0u) | (qs == cv.plan_t - 1 ? 0x8u : 0u);
         const unsigned store0 = (qs == 0 && cv.plan_m > 1 ? 0x7u : 0u) | (qs == 0 && cv.plan_t > 1 ? 0x8u : 0u);
         const int lt = t - m.tile0;
