@@ -174,13 +174,16 @@ hosc_status hosc_set_state(hosc_solver *s, const double *u, const double *v, con
 /* Copy level n to host arrays (any pointer may be NULL). */
 hosc_status hosc_get_state(hosc_solver *s, double *u, double *v, double *w, double *theta, double *p);
 
-/* Advance nsteps time steps (Sec. 2.2).  info (may be NULL) reports the last step. */
+/* Advance nsteps time steps (Sec. 2.2).  Each step ends with the Nusselt, entropy
+ * and Bejan reductions of the new level (hosc_diagnostics then returns them
+ * without recomputing).  info (may be NULL) reports the last step. */
 hosc_status hosc_step(hosc_solver *s, int32_t nsteps, hosc_step_info *info);
 
 /* Step until max_f res[f] < res_tol or max_steps steps were taken. */
 hosc_status hosc_run_to_steady(hosc_solver *s, double res_tol, int64_t max_steps, hosc_step_info *info);
 
-/* Nusselt, entropy and Bejan diagnostics of level n.  Optional host outputs (may
+/* Nusselt, entropy and Bejan diagnostics of level n (those of the step that produced
+ * it, or computed now after a state was set).  Optional host outputs (may
  * be NULL): nuavg_hot[N], nuavg_cold[N] (Nu_avg(z_k)); nu_hot[N*N], nu_cold[N*N]
  * (Nu_local at node (j, k) stored at j + N*k). */
 hosc_status hosc_diagnostics(hosc_solver *s, hosc_diag *d, double *nuavg_hot, double *nuavg_cold, double *nu_hot,

@@ -208,6 +208,9 @@ struct hosc_solver {
     int last_bicg[2] = {0, 0};
     double om[2] = {1.0, 1.0};          // SOR relaxation of each group (adaptive when P.omega == 0)
     int64_t seeded_at = -1;             // step whose dominance bound was last applied to om
+    bool eta_ready = false;             // eta of level n already computed (by the previous step's diagnostics)
+    bool diag_valid = false;            // diag holds the diagnostics of level n
+    hosc_diag diag{};
     std::string err;
     // kernel timing
     bool prof = false;
@@ -423,6 +426,8 @@ hosc_status reset_state(hosc_solver *s)
     s->bicg_until[0] = s->bicg_until[1] = -1;
     s->om[0] = s->om[1] = s->P.omega > 0.0 ? s->P.omega : 1.0;
     s->seeded_at = -1;
+    s->eta_ready = false;
+    s->diag_valid = false;
     HIPCHK(s, hipStreamSynchronize(s->st));
     return HOSC_OK;
 }
@@ -430,7 +435,7 @@ hosc_status reset_state(hosc_solver *s)
 // eta and E* at level n; on the first step level n-1 := level n.
 hosc_status stage_sources(hosc_solver *s, bool consume_first)
 {
-    k_eta<<<s->L.grd_all, s->L.blk_all, 0, s->st>>>(s->g, s->ph, s->u, s->v, s->w, s->eta);
+    if (!s->eta_ready) k_eta<<<s->L.grd_all, s->L.blk_all, 0, s->st>>>(s->g, s->ph, s->u, s->v, s->w, s->eta);
     k_estar<<<s->L.grd_all, s->L.blk_all, 0, s->st>>>(s->g, s->ph, s->u, s->v, s->w, s->T, s->p, s->eta, s->E[0],
                                                        s->E[1], s->E[2]);
     hosc_status r = launch_check(s, "eta/estar");
@@ -1107,21 +1112,15 @@ hosc_status pre_solve(hosc_solver *s)
         ca.ta[d] = s->ta[d];
     }
     ca.tb = s->tb;
-    ca.fms = s->fms;
-    for (int d = 0; d < 3; ++d) {
-        ca.fma[d] = s->fma[d];
-        ca.fta[d] = s->fta[d];
-    }
     r = timed_begin(s);
     if (r) return r;
-    if (s->fp32)
-        k_assemble<true><<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(
-            s->g, s->ph, s->u, s->v, s->w, s->T, s->eta, s->E[0], s->E[1], s->E[2], s->u2, s->v2, s->w2, s->etap,
-            s->Ep[0], s->Ep[1], s->Ep[2], ca, s->partR, s->partB);
-    else
-        k_assemble<false><<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(
-            s->g, s->ph, s->u, s->v, s->w, s->T, s->eta, s->E[0], s->E[1], s->E[2], s->u2, s->v2, s->w2, s->etap,
-            s->Ep[0], s->Ep[1], s->Ep[2], ca, s->partR, s->partB);
+    k_assemble<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(
+        s->g, s->ph, s->u, s->v, s->w, s->T, s->eta, s->E[0], s->E[1], s->E[2], s->u2, s->v2, s->w2, s->etap,
+        s->Ep[0], s->Ep[1], s->Ep[2], ca, s->partR, s->partB);
+    if (s->fp32)    // a streaming pass: cheaper than the FP32 stores inside the assembly (register budget)
+        k_rows_f32<<<2048, 256, 0, s->st>>>(2 * s->g.cs, s->ms, s->ma[0], s->ma[1], s->ma[2], s->ta[0], s->ta[1],
+                                           s->ta[2], s->fms, s->fma[0], s->fma[1], s->fma[2], s->fta[0], s->fta[1],
+                                           s->fta[2]);
     r = timed_end(s, 1, assemble_bytes(s->g));
     if (r) return r;
     Reductions().add(s->partR, s->L.nb_int, 4, 0, s->red).add(s->partB, s->L.nb_int, 2, 1, s->red + 44).launch(s->st);
@@ -1139,17 +1138,48 @@ hosc_status post_launch(hosc_solver *s)
     const bool gate = s->P.div_tol > 0.0;
     k_divergence<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, s->ph, s->u2, s->v2, s->w2, s->p,
                                                            gate ? s->dbg : nullptr, gate ? 0 : 1, s->partR0);
+    if (!gate) k_p_walls<<<s->L.grd_face, s->L.blk_face, 0, s->st>>>(s->g, s->p);
+    // the step finishes with the Nusselt, entropy and Bejan reductions of level n+1
+    // (red[56..60] and red[24..26]); the entropy pass also leaves eta of level n+1 in
+    // the level n-1 buffer, which becomes level n at the swap
+    const Geo &g = s->g;
+    dim3 b2(16, 16), g2((g.N + 15) / 16, (g.N + 15) / 16);
+    k_nu_local<<<g2, b2, 0, s->st>>>(g, s->T, s->nuh, s->nuc);
+    k_nu_avg<<<g.N, 256, 0, s->st>>>(g, s->wq, s->nuh, s->nuc, s->avh, s->avc);
+    k_nu_final<<<1, 1024, 0, s->st>>>(g, s->wq, s->avh, s->avc, s->nuh, s->red + 56);
+    k_entropy<<<s->L.grd_all, s->L.blk_all, 0, s->st>>>(g, s->ph, s->wq, s->u2, s->v2, s->w2, s->T, nullptr, nullptr,
+                                                         s->etap, s->partB0);
     Reductions()
         .add(s->partR, s->L.nb_int, 8, 0, s->red + 12)
         .add(s->partB, s->L.nb_face, 2, 0, s->red + 20)
         .add(s->partR0, s->L.nb_int, 1, 1, s->red + 22)
+        .add(s->partB0, s->L.nb_all, 3, 0, s->red + 24)
         .launch(s->st);
-    if (!gate) k_p_walls<<<s->L.grd_face, s->L.blk_face, 0, s->st>>>(s->g, s->p);
-    return launch_check(s, "update/divergence");
+    return launch_check(s, "update/divergence/diagnostics");
 }
 
-// Finish the step from hb = red[12..22] read back: gated pressure correction,
-// pressure walls, level swap, steady residual and the step report.
+// Number of reduction outputs the step report reads back: red[12 .. 12 + kPost).
+constexpr int kPost = 49;
+
+// Diagnostics from the reduction block: Nusselt at red[56..60], entropy sums at
+// red[24..26] (hb points at red[base]).
+void diag_from(hosc_diag *d, const double *nu, const double *ent)
+{
+    d->nu_mean_hot = nu[0];
+    d->nu_mean_cold = nu[1];
+    d->nu_max_hot = nu[2];
+    d->nu_max_cold = nu[3];
+    d->nu_local_max_hot = nu[4];
+    d->e_ht = ent[0];
+    d->e_ff = ent[1];
+    d->e_total = ent[0] + ent[1];
+    d->be_global = d->e_total > 0.0 ? ent[0] / d->e_total : 1.0;
+    d->be_mean = ent[2];
+}
+
+// Finish the step from hb = red[12 .. 12 + kPost) read back: gated pressure
+// correction, pressure walls, level swap, steady residual, diagnostics and the
+// step report.
 hosc_status post_finish(hosc_solver *s, const double *hb, const SolveOut &so, hosc_step_info *info)
 {
     const bool gate = s->P.div_tol > 0.0;
@@ -1170,6 +1200,9 @@ hosc_status post_finish(hosc_solver *s, const double *hb, const SolveOut &so, ho
     std::swap(s->eta, s->etap);
     for (int d = 0; d < 3; ++d) std::swap(s->E[d], s->Ep[d]);
     s->step += 1;
+    s->eta_ready = true;
+    diag_from(&s->diag, hb + 44, hb + 12);
+    s->diag_valid = true;
     auto ratio = [](double num, double den) {
         if (den > 0.0) return std::sqrt(num) / std::sqrt(den);
         return num == 0.0 ? 0.0 : HUGE_VAL;
@@ -1212,7 +1245,7 @@ hosc_status one_step(hosc_solver *s, hosc_step_info *info)
     if (r) return r;
     r = post_launch(s);
     if (r) return r;
-    HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red + 12, 11 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red + 12, kPost * sizeof(double), hipMemcpyDeviceToHost, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
     return post_finish(s, s->hbuf, so, info);
 }
@@ -1646,11 +1679,12 @@ hosc_status fused_step(Fused &F, hosc_solver *const *cav, int n, hosc_step_info 
                 hosc_status q = post_launch(cav[i]);
                 if (q) return ffail(F, q, "cavity " + std::to_string(i) + ": " + cav[i]->err);
             }
-            k_gather<<<n, 64, 0, F.st>>>(F.dsrc2(), 11, F.d_gather);
+            k_gather<<<n, 64, 0, F.st>>>(F.dsrc2(), kPost, F.d_gather);
             return HOSC_OK;
         });
         if (r) return r;
-        FHIPCHK(F, hipMemcpyAsync(F.h_gather, F.d_gather, (size_t)n * 11 * sizeof(double), hipMemcpyDeviceToHost, F.st));
+        FHIPCHK(F, hipMemcpyAsync(F.h_gather, F.d_gather, (size_t)n * kPost * sizeof(double), hipMemcpyDeviceToHost,
+                                  F.st));
         FHIPCHK(F, hipStreamSynchronize(F.st));
     } else if (nact) {
         int ng = 0;
@@ -1666,13 +1700,13 @@ hosc_status fused_step(Fused &F, hosc_solver *const *cav, int n, hosc_step_info 
         if (nact) {
             FHIPCHK(F, hipMemcpyAsync(F.d_tab + F.off_src, F.h_tab + F.off_src, (size_t)nact * sizeof(double *),
                                       hipMemcpyHostToDevice, F.st));
-            r = fused_reduce_gather(F, 0, nact, 11);
+            r = fused_reduce_gather(F, 0, nact, kPost);
             if (r) return r;
         }
     }
     for (int a = 0; a < nact; ++a) {
         const int i = act[a];
-        err[i] = post_finish(cav[i], F.h_gather + 11 * a, o[i], info ? &info[i] : nullptr);
+        err[i] = post_finish(cav[i], F.h_gather + kPost * a, o[i], info ? &info[i] : nullptr);
     }
     for (int i = 0; i < n; ++i)
         if (err[i]) {
@@ -2062,34 +2096,35 @@ hosc_status hosc_diagnostics(hosc_solver *s, hosc_diag *d, double *nuavg_hot, do
     if (!s || !d) return HOSC_E_ARG;
     if (!s->has_state) return fail(s, HOSC_E_STATE, "no state set");
     const Geo &g = s->g;
+    const size_t nb = (size_t)g.N * sizeof(double), n2 = (size_t)g.N * g.N * sizeof(double);
+    if (s->diag_valid) {    // computed at the end of the step that produced this state
+        *d = s->diag;
+        if (nuavg_hot) HIPCHK(s, hipMemcpyAsync(nuavg_hot, s->avh, nb, hipMemcpyDeviceToHost, s->st));
+        if (nuavg_cold) HIPCHK(s, hipMemcpyAsync(nuavg_cold, s->avc, nb, hipMemcpyDeviceToHost, s->st));
+        if (nu_hot) HIPCHK(s, hipMemcpyAsync(nu_hot, s->nuh, n2, hipMemcpyDeviceToHost, s->st));
+        if (nu_cold) HIPCHK(s, hipMemcpyAsync(nu_cold, s->nuc, n2, hipMemcpyDeviceToHost, s->st));
+        if (nuavg_hot || nuavg_cold || nu_hot || nu_cold) HIPCHK(s, hipStreamSynchronize(s->st));
+        return HOSC_OK;
+    }
     dim3 b2(16, 16), g2((g.N + 15) / 16, (g.N + 15) / 16);
     k_nu_local<<<g2, b2, 0, s->st>>>(g, s->T, s->nuh, s->nuc);
     k_nu_avg<<<g.N, 256, 0, s->st>>>(g, s->wq, s->nuh, s->nuc, s->avh, s->avc);
-    k_nu_final<<<1, 256, 0, s->st>>>(g, s->wq, s->avh, s->avc, s->nuh, s->nuout);
+    k_nu_final<<<1, 1024, 0, s->st>>>(g, s->wq, s->avh, s->avc, s->nuh, s->nuout);
     k_entropy<<<s->L.grd_all, s->L.blk_all, 0, s->st>>>(g, s->ph, s->wq, s->u, s->v, s->w, s->T, nullptr, nullptr,
-                                                         s->partR);
+                                                         nullptr, s->partR);
     k_reduce<<<1, 1024, 0, s->st>>>(s->partR, (int)s->L.nb_all, 3, 0, s->red + 24);
     hosc_status r = launch_check(s, "diagnostics");
     if (r) return r;
     HIPCHK(s, hipMemcpyAsync(s->hbuf, s->nuout, 5 * sizeof(double), hipMemcpyDeviceToHost, s->st));
     HIPCHK(s, hipMemcpyAsync(s->hbuf + 8, s->red + 24, 3 * sizeof(double), hipMemcpyDeviceToHost, s->st));
-    const size_t nb = (size_t)g.N * sizeof(double), n2 = (size_t)g.N * g.N * sizeof(double);
     if (nuavg_hot) HIPCHK(s, hipMemcpyAsync(nuavg_hot, s->avh, nb, hipMemcpyDeviceToHost, s->st));
     if (nuavg_cold) HIPCHK(s, hipMemcpyAsync(nuavg_cold, s->avc, nb, hipMemcpyDeviceToHost, s->st));
     if (nu_hot) HIPCHK(s, hipMemcpyAsync(nu_hot, s->nuh, n2, hipMemcpyDeviceToHost, s->st));
     if (nu_cold) HIPCHK(s, hipMemcpyAsync(nu_cold, s->nuc, n2, hipMemcpyDeviceToHost, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
-    const double *hb = s->hbuf;
-    d->nu_mean_hot = hb[0];
-    d->nu_mean_cold = hb[1];
-    d->nu_max_hot = hb[2];
-    d->nu_max_cold = hb[3];
-    d->nu_local_max_hot = hb[4];
-    d->e_ht = hb[8];
-    d->e_ff = hb[9];
-    d->e_total = hb[8] + hb[9];
-    d->be_global = d->e_total > 0.0 ? hb[8] / d->e_total : 1.0;
-    d->be_mean = hb[10];
+    diag_from(d, s->hbuf, s->hbuf + 8);
+    s->diag = *d;
+    s->diag_valid = true;
     return HOSC_OK;
 }
 
@@ -2099,14 +2134,14 @@ hosc_status hosc_entropy_fields(hosc_solver *s, double *e_local, double *be_loca
     if (!s->has_state) return fail(s, HOSC_E_STATE, "no state set");
     // each field goes through the scratch array and is copied out before the next
     k_entropy<<<s->L.grd_all, s->L.blk_all, 0, s->st>>>(s->g, s->ph, s->wq, s->u, s->v, s->w, s->T, s->dbg,
-                                                         nullptr, s->partR);
+                                                         nullptr, nullptr, s->partR);
     hosc_status r = launch_check(s, "entropy");
     if (r) return r;
     const size_t b = s->g.n3 * sizeof(double);
     if (e_local) HIPCHK(s, hipMemcpyAsync(e_local, s->dbg, b, hipMemcpyDeviceToHost, s->st));
     if (be_local) {
         k_entropy<<<s->L.grd_all, s->L.blk_all, 0, s->st>>>(s->g, s->ph, s->wq, s->u, s->v, s->w, s->T, nullptr,
-                                                             s->dbg, s->partR);
+                                                             s->dbg, nullptr, s->partR);
         r = launch_check(s, "entropy");
         if (r) return r;
         HIPCHK(s, hipMemcpyAsync(be_local, s->dbg, b, hipMemcpyDeviceToHost, s->st));

@@ -180,14 +180,17 @@ __global__ void __launch_bounds__(64) k_gather(const double *const *__restrict__
 
 // ---------------------------------------------------------------------------
 // XCD-aware tile order.  Workgroups reach the eight XCDs round-robin by linear id;
-// slot(b) = (b mod 8)(G/8) + b/8 (when 8 divides G) hands each XCD a contiguous
-// run of tiles, so the rows and planes that neighbouring tiles share are read
-// into the same L2.  Tile ids (and the partial-sum records indexed by them) are
+// slot(b) hands each XCD a contiguous run of tiles (a balanced split of the G
+// tiles into eight runs), so the rows and planes that neighbouring tiles share
+// are read into the same L2.  Tile ids (and the partial-sum records indexed by them) are
 // the plain linear order, so reductions see the same records in the same order.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int persistent_slot(int b, int G)
 {
-    return (G & 7) ? b : (b & 7) * (G >> 3) + (b >> 3);
+    // G = 8q + r: XCD x (x = b mod 8) receives q + (x < r) workgroups and the
+    // contiguous slots starting at x q + min(x, r)
+    const int q = G >> 3, r = G & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
 }
 
 struct Tile {
@@ -490,15 +493,13 @@ struct ColourArrays {
     double *mb[3];                  // momentum right-hand sides b/C (u, v, w)
     double *ta[3];                  // energy rows: a_d/C
     double *tb;                     // energy right-hand side b/C
-    float *fms, *fma[3], *fta[3];   // FP32 copies of the rows for the precision mode (null otherwise)
 };
 
-// Assemble every interior node and write the scaled rows in the colour layout
-// (FP64, plus FP32 copies of the rows when F32: the precision mode); per-block
-// partial sums of ||b/C||^2 for the four systems and the largest
-// off-diagonal/centre ratio.  (The FP32 stores are a separate instantiation: they
-// push the FP64 kernel past the register budget of two waves per SIMD.)
-template <bool F32>
+// Assemble every interior node and write the scaled rows in the colour layout;
+// per-block partial sums of ||b/C||^2 for the four systems and the largest
+// off-diagonal/centre ratio.  (The precision mode's FP32 copies come from a
+// separate streaming pass: stores here would push the kernel past the register
+// budget of two waves per SIMD.)
 __global__ void __launch_bounds__(256) k_assemble(Geo g, Phys P, const double *__restrict__ u,
                                                   const double *__restrict__ v, const double *__restrict__ w,
                                                   const double *__restrict__ T, const double *__restrict__ eta,
@@ -519,18 +520,11 @@ __global__ void __launch_bounds__(256) k_assemble(Geo g, Phys P, const double *_
         assemble_node(g, P, i, j, k, u, v, w, T, eta, Eu, Ev, Ew, up, vp, wp, etap, Eup, Evp, Ewp, a);
         const size_t idx = (size_t)((i + j + k) & 1) * g.cs + rowid(g, j, k) + (i >> 1);
         const double rm = 1.0 / a.Cm, rt = 1.0 / a.Ct;
-        const double sm = a.sm * rm;
-        ca.ms[idx] = sm;
-        if (F32) ca.fms[idx] = (float)sm;
+        ca.ms[idx] = a.sm * rm;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            const double am = a.am[d] * rm, at = a.at[d] * rt;
-            ca.ma[d][idx] = am;
-            ca.ta[d][idx] = at;
-            if (F32) {
-                ca.fma[d][idx] = (float)am;
-                ca.fta[d][idx] = (float)at;
-            }
+            ca.ma[d][idx] = a.am[d] * rm;
+            ca.ta[d][idx] = a.at[d] * rt;
             const double bb = a.b[d] * rm;
             ca.mb[d][idx] = bb;
             acc[d] = bb * bb;
@@ -554,6 +548,29 @@ __global__ void __launch_bounds__(256) k_assemble(Geo g, Phys P, const double *_
 
 // Parity hook: one selected assembled quantity, unscaled, in the natural layout:
 // what 0..6 momentum weight (centre, x+, x-, y+, y-, z+, z-), 7..13 energy weight,
+
+// FP32 copies of the scaled rows (precision mode): the seven row arrays of both
+// colours, converted with round-to-nearest.
+__global__ void __launch_bounds__(256) k_rows_f32(size_t n, const double *__restrict__ ms,
+                                                  const double *__restrict__ mx, const double *__restrict__ my,
+                                                  const double *__restrict__ mz, const double *__restrict__ tx,
+                                                  const double *__restrict__ ty, const double *__restrict__ tz,
+                                                  float *__restrict__ fms, float *__restrict__ fmx,
+                                                  float *__restrict__ fmy, float *__restrict__ fmz,
+                                                  float *__restrict__ ftx, float *__restrict__ fty,
+                                                  float *__restrict__ ftz)
+{
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
+        fms[q] = (float)ms[q];
+        fmx[q] = (float)mx[q];
+        fmy[q] = (float)my[q];
+        fmz[q] = (float)mz[q];
+        ftx[q] = (float)tx[q];
+        fty[q] = (float)ty[q];
+        ftz[q] = (float)tz[q];
+    }
+}
+
 // 14..17 b of u, v, w, theta.
 __global__ void __launch_bounds__(256) k_assemble_debug(Geo g, Phys P, const double *u, const double *v,
                                                         const double *w, const double *T, const double *eta,
@@ -1240,41 +1257,47 @@ __global__ void __launch_bounds__(256) k_nu_avg(Geo g, const double *__restrict_
 
 // Means over z (Simpson), maxima over z of Nu_avg, and the max of the local
 // hot-wall Nu: one block of 256 threads, fixed-order trees.
-__global__ void __launch_bounds__(256) k_nu_final(Geo g, const double *__restrict__ wq, const double *__restrict__ avh,
-                                                  const double *__restrict__ avc, const double *__restrict__ nuh,
-                                                  double *__restrict__ out)
+__global__ void __launch_bounds__(1024) k_nu_final(Geo g, const double *__restrict__ wq, const double *__restrict__ avh,
+                                                   const double *__restrict__ avc, const double *__restrict__ nuh,
+                                                   double *__restrict__ out)
 {
-    __shared__ double sh[5][256];
-    const int t = threadIdx.x;
-    double mh = 0.0, mc = 0.0, xh = -HUGE_VAL, xc = -HUGE_VAL, xl = -HUGE_VAL;
-    for (int k = t; k < g.N; k += 256) {
-        mh += wq[k] * avh[k];
-        mc += wq[k] * avc[k];
-        xh = nanmax(xh, avh[k]);
-        xc = nanmax(xc, avc[k]);
+    __shared__ double sh[5][16];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    double v[5] = {0.0, 0.0, -HUGE_VAL, -HUGE_VAL, -HUGE_VAL};
+    for (int k = t; k < g.N; k += 1024) {
+        v[0] += wq[k] * avh[k];
+        v[1] += wq[k] * avc[k];
+        v[2] = nanmax(v[2], avh[k]);
+        v[3] = nanmax(v[3], avc[k]);
     }
-    for (size_t q = t; q < (size_t)g.N * g.N; q += 256) xl = nanmax(xl, nuh[q]);
-    sh[0][t] = mh; sh[1][t] = mc; sh[2][t] = xh; sh[3][t] = xc; sh[4][t] = xl;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (t < w) {
-            sh[0][t] += sh[0][t + w];
-            sh[1][t] += sh[1][t + w];
-            for (int c = 2; c < 5; ++c) sh[c][t] = nanmax(sh[c][t], sh[c][t + w]);
+    for (size_t q = t; q < (size_t)g.N * g.N; q += 1024) v[4] = nanmax(v[4], nuh[q]);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        double x = v[c];
+        for (int off = 32; off > 0; off >>= 1) {
+            const double y = __shfl_down(x, off, 64);
+            x = c < 2 ? x + y : nanmax(x, y);
         }
-        __syncthreads();
+        if (lane == 0) sh[c][wave] = x;
     }
-    if (t < 5) out[t] = sh[t][0];
+    __syncthreads();
+    if (t < 5) {
+        double x = sh[t][0];
+        for (int w = 1; w < 16; ++w) x = t < 2 ? x + sh[t][w] : nanmax(x, sh[t][w]);
+        out[t] = x;
+    }
 }
 
 // Entropy generation (Sec. 4.3): E_HT = |grad theta|^2, E_FF = phi eta I2 with eta
 // from the current velocity, E_local = E_HT + E_FF, Be_local = E_HT / E_local (1
 // where E_local = 0).  Partial Simpson-weighted sums of E_HT, E_FF and Be_local.
+// eta_out (optional) receives eta, computed exactly as k_eta computes it: run at
+// the end of a step on the new velocities, it supplies the next step's viscosity.
 __global__ void __launch_bounds__(256) k_entropy(Geo g, Phys P, const double *__restrict__ wq,
                                                  const double *__restrict__ u, const double *__restrict__ v,
                                                  const double *__restrict__ w, const double *__restrict__ T,
                                                  double *__restrict__ el, double *__restrict__ bl,
-                                                 double *__restrict__ partial)
+                                                 double *__restrict__ eta_out, double *__restrict__ partial)
 {
     const Tile tl = xcd_tile();
     const int i = tl.x * blockDim.x + threadIdx.x, j = tl.y * blockDim.y + threadIdx.y, k = tl.z;
@@ -1286,7 +1309,8 @@ __global__ void __launch_bounds__(256) k_entropy(Geo g, Phys P, const double *__
         const double eht = tx * tx + ty * ty + tz * tz;
         const VelGrad d = vel_grad(g, u, v, w, i, j, k);
         const double I2 = strain_I2(d);
-        const double eta = pow(fmax(I2, P.i2_floor), P.ex);
+        const double eta = pow(fmax(I2, P.i2_floor), P.ex);    // as k_eta computes it
+        if (eta_out) eta_out[c] = eta;
         const double eff = P.phi * eta * I2;
         const double e = eht + eff;
         const double be = e > 0.0 ? eht / e : 1.0;
