@@ -330,8 +330,8 @@ def main():
     ap.add_argument("--requests", type=int, default=None)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build measures the single-cavity hot path on one MI355X "
-              "(multi-GPU sharding is a design note, not a measured mode)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the HOSC hot path is measured on one MI355X "
+              "(sharding across GPUs is a design note, not a measured mode)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -238,6 +238,18 @@ hosc_status fail(hosc_solver *s, hosc_status st, const std::string &msg)
             return fail((s), HOSC_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));    \
     } while (0)
 
+// Wait for a stream by polling.  The convergence checks sit on the critical path
+// between batches of kernels; a polling wait resumes the host within microseconds
+// of the last kernel, a blocking one can take tens.  Every kernel terminates, so
+// the loop ends.
+hipError_t wait_stream(hipStream_t st)
+{
+    for (;;) {
+        const hipError_t e = hipStreamQuery(st);
+        if (e != hipErrorNotReady) return e;
+    }
+}
+
 hosc_status launch_check(hosc_solver *s, const char *what)
 {
     hipError_t e = hipGetLastError();
@@ -755,7 +767,7 @@ hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *f
     *failed = 0;
     if (sor_wants_seed(s, c)) {
         HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red, 48 * sizeof(double), hipMemcpyDeviceToHost, s->st));
-        HIPCHK(s, hipStreamSynchronize(s->st));
+        HIPCHK(s, wait_stream(s->st));
         sor_seed(s, c, s->hbuf + 44);
         if (bn2[0] < 0.0) {
             for (int f = 0; f < 4; ++f) bn2[f] = s->hbuf[f];
@@ -790,7 +802,7 @@ hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *f
             .add(s->partB0, s->L.nb_sw, 4, 0, s->red + 36)
             .launch(s->st);
         HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red, 48 * sizeof(double), hipMemcpyDeviceToHost, s->st));
-        HIPCHK(s, hipStreamSynchronize(s->st));
+        HIPCHK(s, wait_stream(s->st));
         r = harvest_events(s);
         if (r) return r;
         r = sor_decide<TM>(s, c, s->hbuf, bn2, o, a);
@@ -839,7 +851,7 @@ hosc_status run_bicg(hosc_solver *s, int mask, double bn2[4], SolveOut &o, BicgA
     if (!mask) return HOSC_OK;
     if (bn2[0] < 0.0) {
         HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red, 4 * sizeof(double), hipMemcpyDeviceToHost, s->st));
-        HIPCHK(s, hipStreamSynchronize(s->st));
+        HIPCHK(s, wait_stream(s->st));
         for (int f = 0; f < 4; ++f) bn2[f] = s->hbuf[f];
         for (int f = 0; f < 4; ++f)
             if (!std::isfinite(bn2[f])) return fail(s, HOSC_E_NONFINITE, "non-finite right-hand side");
@@ -879,7 +891,7 @@ hosc_status run_bicg(hosc_solver *s, int mask, double bn2[4], SolveOut &o, BicgA
         for (int grp = 0; grp < 2; ++grp)
             if (active & (1 << grp)) o.bicg[grp] += m;
         HIPCHK(s, hipMemcpyAsync(s->hbuf, s->bsc, 32 * sizeof(double), hipMemcpyDeviceToHost, s->st));
-        HIPCHK(s, hipStreamSynchronize(s->st));
+        HIPCHK(s, wait_stream(s->st));
         r = harvest_events(s);
         if (r) return r;
         // candidates: recursive residual small enough, or breakdown -> recompute the true
@@ -901,7 +913,7 @@ hosc_status run_bicg(hosc_solver *s, int mask, double bn2[4], SolveOut &o, BicgA
             r = bicg_phase(s, 0, recheck, st, a);
             if (r) return r;
             HIPCHK(s, hipMemcpyAsync(s->hbuf, s->bsc, 32 * sizeof(double), hipMemcpyDeviceToHost, s->st));
-            HIPCHK(s, hipStreamSynchronize(s->st));
+            HIPCHK(s, wait_stream(s->st));
             for (int grp = 0; grp < 2; ++grp) {
                 if (!(recheck & (1 << grp))) continue;
                 const int f0 = grp == 0 ? 0 : 3, f1 = grp == 0 ? 3 : 4;
@@ -1036,7 +1048,7 @@ hosc_status solve_refined(hosc_solver *s, int mask, double bn2[4], SolveOut &o, 
         if (r) return r;
         Reductions().add(s->partR, s->L.nb_sw, 4, 0, s->red + 48).add(s->partB, s->L.nb_sw, 4, 0, s->red + 52).launch(s->st);
         HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red, 56 * sizeof(double), hipMemcpyDeviceToHost, s->st));
-        HIPCHK(s, hipStreamSynchronize(s->st));
+        HIPCHK(s, wait_stream(s->st));
         r = harvest_events(s);
         if (r) return r;
         double inner_bn2[4], inner_rtol;
@@ -1246,7 +1258,7 @@ hosc_status one_step(hosc_solver *s, hosc_step_info *info)
     r = post_launch(s);
     if (r) return r;
     HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red + 12, kPost * sizeof(double), hipMemcpyDeviceToHost, s->st));
-    HIPCHK(s, hipStreamSynchronize(s->st));
+    HIPCHK(s, wait_stream(s->st));
     return post_finish(s, s->hbuf, so, info);
 }
 
@@ -1369,7 +1381,7 @@ hosc_status fused_reduce_gather(Fused &F, int njobs, int nsrc, int len)
     k_gather<<<nsrc, 64, 0, F.st>>>(F.dsrc(), len, F.d_gather);
     FHIPCHK(F, hipGetLastError());
     FHIPCHK(F, hipMemcpyAsync(F.h_gather, F.d_gather, (size_t)nsrc * len * sizeof(double), hipMemcpyDeviceToHost, F.st));
-    FHIPCHK(F, hipStreamSynchronize(F.st));
+    FHIPCHK(F, wait_stream(F.st));
     return HOSC_OK;
 }
 
@@ -1685,7 +1697,7 @@ hosc_status fused_step(Fused &F, hosc_solver *const *cav, int n, hosc_step_info 
         if (r) return r;
         FHIPCHK(F, hipMemcpyAsync(F.h_gather, F.d_gather, (size_t)n * kPost * sizeof(double), hipMemcpyDeviceToHost,
                                   F.st));
-        FHIPCHK(F, hipStreamSynchronize(F.st));
+        FHIPCHK(F, wait_stream(F.st));
     } else if (nact) {
         int ng = 0;
         for (int a = 0; a < nact; ++a) {
