@@ -64,6 +64,10 @@ Geo make_geo(int N)
     g.h2 = g.h * g.h;
     g.inv2h = 1.0 / (2.0 * g.h);
     g.invh2 = 1.0 / g.h2;
+    g.h2_12 = g.h2 / 12.0;
+    g.inv3h = 1.0 / (3.0 * g.h);
+    g.inv12h = 1.0 / (12.0 * g.h);
+    g.inv6h2 = 1.0 / (6.0 * g.h2);
     g.n3 = (size_t)N * N * N;
     g.cs = (size_t)N * N * g.H;
     return g;

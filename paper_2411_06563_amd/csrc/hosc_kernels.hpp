@@ -28,6 +28,7 @@ struct Geo {
     int Q;          // colour-row entries that can hold interior nodes
     int pad;
     double h, h2, inv2h, invh2;
+    double h2_12, inv3h, inv12h, inv6h2;   // h^2/12, 1/(3h), 1/(12h), 1/(6h^2) (uniform grid: h = k = l)
     size_t n3;      // N^3
     size_t cs;      // entries of one colour array (N*N*H)
 };
@@ -314,9 +315,14 @@ struct Coef19 {
 __device__ __forceinline__ void explicit_weights(const Geo &g, double dt, const double (&G)[7], const double (&Hc)[7],
                                                  const double (&I)[7], double Gp, double Hp, double Ip, Coef19 &cw)
 {
-    const double h = g.h, k = g.h, l = g.h;
-    const double hh = h * h, kk = k * k, ll = l * l;
-    const double i2h = g.inv2h, ih2 = g.invh2;
+    // On the uniform grid (h = k = l) the grid factors of the expanded weights
+    // reduce to constants: M5 = M6 = M7 = h^2/6, M5/(h^2 k^2) = 1/(6h^2),
+    // M5/(h k^2) = 1/(6h) (twice per weight: 1/(3h)), M5/(4hk) = 1/24,
+    // M5/(2 h k^2) = 1/(12h), and 2/(h^2 + k^2) (k^2 a + h^2 b) = a + b; the
+    // (dt/2) delta_t^- terms are (f^n - f^(n-1))/2.  Products with precomputed
+    // reciprocals replace the divisions of the printed form.
+    (void)dt;
+    const double i2h = g.inv2h, ih2 = g.invh2, h12 = g.h2_12;
     const double G0 = G[0], H0 = Hc[0], I0 = I[0];
     // first and second central differences of the convective coefficients
     const double Gx = (G[1] - G[2]) * i2h, Gy = (G[3] - G[4]) * i2h, Gz = (G[5] - G[6]) * i2h;
@@ -329,46 +335,42 @@ __device__ __forceinline__ void explicit_weights(const Geo &g, double dt, const 
     const double Ixx = (I[1] - 2.0 * I0 + I[2]) * ih2, Iyy = (I[3] - 2.0 * I0 + I[4]) * ih2,
                  Izz = (I[5] - 2.0 * I0 + I[6]) * ih2;
     // alpha, beta, gamma (K* = 0)
-    const double alpha = (G0 * G0 - 2.0 * Gx) * hh / 12.0 + 1.0;
-    const double beta = (H0 * H0 - 2.0 * Hy) * kk / 12.0 + 1.0;
-    const double gamma = (I0 * I0 - 2.0 * Iz) * ll / 12.0 + 1.0;
+    const double alpha = (G0 * G0 - 2.0 * Gx) * h12 + 1.0;
+    const double beta = (H0 * H0 - 2.0 * Hy) * h12 + 1.0;
+    const double gamma = (I0 * I0 - 2.0 * Iz) * h12 + 1.0;
     // M1, M2, M3: the bracket [1 + (dxx - G dx) h^2/12 + (dyy - H dy) k^2/12 +
     // (dzz - I dz) l^2/12 + (dt/2) delta_t^-] applied to G*, H*, I*
-    const double M1 = G0 + (Gxx - G0 * Gx) * hh / 12.0 + (Gyy - H0 * Gy) * kk / 12.0 + (Gzz - I0 * Gz) * ll / 12.0
-                      + 0.5 * dt * ((G0 - Gp) / dt);
-    const double M2 = H0 + (Hxx - G0 * Hx) * hh / 12.0 + (Hyy - H0 * Hy) * kk / 12.0 + (Hzz - I0 * Hz) * ll / 12.0
-                      + 0.5 * dt * ((H0 - Hp) / dt);
-    const double M3 = I0 + (Ixx - G0 * Ix) * hh / 12.0 + (Iyy - H0 * Iy) * kk / 12.0 + (Izz - I0 * Iz) * ll / 12.0
-                      + 0.5 * dt * ((I0 - Ip) / dt);
-    const double p1 = -G0 * H0 + 2.0 / (hh + kk) * (kk * Gy + hh * Hx);
-    const double q1 = -H0 * I0 + 2.0 / (kk + ll) * (ll * Hz + kk * Iy);
-    const double r1 = -I0 * G0 + 2.0 / (ll + hh) * (hh * Ix + ll * Gz);
-    const double M5 = (hh + kk) / 12.0, M6 = (kk + ll) / 12.0, M7 = (ll + hh) / 12.0;
-    const double c5 = M5 / (hh * kk), c6 = M6 / (kk * ll), c7 = M7 / (ll * hh);
+    const double M1 = G0 + ((Gxx - G0 * Gx) + (Gyy - H0 * Gy) + (Gzz - I0 * Gz)) * h12 + 0.5 * (G0 - Gp);
+    const double M2 = H0 + ((Hxx - G0 * Hx) + (Hyy - H0 * Hy) + (Hzz - I0 * Hz)) * h12 + 0.5 * (H0 - Hp);
+    const double M3 = I0 + ((Ixx - G0 * Ix) + (Iyy - H0 * Iy) + (Izz - I0 * Iz)) * h12 + 0.5 * (I0 - Ip);
+    const double p1 = -G0 * H0 + (Gy + Hx);
+    const double q1 = -H0 * I0 + (Hz + Iy);
+    const double r1 = -I0 * G0 + (Ix + Gz);
+    const double c = g.inv6h2, c4 = 4.0 * c, i3h = g.inv3h, i12h = g.inv12h;
     // Q2 - L7 and Q1 - L1 ... Q7 - L6, divided by dt
-    cw.W[0] = -2.0 * (alpha / hh + beta / kk + gamma / ll) + 4.0 * (c5 + c6 + c7);
-    cw.W[1] = alpha / hh - M1 / (2.0 * h) - 2.0 * c5 + M5 * G0 / (h * kk) - 2.0 * c7 + M7 * G0 / (h * ll);
-    cw.W[2] = alpha / hh + M1 / (2.0 * h) - 2.0 * c5 - M5 * G0 / (h * kk) - 2.0 * c7 - M7 * G0 / (h * ll);
-    cw.W[3] = beta / kk - M2 / (2.0 * k) - 2.0 * c5 + M5 * H0 / (hh * k) - 2.0 * c6 + M6 * H0 / (k * ll);
-    cw.W[4] = beta / kk + M2 / (2.0 * k) - 2.0 * c5 - M5 * H0 / (hh * k) - 2.0 * c6 - M6 * H0 / (k * ll);
-    cw.W[5] = gamma / ll - M3 / (2.0 * l) - 2.0 * c6 + M6 * I0 / (kk * l) - 2.0 * c7 + M7 * I0 / (l * hh);
-    cw.W[6] = gamma / ll + M3 / (2.0 * l) - 2.0 * c6 - M6 * I0 / (kk * l) - 2.0 * c7 - M7 * I0 / (l * hh);
+    cw.W[0] = -2.0 * (alpha + beta + gamma) * ih2 + 12.0 * c;
+    cw.W[1] = alpha * ih2 - M1 * i2h - c4 + G0 * i3h;
+    cw.W[2] = alpha * ih2 + M1 * i2h - c4 - G0 * i3h;
+    cw.W[3] = beta * ih2 - M2 * i2h - c4 + H0 * i3h;
+    cw.W[4] = beta * ih2 + M2 * i2h - c4 - H0 * i3h;
+    cw.W[5] = gamma * ih2 - M3 * i2h - c4 + I0 * i3h;
+    cw.W[6] = gamma * ih2 + M3 * i2h - c4 - I0 * i3h;
     // Q8..Q19 / dt
-    const double a5 = M5 * p1 / (4.0 * h * k), g5 = M5 * G0 / (2.0 * h * kk), h5 = M5 * H0 / (2.0 * hh * k);
-    cw.W[7] = c5 - a5 - h5 - g5;     // (i+1, j+1)
-    cw.W[8] = c5 + a5 - h5 + g5;     // (i-1, j+1)
-    cw.W[9] = c5 + a5 + h5 - g5;     // (i+1, j-1)
-    cw.W[10] = c5 - a5 + h5 + g5;    // (i-1, j-1)
-    const double a6 = M6 * q1 / (4.0 * k * l), i6 = M6 * I0 / (2.0 * kk * l), h6 = M6 * H0 / (2.0 * k * ll);
-    cw.W[11] = c6 - a6 - i6 - h6;    // (j+1, k+1)
-    cw.W[12] = c6 + a6 - i6 + h6;    // (j-1, k+1)
-    cw.W[13] = c6 + a6 + i6 - h6;    // (j+1, k-1)
-    cw.W[14] = c6 - a6 + i6 + h6;    // (j-1, k-1)
-    const double a7 = M7 * r1 / (4.0 * l * h), g7 = M7 * G0 / (2.0 * ll * h), i7 = M7 * I0 / (2.0 * l * hh);
-    cw.W[15] = c7 - a7 - g7 - i7;    // (i+1, k+1)
-    cw.W[16] = c7 + a7 - g7 + i7;    // (i+1, k-1)
-    cw.W[17] = c7 + a7 + g7 - i7;    // (i-1, k+1)
-    cw.W[18] = c7 - a7 + g7 + i7;    // (i-1, k-1)
+    const double a5 = p1 * (1.0 / 24.0), g5 = G0 * i12h, h5 = H0 * i12h;
+    cw.W[7] = c - a5 - h5 - g5;     // (i+1, j+1)
+    cw.W[8] = c + a5 - h5 + g5;     // (i-1, j+1)
+    cw.W[9] = c + a5 + h5 - g5;     // (i+1, j-1)
+    cw.W[10] = c - a5 + h5 + g5;    // (i-1, j-1)
+    const double a6 = q1 * (1.0 / 24.0), i6 = I0 * i12h, h6 = H0 * i12h;
+    cw.W[11] = c - a6 - i6 - h6;    // (j+1, k+1)
+    cw.W[12] = c + a6 - i6 + h6;    // (j-1, k+1)
+    cw.W[13] = c + a6 + i6 - h6;    // (j+1, k-1)
+    cw.W[14] = c - a6 + i6 + h6;    // (j-1, k-1)
+    const double a7 = r1 * (1.0 / 24.0), g7 = G0 * i12h, i7 = I0 * i12h;
+    cw.W[15] = c - a7 - g7 - i7;    // (i+1, k+1)
+    cw.W[16] = c + a7 - g7 + i7;    // (i+1, k-1)
+    cw.W[17] = c + a7 + g7 - i7;    // (i-1, k+1)
+    cw.W[18] = c - a7 + g7 + i7;    // (i-1, k-1)
 }
 
 __device__ __forceinline__ void offsets19(const Geo &g, size_t c, size_t (&o)[19])
@@ -385,12 +387,11 @@ __device__ __forceinline__ void offsets19(const Geo &g, size_t c, size_t (&o)[19
 __device__ __forceinline__ double source_R(const Geo &g, double dt, const double (&E)[7], double Ep, double G0,
                                            double H0, double I0)
 {
-    const double hh = g.h2;
+    (void)dt;   // (dt/2) delta_t^- E = (E^n - E^(n-1))/2
     const double Ex = (E[1] - E[2]) * g.inv2h, Ey = (E[3] - E[4]) * g.inv2h, Ez = (E[5] - E[6]) * g.inv2h;
     const double Exx = (E[1] - 2.0 * E[0] + E[2]) * g.invh2, Eyy = (E[3] - 2.0 * E[0] + E[4]) * g.invh2,
                  Ezz = (E[5] - 2.0 * E[0] + E[6]) * g.invh2;
-    return E[0] + (Exx - G0 * Ex) * hh / 12.0 + (Eyy - H0 * Ey) * hh / 12.0 + (Ezz - I0 * Ez) * hh / 12.0
-           + 0.5 * dt * ((E[0] - Ep) / dt);
+    return E[0] + ((Exx - G0 * Ex) + (Eyy - H0 * Ey) + (Ezz - I0 * Ez)) * g.h2_12 + 0.5 * (E[0] - Ep);
 }
 
 struct NodeAssembly {
@@ -409,7 +410,7 @@ __device__ __forceinline__ void assemble_node(const Geo &g, const Phys &P, int i
     const size_t c = nid(g, i, j, k);
     size_t o[19];
     offsets19(g, c, o);
-    const double dt = P.dt, hh = g.h2;
+    const double dt = P.dt;
     // ---- momentum coefficients: L = 1/(Pr eta), (G*, H*, I*) = (u, v, w) L
     double Lm[7], G[7], Hm[7], I[7];
 #pragma unroll
@@ -427,17 +428,16 @@ __device__ __forceinline__ void assemble_node(const Geo &g, const Phys &P, int i
         const double Lxx = (Lm[1] - 2.0 * L0 + Lm[2]) * g.invh2, Lyy = (Lm[3] - 2.0 * L0 + Lm[4]) * g.invh2,
                      Lzz = (Lm[5] - 2.0 * L0 + Lm[6]) * g.invh2;
         // M18 = [(dt/2) delta_t^- + sum (d_dd - V_d d_d) h_d^2/12] L
-        const double M18 = dt / 2.0 * ((L0 - Lp) / dt) + (Lxx - G[0] * Lx) * hh / 12.0
-                           + (Lyy - Hm[0] * Ly) * hh / 12.0 + (Lzz - I[0] * Lz) * hh / 12.0;
-        const double M_1 = -dt / (2.0 * L0) + hh / 12.0;   // M_1 = M_2 = M_3 (h = k = l)
-        const double cc = L0 * M_1;
-        const double M_4 = dt / (2.0 * L0);
-        out.Cm = (1.0 + 2.0 * M_4 * M18 / dt) * L0 - 6.0 * cc * g.invh2;
+        const double M18 = 0.5 * (L0 - Lp) + ((Lxx - G[0] * Lx) + (Lyy - Hm[0] * Ly) + (Lzz - I[0] * Lz)) * g.h2_12;
+        // c = L M_1 = L h^2/12 - dt/2 (M_1 = M_2 = M_3 for h = k = l); the centre
+        // (1 + 2 M_4 M18 / dt) L with M_4 = dt/(2L) is L + M18
+        const double cc = L0 * g.h2_12 - 0.5 * dt;
+        out.Cm = L0 + M18 - 6.0 * cc * g.invh2;
         out.sm = cc * g.invh2;
         // L M15 = (h^2/6) dL/dx, etc.
-        out.am[0] = (cc * G[0] - hh / 6.0 * Lx) * g.inv2h;
-        out.am[1] = (cc * Hm[0] - hh / 6.0 * Ly) * g.inv2h;
-        out.am[2] = (cc * I[0] - hh / 6.0 * Lz) * g.inv2h;
+        out.am[0] = (cc * G[0] - 2.0 * g.h2_12 * Lx) * g.inv2h;
+        out.am[1] = (cc * Hm[0] - 2.0 * g.h2_12 * Ly) * g.inv2h;
+        out.am[2] = (cc * I[0] - 2.0 * g.h2_12 * Lz) * g.inv2h;
     }
     // ---- momentum right-hand sides
     {
@@ -473,7 +473,7 @@ __device__ __forceinline__ void assemble_node(const Geo &g, const Phys &P, int i
             vv[m] = v[o[m]];
             ww[m] = w[o[m]];
         }
-        const double ct = hh / 12.0 - dt / 2.0;     // L M_1 with L = 1
+        const double ct = g.h2_12 - 0.5 * dt;       // L M_1 with L = 1
         out.Ct = 1.0 - 6.0 * ct * g.invh2;          // M18 = 0 and M15..M17 = 0 for constant L
         out.st = ct * g.invh2;
         out.at[0] = ct * uu[0] * g.inv2h;
