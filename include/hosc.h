@@ -85,7 +85,14 @@ typedef struct hosc_params {
     int32_t solve_maxit;    /* cap on red-black sweeps per solve (default 4000) */
     int32_t check_every;    /* sweeps between convergence checks; 0 -> adaptive */
     int32_t solver;         /* hosc_solver_kind (default HOSC_SOLVER_AUTO) */
-    int32_t reserved;       /* must be 0 */
+    int32_t p_iters;        /* pressure iterations (Sec. 2.2): momentum solves per step at most.
+                               After a momentum solve whose trial velocity has max|div v| > div_tol
+                               the pressure is corrected (p <- p - lambda div v) and, while fewer
+                               than p_iters solves were made, the momentum sources are re-formed
+                               from level n with the corrected pressure and the momentum increments
+                               solved again.  0 or 1: one solve and at most one correction per step
+                               (default 1); at most 64.  Single-cavity solvers only: batches and the
+                               server refuse p_iters > 1 with HOSC_E_ARG. */
     double omega;           /* SOR relaxation of the red-black sweeps: 0 = adaptive per system (default),
                                else fixed in (0, 2) */
     double i2_floor;        /* eta = max(I2, i2_floor)^((n-1)/2), default 1e-8 */
@@ -96,14 +103,16 @@ typedef struct hosc_params {
 typedef struct hosc_step_info {
     double res[4];          /* steady residual ||chi^{n+1}-chi^n||_2/||chi^{n+1}||_2 of u, v, w, theta */
     double relres[4];       /* last measured relative residual of each implicit solve */
-    double maxdiv;          /* max |div v^{n+1}| over interior nodes before the correction */
+    double maxdiv;          /* max |div v^{n+1}| over interior nodes of the accepted velocity, before
+                               its correction */
     int64_t step;           /* steps taken since the state was set */
     int32_t sweeps[2];      /* red-black sweeps of the momentum and the energy solve (last step) */
     int32_t bicg_iters[2];  /* BiCGSTAB iterations of the momentum and the energy solve (last step) */
     double omega[2];        /* SOR relaxation of the momentum and the energy sweeps after the last step */
     double dominance[2];    /* max over rows of (sum |off-diagonal|) / |centre| of the momentum and energy
                                matrices (> 1: a row is not diagonally dominant); 0 if not measured */
-    int32_t corrected;      /* 1 if the pressure correction was applied */
+    int32_t corrected;      /* pressure corrections applied in the step (0 .. p_iters; 0 or 1 with one
+                               pressure iteration) */
     int32_t status;         /* hosc_status of the step */
 } hosc_step_info;
 

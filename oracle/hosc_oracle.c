@@ -41,7 +41,14 @@
  *   R12 eta = max(I2, i2_floor)^((n-1)/2); I2 itself is left raw in E_FF.
  *   R13 buoyancy Ra Pr (theta - theta_ref), theta_ref = 1/2 by default.
  *   R14 lambda defaults to h^2/(3 dt) (chosen by the caller).
- *   R15 one pressure correction per step, applied when max|div| > div_tol.
+ *   R15 pressure iterations within a step (Sec. 2.2): after the momentum solves the
+ *       largest |div v^{n+1}| is measured; above div_tol the pressure is corrected
+ *       by p <- p - lambda div v and, while fewer than p_iters solves were made,
+ *       the sources E* are re-formed from level n with the corrected pressure and
+ *       the momentum increments solved again.  p_iters <= 1 is one correction per
+ *       step.  Each re-solve starts from level n (never from the trial velocity).
+ *   R26 at the first step (R11) the level n-1 sources follow each pressure iterate,
+ *       so that their time difference stays zero in every solve of that step.
  *   R16 both sides solve in increment form B dchi = b, b = dt (R - A chi^n).
  *   R17 steady residual per field ||chi^{n+1}-chi^n||_2 / ||chi^{n+1}||_2 over all
  *       nodes.
@@ -65,7 +72,7 @@ typedef struct {
     int32_t N;          /* nodes per side including walls */
     int32_t maxit;      /* BiCGSTAB iteration cap */
     int32_t dense;      /* nonzero: dense LU instead of BiCGSTAB */
-    int32_t pad;
+    int32_t p_iters;    /* momentum solves per step at most (pressure iterations, R15); <= 1: one */
     double Ra, Pr, n_pl, dt;
     double theta_hot, theta_cold, theta_ref;
     double lambda, div_tol, i2_floor, phi, solve_tol;
@@ -84,7 +91,7 @@ typedef struct {
     double maxdiv;          /* max |div v^{n+1}| over interior nodes, before correction */
     double relres[4];       /* final ||b - B dchi|| / ||b|| of each solve */
     int32_t iters[4];       /* solver iterations (0 for dense) */
-    int32_t corrected;      /* 1 if the pressure correction was applied */
+    int32_t corrected;      /* pressure corrections applied in the step (0 .. p_iters) */
     int32_t status;         /* 0 ok, 1 not converged, 2 non-finite */
 } or_info;
 
@@ -728,13 +735,16 @@ int or_apply_B(const or_params *P, const or_state *S, int eq, const double *x, d
 }
 
 /* One HOSC time step (Sec. 2.2): viscosity and sources from level n, the four
- * increment solves, the update with boundary conditions, the steady residual and
- * the pressure correction; level n becomes level n-1. */
+ * increment solves, the pressure iterations of the modified artificial-
+ * compressibility method (momentum re-solved after each correction, R15), the
+ * update with boundary conditions and the steady residual; level n becomes level
+ * n-1. */
 int or_step(const or_params *P, or_state *S, or_info *info)
 {
     int N = P->N, M = N - 2;
     size_t n3 = (size_t)N * N * N;
     double h = 1.0 / (N - 1);
+    const int first = S->first;
     double *eta = malloc(n3 * sizeof(double));
     double *E[3] = {malloc(n3 * sizeof(double)), malloc(n3 * sizeof(double)), malloc(n3 * sizeof(double))};
     stage_sources(P, S, eta, E[0], E[1], E[2]);
@@ -755,13 +765,53 @@ int or_step(const or_params *P, or_state *S, or_info *info)
     B_rows(&Cm, rows_m);
     B_rows(&Ct, rows_t);
 
+    /* energy: its coefficients and sources do not involve the pressure (R24) */
     double *d = calloc(4 * n3, sizeof(double));
-    int status = 0;
-    for (int q = 0; q < 4; ++q) {
-        int st = solve_increment(P, q < 3 ? rows_m : rows_t, q == 3, b + q * n3, d + q * n3, &info->relres[q],
-                                 &info->iters[q]);
-        if (st > status) status = st;
+    int status = solve_increment(P, rows_t, 1, b + 3 * n3, d + 3 * n3, &info->relres[3], &info->iters[3]);
+
+    /* momentum with pressure iterations: trial velocity level n + increment, its
+     * divergence, and a correction of p followed by a re-solve while allowed */
+    const int K = P->p_iters > 1 ? P->p_iters : 1;
+    double *trial[3] = {malloc(n3 * sizeof(double)), malloc(n3 * sizeof(double)), malloc(n3 * sizeof(double))};
+    double *div = calloc(n3, sizeof(double));
+    double maxdiv = 0.0;
+    info->corrected = 0;
+    for (int q = 0; q < 3; ++q) info->iters[q] = 0;
+    for (int it = 0;; ++it) {
+        for (int q = 0; q < 3; ++q) {
+            int iters = 0;
+            int st = solve_increment(P, rows_m, 0, b + q * n3, d + q * n3, &info->relres[q], &iters);
+            info->iters[q] += iters;
+            if (st > status) status = st;
+            memcpy(trial[q], chi[q], n3 * sizeof(double));
+            for (int k = 1; k < N - 1; ++k)
+                for (int j = 1; j < N - 1; ++j)
+                    for (int i = 1; i < N - 1; ++i) trial[q][ID(N, i, j, k)] += d[q * n3 + ID(N, i, j, k)];
+        }
+        maxdiv = 0.0;
+        for (int k = 1; k < N - 1; ++k)
+            for (int j = 1; j < N - 1; ++j)
+                for (int i = 1; i < N - 1; ++i) {
+                    double D = D1(trial[0], N, h, i, j, k, 0) + D1(trial[1], N, h, i, j, k, 1)
+                               + D1(trial[2], N, h, i, j, k, 2);
+                    div[ID(N, i, j, k)] = D;
+                    if (fabs(D) > maxdiv || isnan(D)) maxdiv = isnan(D) ? NAN : fabs(D);
+                }
+        if (!(maxdiv > P->div_tol)) break;      /* accurate enough (or non-finite) */
+        /* p <- p - lambda div v at interior nodes, walls by the zero-gradient closure */
+        for (int k = 1; k < N - 1; ++k)
+            for (int j = 1; j < N - 1; ++j)
+                for (int i = 1; i < N - 1; ++i) S->p[ID(N, i, j, k)] -= P->lambda * div[ID(N, i, j, k)];
+        pressure_closure(S->p, N);
+        info->corrected += 1;
+        if (it + 1 >= K) break;
+        /* sources of level n with the corrected pressure; eta is unchanged */
+        or_estar_field(P, S->u, S->v, S->w, S->T, S->p, eta, E[0], E[1], E[2]);
+        if (first)
+            for (int q = 0; q < 3; ++q) memcpy(Ep[q], E[q], n3 * sizeof(double));
+        for (int q = 0; q < 3; ++q) rhs_field(&Cm, E[q], Ep[q], chi[q], b + q * n3);
     }
+    info->maxdiv = maxdiv;
 
     /* level n becomes level n-1 */
     memcpy(S->up, S->u, n3 * sizeof(double));
@@ -772,40 +822,23 @@ int or_step(const or_params *P, or_state *S, or_info *info)
     memcpy(S->Evp, E[1], n3 * sizeof(double));
     memcpy(S->Ewp, E[2], n3 * sizeof(double));
 
-    /* update chi^{n+1} = chi^n + dchi at interior nodes, then the theta walls */
+    /* update chi^{n+1} = chi^n + dchi: the accepted trial velocity, theta at interior
+     * nodes and then its walls */
     double *old = malloc(4 * n3 * sizeof(double));
     for (int q = 0; q < 4; ++q) memcpy(old + q * n3, chi[q], n3 * sizeof(double));
-    for (int q = 0; q < 4; ++q)
-        for (int k = 1; k < N - 1; ++k)
-            for (int j = 1; j < N - 1; ++j)
-                for (int i = 1; i < N - 1; ++i) chi[q][ID(N, i, j, k)] += d[q * n3 + ID(N, i, j, k)];
+    for (int q = 0; q < 3; ++q) memcpy(chi[q], trial[q], n3 * sizeof(double));
+    for (int k = 1; k < N - 1; ++k)
+        for (int j = 1; j < N - 1; ++j)
+            for (int i = 1; i < N - 1; ++i) S->T[ID(N, i, j, k)] += d[3 * n3 + ID(N, i, j, k)];
     theta_yz_closure(S->T, N);
     for (int q = 0; q < 4; ++q) info->res[q] = field_res(old + q * n3, chi[q], n3);
 
-    /* modified artificial compressibility: p <- p - lambda div v (Sec. 2.2) */
-    double *div = calloc(n3, sizeof(double));
-    double maxdiv = 0.0;
-    for (int k = 1; k < N - 1; ++k)
-        for (int j = 1; j < N - 1; ++j)
-            for (int i = 1; i < N - 1; ++i) {
-                double D = D1(S->u, N, h, i, j, k, 0) + D1(S->v, N, h, i, j, k, 1) + D1(S->w, N, h, i, j, k, 2);
-                div[ID(N, i, j, k)] = D;
-                if (fabs(D) > maxdiv || isnan(D)) maxdiv = isnan(D) ? NAN : fabs(D);
-            }
-    info->maxdiv = maxdiv;
-    info->corrected = 0;
-    if (maxdiv > P->div_tol) {
-        for (int k = 1; k < N - 1; ++k)
-            for (int j = 1; j < N - 1; ++j)
-                for (int i = 1; i < N - 1; ++i) S->p[ID(N, i, j, k)] -= P->lambda * div[ID(N, i, j, k)];
-        pressure_closure(S->p, N);
-        info->corrected = 1;
-    }
     for (int q = 0; q < 4; ++q)
         if (!isfinite(info->res[q])) status = 2;
     if (!isfinite(maxdiv)) status = 2;
     info->status = status;
 
+    free(trial[0]); free(trial[1]); free(trial[2]);
     free(div); free(old); free(d); free(rows_m); free(rows_t); free(b);
     coef_free(&cs);
     free(eta); free(E[0]); free(E[1]); free(E[2]);

@@ -25,7 +25,7 @@ _dp = ctypes.POINTER(ctypes.c_double)
 
 class _Params(ctypes.Structure):
     _fields_ = [
-        ("N", ctypes.c_int32), ("maxit", ctypes.c_int32), ("dense", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("N", ctypes.c_int32), ("maxit", ctypes.c_int32), ("dense", ctypes.c_int32), ("p_iters", ctypes.c_int32),
         ("Ra", ctypes.c_double), ("Pr", ctypes.c_double), ("n_pl", ctypes.c_double), ("dt", ctypes.c_double),
         ("theta_hot", ctypes.c_double), ("theta_cold", ctypes.c_double), ("theta_ref", ctypes.c_double),
         ("lam", ctypes.c_double), ("div_tol", ctypes.c_double), ("i2_floor", ctypes.c_double),
@@ -99,6 +99,7 @@ class Params:
     solve_tol: float = 1e-13
     maxit: int = 20000
     dense: bool = False
+    p_iters: int = 1                   # momentum solves per step at most (pressure iterations)
 
     @property
     def h(self) -> float:
@@ -106,7 +107,7 @@ class Params:
 
     def c(self) -> _Params:
         lam = self.lam if self.lam is not None else self.h ** 2 / (3.0 * self.dt)
-        return _Params(N=self.N, maxit=self.maxit, dense=int(self.dense), pad=0, Ra=self.Ra, Pr=self.Pr,
+        return _Params(N=self.N, maxit=self.maxit, dense=int(self.dense), p_iters=self.p_iters, Ra=self.Ra, Pr=self.Pr,
                        n_pl=self.n_pl, dt=self.dt, theta_hot=self.theta_hot, theta_cold=self.theta_cold,
                        theta_ref=self.theta_ref, lam=lam, div_tol=self.div_tol, i2_floor=self.i2_floor,
                        phi=self.phi, solve_tol=self.solve_tol)

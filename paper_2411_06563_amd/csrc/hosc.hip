@@ -136,7 +136,7 @@ const char *check_params(const hosc_params *p)
     if (p->check_every < 0) return "check_every must be >= 0";
     if (!(p->omega >= 0.0 && p->omega < 2.0)) return "omega must be 0 (adaptive) or in (0, 2)";
     if (p->solver < HOSC_SOLVER_AUTO || p->solver > HOSC_SOLVER_BICGSTAB) return "unknown solver";
-    if (p->reserved != 0) return "reserved must be 0";
+    if (p->p_iters < 0 || p->p_iters > 64) return "p_iters must be in [0, 64]";
     if (!(p->i2_floor > 0.0) || !std::isfinite(p->i2_floor)) return "i2_floor must be finite and > 0";
     if (!(p->phi >= 0.0) || !std::isfinite(p->phi)) return "phi must be finite and >= 0";
     if (!std::isfinite(p->theta_hot) || !std::isfinite(p->theta_cold) || !std::isfinite(p->theta_ref))
@@ -537,6 +537,7 @@ struct SolveOut {
     double dominance[2] = {0, 0};
     int sweeps[2] = {0, 0};
     int bicg[2] = {0, 0};
+    int corrections = 0;    // pressure corrections made between the momentum solves of the step
 };
 
 hosc_status zero_group(hosc_solver *s, int group)
@@ -1099,13 +1100,16 @@ hosc_status solve_finish(hosc_solver *s, int failed, int bicg_mask, double bn2[4
     return HOSC_OK;
 }
 
-hosc_status solve(hosc_solver *s, SolveOut &o)
+// Solves the groups in `groups` (1 momentum, 2 energy).
+hosc_status solve(hosc_solver *s, SolveOut &o, int groups = 3)
 {
     // ||b/C||^2 of the four systems (reduced after the assembly into red[0..3]) are
     // read by the solvers together with their first convergence check
     double bn2[4] = {-1.0, -1.0, -1.0, -1.0};
     int sor_mask, bicg_mask, failed = 0;
     solve_masks(s, sor_mask, bicg_mask);
+    sor_mask &= groups;
+    bicg_mask &= groups;
     if (sor_mask) {
         hosc_status r = s->fp32 ? solve_refined(s, sor_mask, bn2, o, &failed)
                                 : run_sor<double>(s, sor_mask, bn2, o, &failed, sweep_args(s), s->P.solve_rtol);
@@ -1114,12 +1118,11 @@ hosc_status solve(hosc_solver *s, SolveOut &o)
     return solve_finish(s, failed, bicg_mask, bn2, o);
 }
 
-// eta, E*, assembly and its reductions (||b/C||^2 into red[0..3], dominance into
-// red[44..45]); launches only.
-hosc_status pre_solve(hosc_solver *s)
+// Assembly of the rows and right-hand sides and its reductions (||b/C||^2 into
+// red[0..3], dominance into red[44..45]); with `rows32` the FP32 row copies of the
+// precision mode.  Launches only.
+hosc_status assemble(hosc_solver *s, bool rows32)
 {
-    hosc_status r = stage_sources(s, true);
-    if (r) return r;
     ColourArrays ca;
     ca.ms = s->ms;
     for (int d = 0; d < 3; ++d) {
@@ -1128,12 +1131,12 @@ hosc_status pre_solve(hosc_solver *s)
         ca.ta[d] = s->ta[d];
     }
     ca.tb = s->tb;
-    r = timed_begin(s);
+    hosc_status r = timed_begin(s);
     if (r) return r;
     k_assemble<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(
         s->g, s->ph, s->u, s->v, s->w, s->T, s->eta, s->E[0], s->E[1], s->E[2], s->u2, s->v2, s->w2, s->etap,
         s->Ep[0], s->Ep[1], s->Ep[2], ca, s->partR, s->partB);
-    if (s->fp32)    // a streaming pass: cheaper than the FP32 stores inside the assembly (register budget)
+    if (s->fp32 && rows32)    // a streaming pass: cheaper than the FP32 stores inside the assembly (register budget)
         k_rows_f32<<<2048, 256, 0, s->st>>>(2 * s->g.cs, s->ms, s->ma[0], s->ma[1], s->ma[2], s->ta[0], s->ta[1],
                                            s->ta[2], s->fms, s->fma[0], s->fma[1], s->fma[2], s->fta[0], s->fta[1],
                                            s->fta[2]);
@@ -1141,6 +1144,56 @@ hosc_status pre_solve(hosc_solver *s)
     if (r) return r;
     Reductions().add(s->partR, s->L.nb_int, 4, 0, s->red).add(s->partB, s->L.nb_int, 2, 1, s->red + 44).launch(s->st);
     return launch_check(s, "assemble");
+}
+
+// eta, E*, assembly and its reductions; launches only.
+hosc_status pre_solve(hosc_solver *s)
+{
+    hosc_status r = stage_sources(s, true);
+    if (r) return r;
+    return assemble(s, true);
+}
+
+// Pressure iterations of the step (Sec. 2.2): while the trial velocity level n +
+// increment has max |div| > div_tol and fewer than p_iters momentum solves were
+// made, correct p by -lambda div, re-form the momentum sources of level n with the
+// corrected pressure (eta and the rows are unchanged; at the first step level n-1
+// follows them) and solve the momentum increments again, warm-started from the
+// last ones.  The last solve's divergence and correction are the step's own
+// (post_launch / post_finish).
+hosc_status pressure_iterations(hosc_solver *s, bool first, SolveOut &so)
+{
+    for (int it = 1; it < s->P.p_iters; ++it) {
+        k_divergence_trial<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, s->u, s->v, s->w, s->md[0], s->md[1],
+                                                                     s->md[2], s->dbg, s->partR0);
+        Reductions().add(s->partR0, s->L.nb_int, 1, 1, s->red + 62).launch(s->st);
+        hosc_status r = launch_check(s, "trial divergence");
+        if (r) return r;
+        HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red + 62, sizeof(double), hipMemcpyDeviceToHost, s->st));
+        HIPCHK(s, wait_stream(s->st));
+        if (!(s->hbuf[0] > s->P.div_tol)) break;    // within tolerance (a non-finite value fails later)
+        k_pressure_apply<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, s->ph, s->dbg, s->p);
+        k_p_walls<<<s->L.grd_face, s->L.blk_face, 0, s->st>>>(s->g, s->p);
+        so.corrections += 1;
+        k_estar<<<s->L.grd_all, s->L.blk_all, 0, s->st>>>(s->g, s->ph, s->u, s->v, s->w, s->T, s->p, s->eta,
+                                                           s->E[0], s->E[1], s->E[2]);
+        r = launch_check(s, "pressure iteration");
+        if (r) return r;
+        if (first)
+            for (int d = 0; d < 3; ++d)
+                HIPCHK(s, hipMemcpyAsync(s->Ep[d], s->E[d], s->g.n3 * sizeof(double), hipMemcpyDeviceToDevice,
+                                         s->st));
+        r = assemble(s, false);
+        if (r) return r;
+        SolveOut o2;
+        r = solve(s, o2, 1);
+        if (r) return r;
+        for (int f = 0; f < 3; ++f) so.relres[f] = o2.relres[f];
+        so.dominance[0] = o2.dominance[0];
+        so.sweeps[0] += o2.sweeps[0];
+        so.bicg[0] += o2.bicg[0];
+    }
+    return HOSC_OK;
 }
 
 // Update, theta walls, divergence (with the correction and the pressure walls when
@@ -1245,7 +1298,7 @@ hosc_status post_finish(hosc_solver *s, const double *hb, const SolveOut &so, ho
         info->omega[1] = s->om[1];
         info->dominance[0] = so.dominance[0];
         info->dominance[1] = so.dominance[1];
-        info->corrected = corrected;
+        info->corrected = corrected + so.corrections;
         info->status = finite ? HOSC_OK : HOSC_E_NONFINITE;
     }
     if (!finite) return fail(s, HOSC_E_NONFINITE, "non-finite steady residual or divergence");
@@ -1254,10 +1307,13 @@ hosc_status post_finish(hosc_solver *s, const double *hb, const SolveOut &so, ho
 
 hosc_status one_step(hosc_solver *s, hosc_step_info *info)
 {
+    const bool first = s->first;
     hosc_status r = pre_solve(s);
     if (r) return r;
     SolveOut so;
     r = solve(s, so);
+    if (r) return r;
+    r = pressure_iterations(s, first, so);
     if (r) return r;
     r = post_launch(s);
     if (r) return r;
@@ -1940,7 +1996,7 @@ hosc_status hosc_params_default(hosc_params *p)
     p->solve_maxit = 4000;
     p->check_every = 0;
     p->solver = HOSC_SOLVER_AUTO;
-    p->reserved = 0;
+    p->p_iters = 1;
     p->omega = 0.0;
     p->i2_floor = 1e-8;
     p->phi = 1e-4;
@@ -2294,6 +2350,9 @@ hosc_status hosc_batch_create(const hosc_params *p, int32_t count, void *d_ws, s
     for (int i = 1; i < count; ++i)
         if (p[i].precision != p[0].precision)
             return bfail(nullptr, HOSC_E_ARG, "all cavities of a batch must use one precision");
+    for (int i = 0; i < count; ++i)
+        if (p[i].p_iters > 1)
+            return bfail(nullptr, HOSC_E_ARG, "cavity " + std::to_string(i) + ": p_iters > 1 needs a single-cavity solver");
     if (!d_ws) return bfail(nullptr, HOSC_E_ARG, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return bfail(nullptr, HOSC_E_ARG, "workspace must be 256-byte aligned");
     if (ws_bytes < need) return bfail(nullptr, HOSC_E_NOMEM, "workspace smaller than hosc_batch_workspace_bytes()");
@@ -2476,6 +2535,7 @@ hosc_status hosc_server_submit(hosc_server *v, const hosc_request *rq, uint64_t 
     if (!v || !rq) return HOSC_E_ARG;
     const char *e = check_params(&rq->params);
     if (e) return sfail(v, HOSC_E_ARG, e);
+    if (rq->params.p_iters > 1) return sfail(v, HOSC_E_ARG, "p_iters > 1 needs a single-cavity solver");
     if (!(rq->res_tol > 0.0) || rq->max_steps < 1) return sfail(v, HOSC_E_ARG, "res_tol > 0 and max_steps >= 1 required");
     if (!std::isfinite(rq->noise_amp)) return sfail(v, HOSC_E_ARG, "noise_amp must be finite");
     size_t bytes = 0;

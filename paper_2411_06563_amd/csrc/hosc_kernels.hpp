@@ -1193,6 +1193,39 @@ __global__ void __launch_bounds__(256) k_divergence(Geo g, Phys P, const double 
     block_max_store<1>(acc, partial + blk);
 }
 
+// Divergence of a trial velocity level n + increment (the increments in the
+// colour-split layout, zero on the walls), for the pressure iterations of a step:
+// the same sums as k_update followed by k_divergence, so the value is identical to
+// the one the step measures once the trial is accepted.  D into dstore, partial
+// max |D|.
+__device__ __forceinline__ double trial_vel(const Geo &g, const double *__restrict__ f,
+                                            const double *__restrict__ df, int i, int j, int k)
+{
+    const double x = f[nid(g, i, j, k)];
+    if (i < 1 || i > g.N - 2 || j < 1 || j > g.N - 2 || k < 1 || k > g.N - 2) return x;
+    return x + df[(size_t)((i + j + k) & 1) * g.cs + rowid(g, j, k) + (i >> 1)];
+}
+
+__global__ void __launch_bounds__(256) k_divergence_trial(Geo g, const double *__restrict__ u,
+                                                          const double *__restrict__ v, const double *__restrict__ w,
+                                                          const double *__restrict__ du, const double *__restrict__ dv,
+                                                          const double *__restrict__ dw, double *__restrict__ dstore,
+                                                          double *__restrict__ partial)
+{
+    const Tile tl = xcd_tile();
+    const int i = 1 + tl.x * blockDim.x + threadIdx.x, j = 1 + tl.y * blockDim.y + threadIdx.y, k = 1 + tl.z;
+    double acc[1] = {0.0};
+    if (i <= g.N - 2 && j <= g.N - 2) {
+        const double D = (trial_vel(g, u, du, i + 1, j, k) - trial_vel(g, u, du, i - 1, j, k)) * g.inv2h
+                         + (trial_vel(g, v, dv, i, j + 1, k) - trial_vel(g, v, dv, i, j - 1, k)) * g.inv2h
+                         + (trial_vel(g, w, dw, i, j, k + 1) - trial_vel(g, w, dw, i, j, k - 1)) * g.inv2h;
+        acc[0] = fabs(D);
+        dstore[nid(g, i, j, k)] = D;
+    }
+    const int blk = tl.id;
+    block_max_store<1>(acc, partial + blk);
+}
+
 // p <- p - lambda D from a stored divergence (when the correction is gated by a
 // positive tolerance the decision needs the global max first).
 __global__ void __launch_bounds__(256) k_pressure_apply(Geo g, Phys P, const double *__restrict__ dstore,

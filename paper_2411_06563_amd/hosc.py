@@ -41,7 +41,7 @@ class CParams(ctypes.Structure):
                 ("theta_hot", ctypes.c_double), ("theta_cold", ctypes.c_double), ("theta_ref", ctypes.c_double),
                 ("lam", ctypes.c_double), ("div_tol", ctypes.c_double), ("solve_rtol", ctypes.c_double),
                 ("solve_maxit", ctypes.c_int32), ("check_every", ctypes.c_int32), ("solver", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("omega", ctypes.c_double),
+                ("p_iters", ctypes.c_int32), ("omega", ctypes.c_double),
                 ("i2_floor", ctypes.c_double), ("phi", ctypes.c_double)]
 
 

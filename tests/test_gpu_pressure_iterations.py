@@ -1,0 +1,121 @@
+"""Pressure iterations (p_iters > 1): after each momentum solve whose velocity has
+max |div v| above div_tol the pressure is corrected and the momentum equations are
+solved again from level n with the corrected pressure (Sec. 2.2).  The GPU path
+against the FP64 oracle with the same setting: fields to the FP64 bar (relative L2
+<= 1e-10), the number of corrections of every step equal, the measured divergence
+to the same bar.  The decision to stop is taken in FP64 on both sides."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2411_06563_amd.inputs import initial_state
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hosc():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2411_06563_amd import hosc as h
+    return h
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a)
+
+
+def _run_pair(hosc, oracle_lib, N, steps, K, div_tol, seed=9, precision=0, solver="auto", **phys):
+    kind = {"auto": hosc.SOLVER_AUTO, "bicgstab": hosc.SOLVER_BICGSTAB, "sor": hosc.SOLVER_SOR}[solver]
+    s = hosc.Solver(hosc.params(N, p_iters=K, div_tol=div_tol, solve_rtol=1e-12, solver=kind, precision=precision,
+                                **phys))
+    o = oracle_lib.Oracle(oracle_lib.Params(N=N, p_iters=K, div_tol=div_tol, solve_tol=1e-13, **phys))
+    s.init_fields(seed, 1e-3)
+    o.set_state(**initial_state(N, seed, 1e-3))
+    gi = [s.step(1) for _ in range(steps)]
+    oi = o.step(steps)
+    return s, o, gi, oi
+
+
+CASES = [
+    # N, K, div_tol, steps, precision, solver, physics
+    (17, 4, 0.0, 8, 0, "auto", dict(Ra=1e3, n_pl=1.0, Pr=1.0, dt=1e-3)),
+    (18, 3, 0.0, 8, 0, "auto", dict(Ra=1e4, n_pl=0.75, Pr=1.0, dt=5e-4)),
+    (17, 8, 2.5, 8, 0, "auto", dict(Ra=1e3, n_pl=1.0, Pr=1.0, dt=1e-3)),       # stops early in some steps
+    (13, 3, 0.0, 6, 0, "bicgstab", dict(Ra=1e4, n_pl=1.25, Pr=1.0, dt=1e-3)),
+    (17, 4, 0.0, 6, 1, "auto", dict(Ra=1e3, n_pl=1.0, Pr=1.0, dt=1e-3)),       # FP32 sweeps, FP64 refinement
+]
+
+
+@pytest.mark.parametrize("N,K,div_tol,steps,precision,solver,phys", CASES)
+def test_pressure_iterations_match_oracle(hosc, oracle_lib, N, K, div_tol, steps, precision, solver, phys):
+    say(f"[p-iter] N={N} K={K} div_tol={div_tol} precision={precision} {solver} {phys}")
+    s, o, gi, oi = _run_pair(hosc, oracle_lib, N, steps, K, div_tol, precision=precision, solver=solver, **phys)
+    gc = [i.corrected for i in gi]
+    oc = [i.corrected for i in oi]
+    say(f"[p-iter] corrections GPU {gc} oracle {oc}")
+    assert gc == oc
+    if div_tol == 0.0:
+        assert all(c == K for c in gc)
+    else:
+        assert min(gc) < K          # the tolerance ended some iterations early
+    for a, b in zip(gi, oi):
+        assert abs(a.maxdiv - b.maxdiv) <= 1e-10 * max(b.maxdiv, 1e-300)
+        if div_tol > 0.0 and a.corrected < K:
+            assert a.maxdiv <= div_tol
+    g = s.get_state()
+    for f in ("u", "v", "w", "T", "p"):
+        e = rel(g[f], o.a[f])
+        say(f"[p-iter] {f} rel L2 {e:.3e}")
+        assert e <= 1e-10, f
+    s.close()
+
+
+def test_pressure_iterations_full_size(hosc, oracle_lib):
+    """129^3 benchmark physics (n = 0.75, Ra = 1e5, dt = 5e-5, seed 2) with three
+    momentum solves per step: two steps against the oracle at full size."""
+    N = 129
+    say("[p-iter] 129^3 K=3, 2 steps")
+    s, o, gi, oi = _run_pair(hosc, oracle_lib, N, 2, 3, 0.0, seed=2, Ra=1e5, n_pl=0.75, Pr=1.0, dt=5e-5)
+    assert [i.corrected for i in gi] == [i.corrected for i in oi] == [3, 3]
+    g = s.get_state()
+    for f in ("u", "v", "w", "T", "p"):
+        e = rel(g[f], o.a[f])
+        say(f"[p-iter] 129^3 {f} rel L2 {e:.3e}")
+        assert e <= 1e-10, f
+    s.close()
+
+
+def test_single_iteration_unchanged(hosc):
+    """p_iters 0 and 1 are the one-correction step: identical results."""
+    out = []
+    for K in (0, 1):
+        s = hosc.Solver(hosc.params(17, Ra=1e4, n_pl=0.75, dt=5e-4, p_iters=K, solve_rtol=1e-12))
+        s.init_fields(4, 1e-3)
+        infos = [s.step(1) for _ in range(5)]
+        out.append((s.get_state(), [i.corrected for i in infos]))
+        s.close()
+    assert out[0][1] == out[1][1] == [1] * 5
+    for f in ("u", "v", "w", "T", "p"):
+        assert np.array_equal(out[0][0][f], out[1][0][f]), f
+
+
+def test_batch_and_server_refuse_pressure_iterations(hosc):
+    p = hosc.params(17, p_iters=2)
+    with pytest.raises(hosc.HoscError) as e:
+        hosc.Batch([hosc.params(17), p])
+    assert "p_iters" in str(e.value)
+    srv = hosc.Server(1 << 28, max_resident=2)
+    with pytest.raises(hosc.HoscError) as e:
+        srv.submit(p, 1)
+    assert "p_iters" in str(e.value)
+    srv.close()
+    with pytest.raises(hosc.HoscError):
+        hosc.Solver(hosc.params(17, p_iters=65))
