@@ -202,6 +202,15 @@ hosc_status hosc_diagnostics(hosc_solver *s, hosc_diag *d, double *nuavg_hot, do
  * arrays; either may be NULL). */
 hosc_status hosc_entropy_fields(hosc_solver *s, double *e_local, double *be_local);
 
+/* Monitoring points (the probes of the grid-independence study, Sec. 3.1, Table 1):
+ * u, v, w, theta and p of level n at n points of the closed unit cube, each by
+ * trilinear interpolation of the eight surrounding nodes (a point on a node returns
+ * that node's values).  xyz: host, n x 3 (x, y, z of each point, every coordinate
+ * in [0, 1]); out: host, n x 5 (u, v, w, theta, p of each point).  1 <= n <=
+ * min(4096, N^3/8).  Fails with HOSC_E_ARG on a bad count or coordinate and
+ * HOSC_E_STATE before a state was set.  Synchronous on the solver's stream. */
+hosc_status hosc_probe(hosc_solver *s, const double *xyz, int32_t n, double *out);
+
 /* Parity hook: assemble the step from the current state without advancing it.
  * Outputs (host, any may be NULL): eta[N^3], estar[3 N^3] (E*_u, E*_v, E*_w),
  * b[4 N^3] right-hand sides of the u, v, w, theta increment systems (walls 0),

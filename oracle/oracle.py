@@ -188,6 +188,33 @@ class Oracle:
         return {f: self.a[f].copy() for f in ("u", "v", "w", "T", "p")}
 
 
+def probe(fields: dict, points) -> np.ndarray:
+    """Trilinear interpolation of u, v, w, T, p (arrays [k, j, i]) at points
+    (n x 3, x y z in [0, 1]) from the eight surrounding nodes; n x 5.  The cell of a
+    point on the far wall is the last one (its upper weight is 1)."""
+    pts = np.asarray(points, dtype=np.float64).reshape(-1, 3)
+    N = fields["u"].shape[0]
+    out = np.zeros((pts.shape[0], 5))
+    for q, (x, y, z) in enumerate(pts):
+        lo, t = [], []
+        for c in (x, y, z):
+            f = c * (N - 1)
+            i = min(max(int(np.floor(f)), 0), N - 2)
+            lo.append(i)
+            t.append(f - i)
+        for fi, name in enumerate(("u", "v", "w", "T", "p")):
+            a = fields[name]
+            val = 0.0
+            for dk in (0, 1):
+                for dj in (0, 1):
+                    for di in (0, 1):
+                        wgt = ((t[0] if di else 1 - t[0]) * (t[1] if dj else 1 - t[1])
+                               * (t[2] if dk else 1 - t[2]))
+                        val += wgt * a[lo[2] + dk, lo[1] + dj, lo[0] + di]
+            out[q, fi] = val
+    return out
+
+
 def num_threads() -> int:
     return int(lib().or_num_threads())
 

@@ -2222,6 +2222,27 @@ hosc_status hosc_entropy_fields(hosc_solver *s, double *e_local, double *be_loca
     return HOSC_OK;
 }
 
+hosc_status hosc_probe(hosc_solver *s, const double *xyz, int32_t n, double *out)
+{
+    if (!s) return HOSC_E_ARG;
+    if (!xyz || !out) return fail(s, HOSC_E_ARG, "xyz and out are required");
+    const size_t cap = std::min<size_t>(4096, s->g.n3 / 8);
+    if (n < 1 || (size_t)n > cap)
+        return fail(s, HOSC_E_ARG, "n must be in [1, min(4096, N^3/8)] (" + std::to_string(cap) + " here)");
+    for (int i = 0; i < 3 * n; ++i)
+        if (!(xyz[i] >= 0.0 && xyz[i] <= 1.0)) return fail(s, HOSC_E_ARG, "probe coordinates must lie in [0, 1]");
+    if (!s->has_state) return fail(s, HOSC_E_STATE, "no state set");
+    // points and results staged in the scratch array (3n + 5n <= N^3 doubles)
+    double *dx = s->dbg, *dout = s->dbg + 3 * (size_t)n;
+    HIPCHK(s, hipMemcpyAsync(dx, xyz, 3 * (size_t)n * sizeof(double), hipMemcpyHostToDevice, s->st));
+    k_probe<<<(n + 255) / 256, 256, 0, s->st>>>(s->g, s->u, s->v, s->w, s->T, s->p, dx, n, dout);
+    hosc_status r = launch_check(s, "probe");
+    if (r) return r;
+    HIPCHK(s, hipMemcpyAsync(out, dout, 5 * (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    return HOSC_OK;
+}
+
 hosc_status hosc_debug_assemble(hosc_solver *s, double *eta, double *estar, double *b, double *Bmom, double *Btheta)
 {
     if (!s) return HOSC_E_ARG;

@@ -1240,6 +1240,42 @@ __global__ void __launch_bounds__(256) k_pressure_apply(Geo g, Phys P, const dou
 }
 
 // ---------------------------------------------------------------------------
+// Probes (the monitoring points of the grid-independence study, Sec. 3.1): u, v,
+// w, theta, p of level n at points of the closed unit cube by trilinear
+// interpolation of the eight surrounding nodes.  xyz[3q..3q+2] in [0, 1] (checked
+// by the caller), out[5q..5q+4].
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_probe(Geo g, const double *__restrict__ u, const double *__restrict__ v,
+                                               const double *__restrict__ w, const double *__restrict__ T,
+                                               const double *__restrict__ p, const double *__restrict__ xyz, int n,
+                                               double *__restrict__ out)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    int c0[3];
+    double t[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double f = xyz[3 * q + d] * (double)(g.N - 1);
+        const int i = min(max((int)floor(f), 0), g.N - 2);     // the last cell holds the far wall
+        c0[d] = i;
+        t[d] = f - (double)i;
+    }
+    const double *fld[5] = {u, v, w, T, p};
+    double acc[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int corner = 0; corner < 8; ++corner) {
+        const int a = corner & 1, b = (corner >> 1) & 1, c = corner >> 2;
+        const double wgt = (a ? t[0] : 1.0 - t[0]) * (b ? t[1] : 1.0 - t[1]) * (c ? t[2] : 1.0 - t[2]);
+        const size_t id = nid(g, c0[0] + a, c0[1] + b, c0[2] + c);
+#pragma unroll
+        for (int f = 0; f < 5; ++f) acc[f] += wgt * fld[f][id];
+    }
+#pragma unroll
+    for (int f = 0; f < 5; ++f) out[5 * q + f] = acc[f];
+}
+
+// ---------------------------------------------------------------------------
 // Nusselt numbers (Sec. 4.2): Nu = -d theta/dx on x = 0 and x = 1 by the 5-point
 // 4th-order one-sided difference; Simpson over y gives Nu_avg(z); Simpson over z
 // the mean; the max over z of Nu_avg is the quantity of Table 2.

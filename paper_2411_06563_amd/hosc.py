@@ -113,6 +113,7 @@ def lib() -> ctypes.CDLL:
     L.hosc_run_to_steady.argtypes = [vp, ctypes.c_double, ctypes.c_int64, ctypes.POINTER(CStepInfo)]
     L.hosc_diagnostics.argtypes = [vp, ctypes.POINTER(CDiag), _dp, _dp, _dp, _dp]
     L.hosc_entropy_fields.argtypes = [vp, _dp, _dp]
+    L.hosc_probe.argtypes = [vp, _dp, ctypes.c_int32, _dp]
     L.hosc_debug_assemble.argtypes = [vp, _dp, _dp, _dp, _dp, _dp]
     L.hosc_perf_enable.argtypes = [vp, ctypes.c_int32]
     L.hosc_perf_get.argtypes = [vp, ctypes.POINTER(CPerf)]
@@ -316,6 +317,14 @@ class Solver:
         el, bl = np.empty((N, N, N)), np.empty((N, N, N))
         _check(lib().hosc_entropy_fields(self.h, _ptr(el), _ptr(bl)), self.h)
         return el, bl
+
+    def probe(self, points) -> np.ndarray:
+        """u, v, w, theta, p at points (n x 3, coordinates in [0, 1]) by trilinear
+        interpolation; returns n x 5."""
+        xyz = np.ascontiguousarray(np.asarray(points, dtype=np.float64).reshape(-1, 3))
+        out = np.empty((xyz.shape[0], 5))
+        _check(lib().hosc_probe(self.h, _ptr(xyz), xyz.shape[0], _ptr(out)), self.h)
+        return out
 
     def debug_assemble(self) -> dict:
         N = self.N
