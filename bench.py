@@ -11,6 +11,12 @@ impulsive start (the FP64 oracle diverges at step 16 exactly like the GPU path),
 the timed steps are taken in segments of SEGMENT steps from the seeded initial
 state; the clock is stopped while the state is re-initialised between segments.
 
+`--workload piter` is the benchmark workload with pressure iterations: up to three
+momentum solves per step, the pressure corrected after each (div_tol = 0, so all
+three run).  After the timed run it also marches a Newtonian 41^3 cavity (Ra = 1e4,
+Pr = 1, dt = 0.4 h^2) to a per-step residual of 2.5e-12 with one and with four
+pressure iterations and reports steps and seconds of each.
+
 `--workload fp32r` is the precision form (n = 1.25, Ra = 1e4, FP32 rows and inner
 sweeps with FP64 residuals and refinement).  Shear-thickening flow cannot start
 from rest under the stated scheme (the second step's rows lose their centre), so
@@ -61,6 +67,11 @@ WORKLOADS = {
                   label="serving trace: Poisson arrivals at 2/s (seed 5), N uniform over {33,49,65,97,129}, "
                         "Ra log-uniform in [1e2,1e5], n uniform in [0.7,1.3], Pr=1, dt=0.4 h^2, FP32 rows/sweeps + "
                         "FP64 refinement, rtol 1e-10, each request to res < 1e-8 or 200 steps, HBM budget 4 GiB"),
+    # pressure iterations: the benchmark workload with three momentum solves per step
+    "piter": dict(N=129, Ra=1e5, n_pl=0.75, Pr=1.0, dt=5e-5, seed=2, noise=1e-3, solve_rtol=1e-10, precision=0,
+                  p_iters=3,
+                  label="HOSC cavity 129^3, n=0.75, Ra=1e5, Pr=1, dt=5e-5, FP64, rtol 1e-10, seed 2, "
+                        "3 pressure iterations per step (momentum re-solved after each correction)"),
     "fp32r": dict(N=129, Ra=1e4, n_pl=1.25, Pr=1.0, dt=5e-5, seed=3, noise=1e-3, solve_rtol=1e-10, precision=1,
                   newtonian_start=20, segment=60,
                   label="HOSC cavity 129^3, n=1.25, Ra=1e4, Pr=1, dt=5e-5, FP32 rows/sweeps + FP64 refinement, "
@@ -98,6 +109,33 @@ def cpu_baseline(budget_s: float = 20.0) -> dict:
     return {"value": M3 * steps / el, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
             "sample": f"first {steps} step(s) of the 129^3 workload from its initial state "
                       f"({el:.1f} s, FP64, BiCGSTAB tol 1e-13, {cores} OpenMP threads)"}
+
+
+def steady_comparison(hosc, torch, N=41, tol=2.5e-12):
+    """Steps and seconds to a steady residual `tol` per step for a Newtonian cavity
+    (Ra = 1e4, Pr = 1, dt = 0.4 h^2) with one and with four pressure iterations,
+    and the largest field difference of the two steady states."""
+    import numpy as np
+    h = 1.0 / (N - 1)
+    out, states = {"grid": N, "res_tol": tol}, {}
+    for K in (1, 4):
+        s = hosc.Solver(hosc.params(N, Ra=1e4, n_pl=1.0, Pr=1.0, dt=0.4 * h * h, solve_rtol=1e-11, p_iters=K),
+                        device="cuda:0")
+        s.init_fields(1, 1e-3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while True:
+            info = s.run_to_steady(tol, 5000)
+            if max(info.res) < tol or info.step >= 100000:
+                break
+        torch.cuda.synchronize()
+        out[f"p_iters_{K}"] = {"steps": info.step, "seconds": time.perf_counter() - t0,
+                               "nu_mean_hot": s.diagnostics(arrays=False)["nu_mean_hot"]}
+        states[K] = s.get_state()
+        s.close()
+    out["max_rel_field_diff"] = max(float(np.max(np.abs(states[1][f] - states[4][f])) / np.max(np.abs(states[1][f])))
+                                    for f in ("u", "v", "w", "T"))
+    return out
 
 
 def precision_check(hosc, W, kw, reset, steps):
@@ -349,6 +387,8 @@ def main():
               precision=W["precision"])
     if args.omega is not None:
         kw["omega"] = args.omega
+    if W.get("p_iters"):
+        kw["p_iters"] = W["p_iters"]
     start = None
     if W.get("newtonian_start"):
         w = hosc.Solver(hosc.params(W["N"], **dict(kw, n_pl=1.0, precision=0)), device="cuda:0")
@@ -384,6 +424,7 @@ def main():
     torch.cuda.synchronize()
     el = 0.0
     sweeps = [0, 0, 0, 0]
+    corrections = 0
     t0 = time.perf_counter()
     for _ in range(args.steps):
         if in_segment == args.segment:
@@ -399,6 +440,7 @@ def main():
         sweeps[1] += info.sweeps[1]
         sweeps[2] += info.bicg_iters[0]
         sweeps[3] += info.bicg_iters[1]
+        corrections += info.corrected
         print(f"step {info.step}: sweeps {info.sweeps} bicg {info.bicg_iters} omega "
               f"{info.omega[0]:.3f}/{info.omega[1]:.3f} dominance {info.dominance[0]:.3f}/{info.dominance[1]:.3f} "
               f"res {max(info.res):.3e}",
@@ -431,7 +473,8 @@ def main():
         "config": {"workload": f"{W['label']}; steps 1-{args.segment} from the start state, repeated",
                    "grid": W["N"], "interior_nodes": M3, "precision": args.workload, "segment_steps": args.segment,
                    "mean_sor_sweeps_per_step": [sweeps[0] / args.steps, sweeps[1] / args.steps],
-                   "mean_bicgstab_iters_per_step": [sweeps[2] / args.steps, sweeps[3] / args.steps]},
+                   "mean_bicgstab_iters_per_step": [sweeps[2] / args.steps, sweeps[3] / args.steps],
+                   "p_iters": W.get("p_iters", 1), "mean_pressure_corrections_per_step": corrections / args.steps},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": sweep_traffic() if kind == "sweep" and args.workload == "fp64" else None,
@@ -446,6 +489,8 @@ def main():
     s.close()
     if W["precision"] != 0:
         out["precision_check"] = precision_check(hosc, W, kw, reset, args.segment)
+    if W.get("p_iters"):
+        out["steady_comparison"] = steady_comparison(hosc, torch)
     out["roofline"]["copy_probe_GBs"] = hosc.copy_bandwidth(1 << 30, 10)
     if not args.no_cpu_baseline and args.workload == "fp64":
         out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
