@@ -623,15 +623,17 @@ void sor_seed(hosc_solver *s, SorCtl &c, const double *dom)
         const double mu = std::min(0.98, dom[grp]);
         if (!(mu > 0.0 && std::isfinite(mu))) continue;
         const double w = 2.0 / (1.0 + std::sqrt(1.0 - mu * mu));
+        // sweeps the new relaxation needs from a unit residual (contraction w - 1)
+        const int pred = w > 1.0 ? (int)std::ceil(std::log(c.rtol) / std::log(w - 1.0)) : c.plan[grp];
         if (s->step == 0) {
             s->om[grp] = w;
+            if (s->P.check_every == 0) c.plan[grp] = std::max(c.plan[grp], std::min(256, pred));
         } else if (w < s->om[grp]) {
-            if (s->om[grp] - w > 0.05 && s->P.check_every == 0) {
-                c.plan[grp] = std::max(2, c.plan[grp] / 2);
-                c.first_plan[grp] = c.plan[grp];
-            }
+            if (s->om[grp] - w > 0.05 && s->P.check_every == 0)
+                c.plan[grp] = std::max(2, std::min(c.plan[grp] / 2, pred));
             s->om[grp] = w;
         }
+        c.first_plan[grp] = c.plan[grp];
     }
 }
 
@@ -746,6 +748,10 @@ hosc_status sor_decide(hosc_solver *s, SorCtl &c, const double *hb, double bn2[4
         int next = std::max(2, std::min(done, 64));
         if (rate > 0.0 && rate < 1.0)
             next = (int)std::min(256.0, std::max(2.0, std::ceil(std::log(rtol / worst) / std::log(rate)) + 1.0));
+        // at most double the sweeps of this solve: the contraction of a short batch
+        // still carries the start-up transient (over-relaxed red-black SOR decays
+        // like k (w-1)^k before it settles) and overstates what is left
+        if (!c.inner) next = std::min(next, std::max(4, done));
         c.plan[grp] = s->P.check_every > 0 ? s->P.check_every : next;
         c.plan[grp] = std::min(c.plan[grp], std::max(1, s->P.solve_maxit - done));
     }
