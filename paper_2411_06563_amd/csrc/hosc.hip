@@ -68,6 +68,7 @@ Geo make_geo(int N)
     g.inv3h = 1.0 / (3.0 * g.h);
     g.inv12h = 1.0 / (12.0 * g.h);
     g.inv6h2 = 1.0 / (6.0 * g.h2);
+    g.invN = 1.0 / N;
     g.n3 = (size_t)N * N * N;
     g.cs = (size_t)N * N * g.H;
     return g;
@@ -77,8 +78,8 @@ Launch make_launch(const Geo &g)
 {
     Launch L;
     const int N = g.N, M = N - 2;
-    L.blk_all = dim3(64, 4, 1);
-    L.grd_all = dim3((N + 63) / 64, (N + 3) / 4, N);
+    L.blk_all = dim3(256, 1, 1);
+    L.grd_all = dim3((unsigned)((g.n3 + 255) / 256), 1, 1);
     L.blk_int = dim3(64, 4, 1);
     L.grd_int = dim3((M + 63) / 64, (M + 3) / 4, M);
     int bx = 64;

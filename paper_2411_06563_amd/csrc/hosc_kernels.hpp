@@ -28,6 +28,7 @@ struct Geo {
     int Q;          // colour-row entries that can hold interior nodes
     int pad;
     double h, h2, inv2h, invh2;
+    double invN;            // 1/N (node index arithmetic of the all-node launches)
     double h2_12, inv3h, inv12h, inv6h2;   // h^2/12, 1/(3h), 1/(12h), 1/(6h^2) (uniform grid: h = k = l)
     size_t n3;      // N^3
     size_t cs;      // entries of one colour array (N*N*H)
@@ -210,6 +211,22 @@ __device__ __forceinline__ Tile xcd_tile()
     return t;
 }
 
+// Node of a thread in a launch over every node: one thread per node in storage
+// order (x fastest), 256-thread blocks of a 1D grid taken in XCD-grouped order, so
+// no wave idles on the partial x-rows a 2D tiling leaves when N is not a multiple
+// of 64.  False past the last node.  (n + 1/2)/N lies at least 1/(2N) from an
+// integer, far above the FP64 rounding of the product, so the quotients are exact.
+__device__ __forceinline__ bool all_node(const Geo &g, const Tile &tl, int &i, int &j, int &k)
+{
+    const int n = tl.id * (int)blockDim.x + (int)threadIdx.x;
+    if ((size_t)n >= g.n3) return false;
+    const int row = (int)(((double)n + 0.5) * g.invN);
+    k = (int)(((double)row + 0.5) * g.invN);
+    j = row - k * g.N;
+    i = n - row * g.N;
+    return true;
+}
+
 // ---------------------------------------------------------------------------
 // Derivatives at any node: central inside, 2nd-order one-sided on a wall normal to
 // the axis (velocity, eta, theta); the wall-normal pressure derivative is zero.
@@ -259,8 +276,8 @@ __global__ void __launch_bounds__(256) k_eta(Geo g, Phys P, const double *__rest
                                              const double *__restrict__ w, double *__restrict__ eta)
 {
     const Tile tl = xcd_tile();
-    const int i = tl.x * blockDim.x + threadIdx.x, j = tl.y * blockDim.y + threadIdx.y, k = tl.z;
-    if (i >= g.N || j >= g.N) return;
+    int i, j, k;
+    if (!all_node(g, tl, i, j, k)) return;
     const VelGrad d = vel_grad(g, u, v, w, i, j, k);
     eta[nid(g, i, j, k)] = pow(fmax(strain_I2(d), P.i2_floor), P.ex);
 }
@@ -275,8 +292,8 @@ __global__ void __launch_bounds__(256) k_estar(Geo g, Phys P, const double *__re
                                                double *__restrict__ Ev, double *__restrict__ Ew)
 {
     const Tile tl = xcd_tile();
-    const int i = tl.x * blockDim.x + threadIdx.x, j = tl.y * blockDim.y + threadIdx.y, k = tl.z;
-    if (i >= g.N || j >= g.N) return;
+    int i, j, k;
+    if (!all_node(g, tl, i, j, k)) return;
     const size_t c = nid(g, i, j, k), sy = (size_t)g.N, sz = (size_t)g.N * g.N;
     const VelGrad d = vel_grad(g, u, v, w, i, j, k);
     const double ex = dnode(eta, c, 1, i, g.N, g.inv2h), ey = dnode(eta, c, sy, j, g.N, g.inv2h),
@@ -1369,9 +1386,9 @@ __global__ void __launch_bounds__(256) k_entropy(Geo g, Phys P, const double *__
                                                  double *__restrict__ eta_out, double *__restrict__ partial)
 {
     const Tile tl = xcd_tile();
-    const int i = tl.x * blockDim.x + threadIdx.x, j = tl.y * blockDim.y + threadIdx.y, k = tl.z;
+    int i, j, k;
     double acc[3] = {0.0, 0.0, 0.0};
-    if (i < g.N && j < g.N) {
+    if (all_node(g, tl, i, j, k)) {
         const size_t c = nid(g, i, j, k), sy = (size_t)g.N, sz = (size_t)g.N * g.N;
         const double tx = dnode(T, c, 1, i, g.N, g.inv2h), ty = dnode(T, c, sy, j, g.N, g.inv2h),
                      tz = dnode(T, c, sz, k, g.N, g.inv2h);
