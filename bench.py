@@ -352,7 +352,64 @@ def bench_serve(args, W, hosc, torch):
                    "cell_updates_per_busy_s": cell_updates / max(st["busy_s"], 1e-9)},
         "mix_vs_alone": {"sampled": len(sample), "bitwise_equal": same},
     }
+    if args.capacity > 0:
+        out["capacity"] = serve_capacity(hosc, W, trace, min(args.capacity, nreq), args.capacity_rtol)
     print(json.dumps(out), flush=True)
+
+
+def serve_capacity(hosc, W, trace, k, rtol=None):
+    """Capacity on a saturated queue: the first k requests of the trace submitted at
+    once, (a) through the server (continuous fused batching, FP32 refined and FP64),
+    (b) through the plain path: one FP64 single-cavity solver after another.  Each
+    request runs to res_tol or max_steps as in the replay.  Reports solves/s (ok
+    solves / wall time) and p50/p99 of completion time."""
+    import numpy as np
+    rtol = W["solve_rtol"] if rtol is None else rtol
+    out = {"requests": k, "solve_rtol": rtol}
+
+    def plist(prec):
+        return [hosc.params(r["N"], Ra=r["Ra"], n_pl=r["n_pl"], Pr=r["Pr"], dt=W["dt_over_h2"] / (r["N"] - 1) ** 2,
+                            solve_rtol=rtol, precision=prec) for r in trace[:k]]
+
+    for name, prec in (("served_fp32_refined", 1), ("served_fp64", 0)):
+        pl = plist(prec)
+        srv = hosc.Server(W["budget"], max_resident=W["max_resident"])
+        t0 = srv.now()
+        ids = {srv.submit(pl[i], trace[i]["seed"], W["noise"], W["res_tol"], W["max_steps"], t0): i for i in range(k)}
+        res = {}
+        while len(res) < k:
+            srv.step()
+            for r in srv.poll():
+                res[ids[r["id"]]] = r
+        wall = max(r["t_done"] for r in res.values()) - t0
+        srv.close()
+        ok = [i for i in range(k) if res[i]["status"] == 0]
+        done = np.array([res[i]["t_done"] - t0 for i in ok])
+        out[name] = {"solves_per_s": len(ok) / wall, "wall_s": wall, "ok": len(ok),
+                     "p50_s": float(np.percentile(done, 50)), "p99_s": float(np.percentile(done, 99))}
+        print(f"capacity {name}: {out[name]}", file=sys.stderr, flush=True)
+    pl = plist(0)
+    torch_sync = __import__("torch").cuda.synchronize
+    torch_sync()
+    t0 = time.perf_counter()
+    done, ok = [], 0
+    for i in range(k):
+        s = hosc.Solver(pl[i])
+        s.init_fields(trace[i]["seed"], W["noise"])
+        try:
+            s.run_to_steady(W["res_tol"], W["max_steps"])
+            s.diagnostics(arrays=False)
+            ok += 1
+            torch_sync()
+            done.append(time.perf_counter() - t0)
+        except hosc.HoscError:
+            pass
+        s.close()
+    wall = time.perf_counter() - t0
+    out["plain_fp64_sequential"] = {"solves_per_s": ok / wall, "wall_s": wall, "ok": ok,
+                                    "p50_s": float(np.percentile(done, 50)), "p99_s": float(np.percentile(done, 99))}
+    print(f"capacity plain: {out['plain_fp64_sequential']}", file=sys.stderr, flush=True)
+    return out
 
 
 def main():
@@ -366,6 +423,10 @@ def main():
     ap.add_argument("--omega", type=float, default=None)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="fp64")
     ap.add_argument("--requests", type=int, default=None)
+    ap.add_argument("--capacity", type=int, default=40,
+                    help="serve: requests of the saturated-queue comparison (0 = skip)")
+    ap.add_argument("--capacity-rtol", type=float, default=None,
+                    help="serve: implicit-solve tolerance of the saturated-queue comparison (default: the workload's)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the HOSC hot path is measured on one MI355X "

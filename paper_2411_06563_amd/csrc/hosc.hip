@@ -851,7 +851,7 @@ hosc_status bicg_phase(hosc_solver *s, int phase, int mask, double st, const Bic
     k_bicg<TR, double, double><<<s->L.grd_bc, s->L.blk_sw, 0, s->st>>>(s->g, phase, mask, st, a, s->bsc, s->partR);
     r = timed_end(s, 2, bicg_bytes(s->g, phase, mask));
     if (r) return r;
-    k_bicg_scalars<<<1, 256, 0, s->st>>>(phase, mask, s->partR, (int)s->L.nb_bc, s->bsc);
+    k_bicg_scalars<<<1, 1024, 0, s->st>>>(phase, mask, s->partR, (int)s->L.nb_bc, s->bsc);
     return launch_check(s, "bicgstab");
 }
 

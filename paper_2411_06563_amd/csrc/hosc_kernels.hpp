@@ -120,16 +120,42 @@ __device__ __forceinline__ void block_max_store(double (&v)[NV], double *out)
 // block of 1024 threads; op 0 = sum, 1 = max.  Thread t folds records t, t+1024, ...
 // in order, then a fixed shuffle tree inside each wavefront and a fixed-order pass
 // over the 16 wavefronts: deterministic.
+// Thread t folds records t, t + 1024, ... of every component (all NC loads of a
+// record issued together, no guard between them); per component the order is
+// that of a component-by-component pass.
+template <int NC>
+__device__ __forceinline__ void fold_records(const double *part, int nb, int op, double (&acc)[8])
+{
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = op == 0 ? 0.0 : -HUGE_VAL;
+    for (int b = threadIdx.x; b < nb; b += 1024) {
+        double x[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) x[c] = part[(size_t)b * NC + c];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] = op == 0 ? acc[c] + x[c] : nanmax(acc[c], x[c]);
+    }
+}
+
 __device__ __forceinline__ void reduce_block(const double *part, int nb, int nc, int op, double *out)
 {
     __shared__ double sh[8][16];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    for (int c = 0; c < nc; ++c) {
-        double s = op == 0 ? 0.0 : -HUGE_VAL;
-        for (int b = t; b < nb; b += 1024) {
-            const double x = part[(size_t)b * nc + c];
-            s = op == 0 ? s + x : nanmax(s, x);
-        }
+    double acc[8];
+    switch (nc) {
+    case 1: fold_records<1>(part, nb, op, acc); break;
+    case 2: fold_records<2>(part, nb, op, acc); break;
+    case 3: fold_records<3>(part, nb, op, acc); break;
+    case 4: fold_records<4>(part, nb, op, acc); break;
+    case 5: fold_records<5>(part, nb, op, acc); break;
+    case 6: fold_records<6>(part, nb, op, acc); break;
+    case 7: fold_records<7>(part, nb, op, acc); break;
+    default: fold_records<8>(part, nb, op, acc); break;    // nc <= 8 (the size of sh)
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        if (c >= nc) break;
+        double s = acc[c];
         for (int off = 32; off > 0; off >>= 1) {
             const double y = __shfl_down(s, off, 64);
             s = op == 0 ? s + y : nanmax(s, y);
@@ -929,27 +955,31 @@ __global__ void __launch_bounds__(256) k_bicg(Geo g, int phase, int mask, TA st,
 
 // Reduce the partial records (8 values each) of one BiCGSTAB phase in fixed order
 // and update the scalars of the active systems (one block of 256 threads).
-__global__ void __launch_bounds__(256) k_bicg_scalars(int phase, int mask, const double *__restrict__ part, int nb,
-                                                      double *__restrict__ sc)
+__global__ void __launch_bounds__(1024) k_bicg_scalars(int phase, int mask, const double *__restrict__ part, int nb,
+                                                       double *__restrict__ sc)
 {
-    __shared__ double sh[8][256];
-    const int t = threadIdx.x;
+    __shared__ double sh[8][16];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    double acc[8];
+    fold_records<8>(part, nb, 0, acc);
+#pragma unroll
     for (int c = 0; c < 8; ++c) {
-        double s = 0.0;
-        for (int b = t; b < nb; b += 256) s += part[(size_t)b * 8 + c];
-        sh[c][t] = s;
+        double s = acc[c];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+        if (lane == 0) sh[c][wave] = s;
     }
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (t < w)
-            for (int c = 0; c < 8; ++c) sh[c][t] += sh[c][t + w];
-        __syncthreads();
-    }
     if (t != 0) return;
+    double tot[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        tot[c] = sh[c][0];
+        for (int w = 1; w < 16; ++w) tot[c] += sh[c][w];
+    }
     for (int f = 0; f < 4; ++f) {
         if (!((f < 3) ? (mask & 1) : (mask & 2))) continue;
         double *S = sc + 8 * f;
-        const double a = sh[2 * f][0], b = sh[2 * f + 1][0];
+        const double a = tot[2 * f], b = tot[2 * f + 1];
         if (phase == 0) {
             S[0] = a; S[1] = 0.0; S[2] = 1.0; S[3] = 0.0; S[4] = b; S[5] = 0.0;
         } else if (phase == 1) {
