@@ -48,7 +48,8 @@ typedef enum {
     HOSC_E_ARG = -1,        /* invalid argument or parameter */
     HOSC_E_NOMEM = -2,      /* workspace too small */
     HOSC_E_DEVICE = -3,     /* a HIP call failed */
-    HOSC_E_NOCONV = -4,     /* an implicit solve hit solve_maxit sweeps */
+    HOSC_E_NOCONV = -4,     /* an implicit solve hit solve_maxit sweeps or iterations, or BiCGSTAB's
+                               residual did not halve within 400 iterations */
     HOSC_E_NONFINITE = -5,  /* a residual or divergence became NaN/Inf */
     HOSC_E_STATE = -6,      /* handle in a sticky error state / no state set */
     HOSC_E_BUDGET = -7      /* (server) one request exceeds the whole budget */
@@ -82,7 +83,7 @@ typedef struct hosc_params {
     double lambda;          /* artificial-compressibility relaxation; 0 -> h^2/(3 dt) */
     double div_tol;         /* correct p when max|div v| > div_tol (default 0: every step) */
     double solve_rtol;      /* stop a solve when ||r|| <= solve_rtol ||b|| (diagonally scaled 2-norms), default 1e-10 */
-    int32_t solve_maxit;    /* cap on red-black sweeps per solve (default 4000) */
+    int32_t solve_maxit;    /* cap on red-black sweeps (or BiCGSTAB iterations) per solve (default 4000) */
     int32_t check_every;    /* sweeps between convergence checks; 0 -> adaptive */
     int32_t solver;         /* hosc_solver_kind (default HOSC_SOLVER_AUTO) */
     int32_t p_iters;        /* pressure iterations (Sec. 2.2): momentum solves per step at most.

@@ -889,6 +889,11 @@ hosc_status run_bicg(hosc_solver *s, int mask, double bn2[4], SolveOut &o, BicgA
     if (r) return r;
     int m = std::max(2, std::max(s->last_bicg[0], s->last_bicg[1]) / 2);
     if (s->P.check_every > 0) m = s->P.check_every;
+    // stall guard: a group whose recursive residual has not halved within
+    // kBicgStall iterations is reported unconverged at once instead of at solve_maxit
+    constexpr int kBicgStall = 400;
+    double best[2] = {HUGE_VAL, HUGE_VAL};
+    int best_at[2] = {0, 0};
     while (active) {
         for (int q = 0; q < m; ++q) {
             for (int ph = 1; ph <= 3; ++ph) {
@@ -913,11 +918,20 @@ hosc_status run_bicg(hosc_solver *s, int mask, double bn2[4], SolveOut &o, BicgA
             if (!(active & (1 << grp))) continue;
             const int f0 = grp == 0 ? 0 : 3, f1 = grp == 0 ? 3 : 4;
             bool small = true, broke = false;
+            double worst = 0.0;
             for (int f = f0; f < f1; ++f) {
                 const double *S = s->hbuf + 8 * f;
                 if (!std::isfinite(S[4])) return fail(s, HOSC_E_NONFINITE, "non-finite residual in BiCGSTAB");
                 if (S[5] != 0.0) broke = true;
                 if (!(bn2[f] == 0.0 || std::sqrt(S[4]) <= rtol * std::sqrt(bn2[f]))) small = false;
+                if (bn2[f] > 0.0) worst = std::max(worst, std::sqrt(S[4] / bn2[f]));
+            }
+            if (worst < 0.5 * best[grp]) {
+                best[grp] = worst;
+                best_at[grp] = o.bicg[grp];
+            } else if (!small && !broke && o.bicg[grp] - best_at[grp] >= kBicgStall) {
+                return fail(s, HOSC_E_NOCONV, "BiCGSTAB stalled: the residual did not halve in " +
+                                                  std::to_string(kBicgStall) + " iterations");
             }
             if (small || broke) recheck |= 1 << grp;
         }
