@@ -92,8 +92,8 @@ typedef struct hosc_params {
                                than p_iters solves were made, the momentum sources are re-formed
                                from level n with the corrected pressure and the momentum increments
                                solved again.  0 or 1: one solve and at most one correction per step
-                               (default 1); at most 64.  Single-cavity solvers only: batches and the
-                               server refuse p_iters > 1 with HOSC_E_ARG. */
+                               (default 1); at most 64.  In batches and the server the re-solves of a
+                               cavity run as single-cavity launches after the fused solve. */
     double omega;           /* SOR relaxation of the red-black sweeps: 0 = adaptive per system (default),
                                else fixed in (0, 2) */
     double i2_floor;        /* eta = max(I2, i2_floor)^((n-1)/2), default 1e-8 */

@@ -1715,7 +1715,8 @@ hosc_status fused_step(Fused &F, hosc_solver *const *cav, int n, hosc_step_info 
 {
     std::vector<SolveOut> o(n);
     std::vector<double> bn2(4 * (size_t)n, -1.0);
-    std::vector<int> sor(n), bic(n), failed(n), act(n);
+    std::vector<int> sor(n), bic(n), failed(n), act(n), first(n);
+    for (int i = 0; i < n; ++i) first[i] = cav[i]->first;
     std::vector<double> rtol(n);
     // the pre- and post-solve phases of steady-going batches run as captured graphs
     bool graphed = F.use_graphs && n <= 64;
@@ -1753,6 +1754,9 @@ hosc_status fused_step(Fused &F, hosc_solver *const *cav, int n, hosc_step_info 
     for (int i = 0; i < n; ++i) {
         if (err[i]) continue;
         err[i] = solve_finish(cav[i], failed[i], bic[i], b4[i], o[i]);
+        // pressure iterations with the single-cavity solves (the same control as the
+        // fused ones, so results stay those of the cavity alone)
+        if (!err[i]) err[i] = pressure_iterations(cav[i], first[i], o[i]);
         if (err[i]) continue;
         act[nact++] = i;
     }
@@ -2392,9 +2396,6 @@ hosc_status hosc_batch_create(const hosc_params *p, int32_t count, void *d_ws, s
     for (int i = 1; i < count; ++i)
         if (p[i].precision != p[0].precision)
             return bfail(nullptr, HOSC_E_ARG, "all cavities of a batch must use one precision");
-    for (int i = 0; i < count; ++i)
-        if (p[i].p_iters > 1)
-            return bfail(nullptr, HOSC_E_ARG, "cavity " + std::to_string(i) + ": p_iters > 1 needs a single-cavity solver");
     if (!d_ws) return bfail(nullptr, HOSC_E_ARG, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return bfail(nullptr, HOSC_E_ARG, "workspace must be 256-byte aligned");
     if (ws_bytes < need) return bfail(nullptr, HOSC_E_NOMEM, "workspace smaller than hosc_batch_workspace_bytes()");
@@ -2577,7 +2578,6 @@ hosc_status hosc_server_submit(hosc_server *v, const hosc_request *rq, uint64_t 
     if (!v || !rq) return HOSC_E_ARG;
     const char *e = check_params(&rq->params);
     if (e) return sfail(v, HOSC_E_ARG, e);
-    if (rq->params.p_iters > 1) return sfail(v, HOSC_E_ARG, "p_iters > 1 needs a single-cavity solver");
     if (!(rq->res_tol > 0.0) || rq->max_steps < 1) return sfail(v, HOSC_E_ARG, "res_tol > 0 and max_steps >= 1 required");
     if (!std::isfinite(rq->noise_amp)) return sfail(v, HOSC_E_ARG, "noise_amp must be finite");
     size_t bytes = 0;

@@ -107,15 +107,45 @@ def test_single_iteration_unchanged(hosc):
         assert np.array_equal(out[0][0][f], out[1][0][f]), f
 
 
-def test_batch_and_server_refuse_pressure_iterations(hosc):
-    p = hosc.params(17, p_iters=2)
-    with pytest.raises(hosc.HoscError) as e:
-        hosc.Batch([hosc.params(17), p])
-    assert "p_iters" in str(e.value)
-    srv = hosc.Server(1 << 28, max_resident=2)
-    with pytest.raises(hosc.HoscError) as e:
-        srv.submit(p, 1)
-    assert "p_iters" in str(e.value)
+def test_batch_and_server_with_pressure_iterations(hosc):
+    """Batched and served cavities with pressure iterations give their single-cavity
+    results bitwise (the re-solves use the single-cavity control the fused solves
+    share)."""
+    plist = [hosc.params(17, Ra=1e3, n_pl=1.0, dt=1e-3, p_iters=3, solve_rtol=1e-11),
+             hosc.params(18, Ra=1e4, n_pl=0.75, dt=5e-4, p_iters=1, solve_rtol=1e-11),
+             hosc.params(13, Ra=1e4, n_pl=1.25, dt=1e-3, p_iters=2, div_tol=5.0, solve_rtol=1e-11)]
+    seeds = [21, 22, 23]
+    steps = 6
+    solo = []
+    for p, sd in zip(plist, seeds):
+        s = hosc.Solver(p)
+        s.init_fields(sd, 1e-3)
+        infos = [s.step(1) for _ in range(steps)]
+        solo.append((s.get_state(), s.diagnostics(arrays=False), [i.corrected for i in infos]))
+        s.close()
+    b = hosc.Batch(plist)
+    b.init_fields(seeds)
+    binfo = [b.step(1) for _ in range(steps)]
+    for i in range(len(plist)):
+        g = b.cavities[i].get_state()
+        say(f"[p-iter] batch cavity {i}: corrections {[bi[i].corrected for bi in binfo]} solo {solo[i][2]}")
+        assert [bi[i].corrected for bi in binfo] == solo[i][2]
+        for f in ("u", "v", "w", "T", "p"):
+            assert np.array_equal(g[f], solo[i][0][f]), (i, f)
+        assert b.cavities[i].diagnostics(arrays=False) == solo[i][1]
+    b.close()
+    srv = hosc.Server(1 << 28, max_resident=4)
+    ids = {srv.submit(p, sd, res_tol=1e-30, max_steps=steps): i for i, (p, sd) in enumerate(zip(plist, seeds))}
+    res = {}
+    for _ in range(50):
+        srv.step()
+        for r in srv.poll():
+            res[ids[r["id"]]] = r
+        if len(res) == len(plist):
+            break
     srv.close()
+    for i in range(len(plist)):
+        assert res[i]["status"] == 0 and res[i]["steps"] == steps
+        assert res[i]["diag"] == solo[i][1], i
     with pytest.raises(hosc.HoscError):
         hosc.Solver(hosc.params(17, p_iters=65))
