@@ -388,9 +388,9 @@ def serve_capacity(hosc, W, trace, k, rtol=None):
         out[name] = {"solves_per_s": len(ok) / wall, "wall_s": wall, "ok": len(ok),
                      "p50_s": float(np.percentile(done, 50)), "p99_s": float(np.percentile(done, 99))}
         print(f"capacity {name}: {out[name]}", file=sys.stderr, flush=True)
+    import torch
     pl = plist(0)
-    torch_sync = __import__("torch").cuda.synchronize
-    torch_sync()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     done, ok = [], 0
     for i in range(k):
@@ -400,7 +400,7 @@ def serve_capacity(hosc, W, trace, k, rtol=None):
             s.run_to_steady(W["res_tol"], W["max_steps"])
             s.diagnostics(arrays=False)
             ok += 1
-            torch_sync()
+            torch.cuda.synchronize()
             done.append(time.perf_counter() - t0)
         except hosc.HoscError:
             pass
