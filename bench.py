@@ -17,6 +17,13 @@ three run).  After the timed run it also marches a Newtonian 41^3 cavity (Ra = 1
 Pr = 1, dt = 0.4 h^2) to a per-step residual of 2.5e-12 with one and with four
 pressure iterations and reports steps and seconds of each.
 
+`--workload serve` replays the seeded Poisson trace in real time against the
+server (completed solves/s, p50/p99 latency, a mix-vs-alone check) and then
+compares, on a saturated queue of its first 40 requests, the server (FP32 refined
+and FP64) with the plain path of one FP64 single-cavity solver after another.
+`--workload batch12` advances the 12-cavity batch with fused launches and compares
+it with the same steps cavity by cavity.
+
 `--workload fp32r` is the precision form (n = 1.25, Ra = 1e4, FP32 rows and inner
 sweeps with FP64 residuals and refinement).  Shear-thickening flow cannot start
 from rest under the stated scheme (the second step's rows lose their centre), so
