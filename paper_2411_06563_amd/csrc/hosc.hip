@@ -1375,6 +1375,10 @@ struct Fused {
     bool prof = false;
     hipEvent_t ev[2] = {nullptr, nullptr};
     hosc_perf perf{};
+    // side streams (default priority) for the per-cavity phases, and their events
+    static constexpr int kSide = 4;
+    hipStream_t side[kSide] = {};
+    hipEvent_t fork = nullptr, join[kSide] = {};
     TileMap *hmap() { return reinterpret_cast<TileMap *>(h_tab); }
     template <typename T> T *hcav() { return reinterpret_cast<T *>(h_tab + off_cav); }
     ReduceJob *hjobs() { return reinterpret_cast<ReduceJob *>(h_tab + off_jobs); }
@@ -1427,6 +1431,13 @@ hosc_status fused_init(Fused &F, int cap, char *d_dev, hipStream_t st)
     std::memset(F.h_tab, 0, F.tab_bytes);
     FHIPCHK(F, hipEventCreate(&F.ev[0]));
     FHIPCHK(F, hipEventCreate(&F.ev[1]));
+    if (st != nullptr) {
+        FHIPCHK(F, hipEventCreateWithFlags(&F.fork, hipEventDisableTiming));
+        for (int q = 0; q < Fused::kSide; ++q) {
+            FHIPCHK(F, hipStreamCreateWithFlags(&F.side[q], hipStreamNonBlocking));
+            FHIPCHK(F, hipEventCreateWithFlags(&F.join[q], hipEventDisableTiming));
+        }
+    }
     return HOSC_OK;
 }
 void fused_free(Fused &F)
@@ -1437,6 +1448,14 @@ void fused_free(Fused &F)
     if (F.h_gather) (void)hipHostFree(F.h_gather);
     for (hipEvent_t &e : F.ev)
         if (e) (void)hipEventDestroy(e);
+    for (int q = 0; q < Fused::kSide; ++q) {
+        if (F.side[q]) (void)hipStreamDestroy(F.side[q]);
+        if (F.join[q]) (void)hipEventDestroy(F.join[q]);
+        F.side[q] = nullptr;
+        F.join[q] = nullptr;
+    }
+    if (F.fork) (void)hipEventDestroy(F.fork);
+    F.fork = nullptr;
     F.h_tab = nullptr;
     F.h_gather = nullptr;
 }
@@ -1708,6 +1727,39 @@ hosc_status graph_run(Fused &F, int kind, uint64_t sig, Fn &&record)
     return HOSC_OK;
 }
 
+// Runs fn(i) for each cavity i with use[i] set, with that cavity's launches on side
+// stream i mod kSide: the phases of different cavities touch disjoint memory, so
+// they run concurrently; F.st then waits for every side stream.  Inside a capture
+// the side streams join it through the fork event (one graph branch per stream).
+// Without side streams (the null stream) the cavities run in order on their own.
+template <typename Fn>
+hosc_status fan_out(Fused &F, hosc_solver *const *cav, int n, const int *use, Fn &&fn)
+{
+    int m = 0;
+    for (int i = 0; i < n; ++i) m += use[i] != 0;
+    if (!F.side[0] || m < 2) {
+        for (int i = 0; i < n; ++i)
+            if (use[i]) fn(i);
+        return HOSC_OK;
+    }
+    const int ns = std::min(m, Fused::kSide);
+    FHIPCHK(F, hipEventRecord(F.fork, F.st));
+    for (int q = 0; q < ns; ++q) FHIPCHK(F, hipStreamWaitEvent(F.side[q], F.fork, 0));
+    for (int i = 0, k = 0; i < n; ++i) {
+        if (!use[i]) continue;
+        hosc_solver *s = cav[i];
+        const hipStream_t own = s->st;
+        s->st = F.side[k++ % ns];
+        fn(i);
+        s->st = own;
+    }
+    for (int q = 0; q < ns; ++q) {
+        FHIPCHK(F, hipEventRecord(F.join[q], F.side[q]));
+        FHIPCHK(F, hipStreamWaitEvent(F.st, F.join[q], 0));
+    }
+    return HOSC_OK;
+}
+
 // One step of every cavity in cav[0..n) (all of one precision).  Per-cavity
 // failures are returned in err[i] (and make that solver sticky, as hosc_step
 // does); the return value reports failures of the fused machinery itself.
@@ -1725,22 +1777,37 @@ hosc_status fused_step(Fused &F, hosc_solver *const *cav, int n, hosc_step_info 
         graphed = graphed && s->has_state && !s->sticky && !s->first && !s->prof;
     }
     const uint64_t sig = graphed ? parity_sig(cav, n) : 0;
+    std::vector<int> all(n, 1);
     if (graphed) {
         hosc_status r = graph_run(F, 0, sig, [&]() {
-            for (int i = 0; i < n; ++i) {
+            hosc_status first_err = HOSC_OK;
+            std::string msg;
+            hosc_status fr = fan_out(F, cav, n, all.data(), [&](int i) {
                 hosc_status q = pre_solve(cav[i]);
-                if (q) return ffail(F, q, "cavity " + std::to_string(i) + ": " + cav[i]->err);
-            }
-            return HOSC_OK;
+                if (q && !first_err) {
+                    first_err = q;
+                    msg = "cavity " + std::to_string(i) + ": " + cav[i]->err;
+                }
+            });
+            if (fr) return fr;
+            return first_err ? ffail(F, first_err, msg) : HOSC_OK;
         });
         if (r) return r;
     }
+    std::vector<int> go(n, 0);
     for (int i = 0; i < n; ++i) {
         err[i] = HOSC_OK;
         hosc_solver *s = cav[i];
         if (!s->has_state) err[i] = fail(s, HOSC_E_STATE, "no state set");
         else if (s->sticky) err[i] = fail(s, HOSC_E_STATE, "solver is in an error state; set a new state");
-        else if (!graphed) err[i] = pre_solve(s);
+        else go[i] = !graphed;
+    }
+    {
+        hosc_status r = fan_out(F, cav, n, go.data(), [&](int i) { err[i] = pre_solve(cav[i]); });
+        if (r) return r;
+    }
+    for (int i = 0; i < n; ++i) {
+        hosc_solver *s = cav[i];
         solve_masks(s, sor[i], bic[i]);
         rtol[i] = s->P.solve_rtol;
         if (err[i]) sor[i] = bic[i] = 0;
@@ -1772,10 +1839,17 @@ hosc_status fused_step(Fused &F, hosc_solver *const *cav, int n, hosc_step_info 
             FHIPCHK(F, hipMemcpyAsync(F.d_tab + F.off_src2, F.h_tab + F.off_src2, (size_t)n * sizeof(double *),
                                       hipMemcpyHostToDevice, F.st));
         r = graph_run(F, 1, sig, [&]() {
-            for (int i = 0; i < n; ++i) {
+            hosc_status first_err = HOSC_OK;
+            std::string msg;
+            hosc_status fr = fan_out(F, cav, n, all.data(), [&](int i) {
                 hosc_status q = post_launch(cav[i]);
-                if (q) return ffail(F, q, "cavity " + std::to_string(i) + ": " + cav[i]->err);
-            }
+                if (q && !first_err) {
+                    first_err = q;
+                    msg = "cavity " + std::to_string(i) + ": " + cav[i]->err;
+                }
+            });
+            if (fr) return fr;
+            if (first_err) return ffail(F, first_err, msg);
             k_gather<<<n, 64, 0, F.st>>>(F.dsrc2(), kPost, F.d_gather);
             return HOSC_OK;
         });
@@ -1784,10 +1858,13 @@ hosc_status fused_step(Fused &F, hosc_solver *const *cav, int n, hosc_step_info 
                                   F.st));
         FHIPCHK(F, wait_stream(F.st));
     } else if (nact) {
+        std::vector<int> post(n, 0);
+        for (int a = 0; a < nact; ++a) post[act[a]] = 1;
+        r = fan_out(F, cav, n, post.data(), [&](int i) { err[i] = post_launch(cav[i]); });
+        if (r) return r;
         int ng = 0;
         for (int a = 0; a < nact; ++a) {
             const int i = act[a];
-            err[i] = post_launch(cav[i]);
             if (!err[i]) {
                 F.hsrc()[ng] = cav[i]->red + 12;
                 act[ng++] = i;
