@@ -114,3 +114,29 @@ def test_batch_failure_is_isolated(hosc):
         gb = b.cavities[i].get_state()
         assert all(np.array_equal(gb[f], g[f]) for f in ("u", "v", "w", "T", "p")), i
     b.close()
+
+
+def test_batch_benchmark_sizes_bitwise_equal_to_solo(hosc):
+    """The batch benchmark's cavity sizes (97^3, 65^3, 33^3), FP32 refined, in the
+    benchmark's launch configuration (autotuned schedule, graph-captured phases on
+    side streams): four steps bitwise equal to each cavity alone."""
+    cases = [(97, 1e5, 1.0), (65, 1e3, 1.25), (33, 1e4, 0.75)]
+    plist = [hosc.params(N, Ra=Ra, n_pl=n, Pr=1.0, dt=max(5e-5, 0.2 / (N - 1) ** 2), precision=hosc.HOSC_FP32_REFINED,
+                         solve_rtol=1e-10) for (N, Ra, n) in cases]
+    seeds = [100, 101, 102]
+    b = hosc.Batch(plist)
+    b.init_fields(seeds)
+    grid = b.tune()
+    steps = 4
+    for _ in range(steps):
+        b.step(1)
+    say(f"[batch] benchmark sizes, tuned grid {grid}, graph launches {b.graph_launches()}")
+    assert b.graph_launches() == 2 * (steps - 1)
+    for i, p in enumerate(plist):
+        g, d, _ = _solo(hosc, p, seeds[i], steps)
+        gb = b.cavities[i].get_state()
+        worst = max(float(np.max(np.abs(gb[f] - g[f]))) for f in ("u", "v", "w", "T", "p"))
+        say(f"[batch] N={p.N}: max abs diff {worst:.3e}")
+        assert worst == 0.0, i
+        assert b.cavities[i].diagnostics(arrays=False) == d
+    b.close()
