@@ -98,6 +98,12 @@ typedef struct hosc_params {
                                else fixed in (0, 2) */
     double i2_floor;        /* eta = max(I2, i2_floor)^((n-1)/2), default 1e-8 */
     double phi;             /* irreversibility ratio of the fluid-friction entropy, default 1e-4 */
+    double eta_relax;       /* viscosity relaxation for steady-state marching (an addition to the
+                               paper's scheme): the viscosity of level n is r eta(v^n) + (1 - r) times
+                               that of level n-1, r = eta_relax in (0, 1].  1 (default) is the stated
+                               scheme; r < 1 damps the period-2 oscillation the lagged viscosity can
+                               sustain and leaves every steady state unchanged (a fixed point of
+                               both).  The first step after a state is set uses eta(v^n). */
 } hosc_params;
 
 /* Per-step report. */

@@ -49,6 +49,10 @@
  *       step.  Each re-solve starts from level n (never from the trial velocity).
  *   R26 at the first step (R11) the level n-1 sources follow each pressure iterate,
  *       so that their time difference stays zero in every solve of that step.
+ *   R27 optional viscosity relaxation for steady-state marching (not in the paper):
+ *       the viscosity of level n is r eta(v^n) + (1 - r) times that of level n-1
+ *       (level n-1 set, r < 1); r = 1 is the stated scheme.  A steady state is a
+ *       fixed point of both.
  *   R16 both sides solve in increment form B dchi = b, b = dt (R - A chi^n).
  *   R17 steady residual per field ||chi^{n+1}-chi^n||_2 / ||chi^{n+1}||_2 over all
  *       nodes.
@@ -76,6 +80,7 @@ typedef struct {
     double Ra, Pr, n_pl, dt;
     double theta_hot, theta_cold, theta_ref;
     double lambda, div_tol, i2_floor, phi, solve_tol;
+    double eta_relax;   /* weight r of the new viscosity (R27); 1: the stated scheme */
 } or_params;
 
 typedef struct {
@@ -662,11 +667,20 @@ static void coef_free(coef_store_t *cs)
     free(cs->Lmp); free(cs->Gmp); free(cs->Hmp); free(cs->Imp); free(cs->one);
 }
 
+/* Viscosity of level n: eta(v^n), relaxed towards level n-1 when asked (R27). */
+static void level_eta(const or_params *P, const or_state *S, double *eta)
+{
+    size_t n3 = (size_t)P->N * P->N * P->N;
+    or_eta_field(P, S->u, S->v, S->w, eta, NULL);
+    if (!S->first && P->eta_relax < 1.0)
+        for (size_t c = 0; c < n3; ++c) eta[c] = P->eta_relax * eta[c] + (1.0 - P->eta_relax) * S->etap[c];
+}
+
 /* Level-n viscosity and sources, and level n-1 set equal on the first step. */
 static void stage_sources(const or_params *P, or_state *S, double *eta, double *Eu, double *Ev, double *Ew)
 {
     size_t n3 = (size_t)P->N * P->N * P->N;
-    or_eta_field(P, S->u, S->v, S->w, eta, NULL);
+    level_eta(P, S, eta);
     or_estar_field(P, S->u, S->v, S->w, S->T, S->p, eta, Eu, Ev, Ew);
     if (S->first) {
         memcpy(S->up, S->u, n3 * sizeof(double));
@@ -718,7 +732,7 @@ int or_apply_B(const or_params *P, const or_state *S, int eq, const double *x, d
     int N = P->N;
     size_t n3 = (size_t)N * N * N;
     double *eta = malloc(n3 * sizeof(double));
-    or_eta_field(P, S->u, S->v, S->w, eta, NULL);
+    level_eta(P, S, eta);
     coef_store_t cs;
     coef_alloc(&cs, n3);
     coef_t Cm, Ct;

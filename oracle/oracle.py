@@ -29,7 +29,7 @@ class _Params(ctypes.Structure):
         ("Ra", ctypes.c_double), ("Pr", ctypes.c_double), ("n_pl", ctypes.c_double), ("dt", ctypes.c_double),
         ("theta_hot", ctypes.c_double), ("theta_cold", ctypes.c_double), ("theta_ref", ctypes.c_double),
         ("lam", ctypes.c_double), ("div_tol", ctypes.c_double), ("i2_floor", ctypes.c_double),
-        ("phi", ctypes.c_double), ("solve_tol", ctypes.c_double),
+        ("phi", ctypes.c_double), ("solve_tol", ctypes.c_double), ("eta_relax", ctypes.c_double),
     ]
 
 
@@ -100,6 +100,7 @@ class Params:
     maxit: int = 20000
     dense: bool = False
     p_iters: int = 1                   # momentum solves per step at most (pressure iterations)
+    eta_relax: float = 1.0             # weight of the new viscosity (1: the stated scheme)
 
     @property
     def h(self) -> float:
@@ -110,7 +111,7 @@ class Params:
         return _Params(N=self.N, maxit=self.maxit, dense=int(self.dense), p_iters=self.p_iters, Ra=self.Ra, Pr=self.Pr,
                        n_pl=self.n_pl, dt=self.dt, theta_hot=self.theta_hot, theta_cold=self.theta_cold,
                        theta_ref=self.theta_ref, lam=lam, div_tol=self.div_tol, i2_floor=self.i2_floor,
-                       phi=self.phi, solve_tol=self.solve_tol)
+                       phi=self.phi, solve_tol=self.solve_tol, eta_relax=self.eta_relax)
 
 
 @dataclass

@@ -140,6 +140,7 @@ const char *check_params(const hosc_params *p)
     if (p->p_iters < 0 || p->p_iters > 64) return "p_iters must be in [0, 64]";
     if (!(p->i2_floor > 0.0) || !std::isfinite(p->i2_floor)) return "i2_floor must be finite and > 0";
     if (!(p->phi >= 0.0) || !std::isfinite(p->phi)) return "phi must be finite and >= 0";
+    if (!(p->eta_relax > 0.0 && p->eta_relax <= 1.0)) return "eta_relax must be in (0, 1]";
     if (!std::isfinite(p->theta_hot) || !std::isfinite(p->theta_cold) || !std::isfinite(p->theta_ref))
         return "wall and reference temperatures must be finite";
     return nullptr;
@@ -1237,8 +1238,10 @@ hosc_status post_launch(hosc_solver *s)
     k_nu_local<<<g2, b2, 0, s->st>>>(g, s->T, s->nuh, s->nuc);
     k_nu_avg<<<g.N, 256, 0, s->st>>>(g, s->wq, s->nuh, s->nuc, s->avh, s->avc);
     k_nu_final<<<1, 1024, 0, s->st>>>(g, s->wq, s->avh, s->avc, s->nuh, s->red + 56);
+    const bool relax = s->P.eta_relax < 1.0;     // level n's viscosity is s->eta until the swap
     k_entropy<<<s->L.grd_all, s->L.blk_all, 0, s->st>>>(g, s->ph, s->wq, s->u2, s->v2, s->w2, s->T, nullptr, nullptr,
-                                                         s->etap, s->partB0);
+                                                         s->etap, s->partB0, relax ? s->eta : nullptr,
+                                                         s->P.eta_relax);
     Reductions()
         .add(s->partR, s->L.nb_int, 8, 0, s->red + 12)
         .add(s->partB, s->L.nb_face, 2, 0, s->red + 20)
@@ -2102,6 +2105,7 @@ hosc_status hosc_params_default(hosc_params *p)
     p->omega = 0.0;
     p->i2_floor = 1e-8;
     p->phi = 1e-4;
+    p->eta_relax = 1.0;
     return HOSC_OK;
 }
 

@@ -1408,12 +1408,14 @@ __global__ void __launch_bounds__(1024) k_nu_final(Geo g, const double *__restri
 // from the current velocity, E_local = E_HT + E_FF, Be_local = E_HT / E_local (1
 // where E_local = 0).  Partial Simpson-weighted sums of E_HT, E_FF and Be_local.
 // eta_out (optional) receives eta, computed exactly as k_eta computes it: run at
-// the end of a step on the new velocities, it supplies the next step's viscosity.
+// the end of a step on the new velocities, it supplies the next step's viscosity
+// (with eta_prev, relaxed: relax eta + (1 - relax) eta_prev).
 __global__ void __launch_bounds__(256) k_entropy(Geo g, Phys P, const double *__restrict__ wq,
                                                  const double *__restrict__ u, const double *__restrict__ v,
                                                  const double *__restrict__ w, const double *__restrict__ T,
                                                  double *__restrict__ el, double *__restrict__ bl,
-                                                 double *__restrict__ eta_out, double *__restrict__ partial)
+                                                 double *__restrict__ eta_out, double *__restrict__ partial,
+                                                 const double *__restrict__ eta_prev = nullptr, double relax = 1.0)
 {
     const Tile tl = xcd_tile();
     int i, j, k;
@@ -1426,7 +1428,7 @@ __global__ void __launch_bounds__(256) k_entropy(Geo g, Phys P, const double *__
         const VelGrad d = vel_grad(g, u, v, w, i, j, k);
         const double I2 = strain_I2(d);
         const double eta = pow(fmax(I2, P.i2_floor), P.ex);    // as k_eta computes it
-        if (eta_out) eta_out[c] = eta;
+        if (eta_out) eta_out[c] = eta_prev ? relax * eta + (1.0 - relax) * eta_prev[c] : eta;
         const double eff = P.phi * eta * I2;
         const double e = eht + eff;
         const double be = e > 0.0 ? eht / e : 1.0;

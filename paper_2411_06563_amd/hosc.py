@@ -42,7 +42,7 @@ class CParams(ctypes.Structure):
                 ("lam", ctypes.c_double), ("div_tol", ctypes.c_double), ("solve_rtol", ctypes.c_double),
                 ("solve_maxit", ctypes.c_int32), ("check_every", ctypes.c_int32), ("solver", ctypes.c_int32),
                 ("p_iters", ctypes.c_int32), ("omega", ctypes.c_double),
-                ("i2_floor", ctypes.c_double), ("phi", ctypes.c_double)]
+                ("i2_floor", ctypes.c_double), ("phi", ctypes.c_double), ("eta_relax", ctypes.c_double)]
 
 
 class CStepInfo(ctypes.Structure):
