@@ -361,6 +361,8 @@ def bench_serve(args, W, hosc, torch):
     }
     if args.capacity > 0:
         out["capacity"] = serve_capacity(hosc, W, trace, min(args.capacity, nreq), args.capacity_rtol)
+    if args.steady > 0:
+        out["time_to_steady"] = serve_steady(hosc, W, args.steady)
     print(json.dumps(out), flush=True)
 
 
@@ -419,6 +421,66 @@ def serve_capacity(hosc, W, trace, k, rtol=None):
     return out
 
 
+def steady_relax(n_pl: float) -> float:
+    """Viscosity relaxation used for marching to steady state: strong for shear-
+    thinning fluids (their lagged viscosity sustains a period-2 oscillation), mild
+    otherwise (a shear-thickening fluid must leave its low rest-state viscosity)."""
+    return 0.1 if n_pl < 1.0 else 0.5
+
+
+def serve_steady(hosc, W, k):
+    """Time to steady state: the first k requests of the trace with N <= 49 (the
+    larger cavities need 1e4-1e5 steps at the stable time steps), each marched to
+    res 1e-8 (at most 30000 steps) with the viscosity relaxation, submitted at once
+    to the server (FP32 refined), and the same requests through the plain path (one
+    FP64 single-cavity solver after another).  Reports steady solves, solves/s and
+    p50/p99 time to steady state."""
+    import numpy as np
+    import torch
+    from paper_2411_06563_amd.inputs import serving_trace
+    trace = [r for r in serving_trace(500, W["rate"], W["trace_seed"]) if r["N"] <= 49][:k]
+
+    def params(r, prec):
+        return hosc.params(r["N"], Ra=r["Ra"], n_pl=r["n_pl"], Pr=r["Pr"], dt=W["dt_over_h2"] / (r["N"] - 1) ** 2,
+                           solve_rtol=W["solve_rtol"], precision=prec, eta_relax=steady_relax(r["n_pl"]))
+
+    out = {"requests": k, "sizes": sorted({r["N"] for r in trace}), "res_tol": 1e-8, "max_steps": 30000}
+    srv = hosc.Server(W["budget"], max_resident=W["max_resident"])
+    t0 = srv.now()
+    ids = {srv.submit(params(r, W["precision"]), r["seed"], W["noise"], 1e-8, 30000, t0): i
+           for i, r in enumerate(trace)}
+    res = {}
+    while len(res) < k:
+        srv.step()
+        for q in srv.poll():
+            res[ids[q["id"]]] = q
+    srv.close()
+    done = [res[i]["t_done"] - t0 for i in range(k) if res[i]["status"] == 0 and res[i]["steady"]]
+    wall = max(q["t_done"] for q in res.values()) - t0
+    out["served_fp32_refined"] = {"steady": len(done), "wall_s": wall, "solves_per_s": len(done) / wall,
+                                  "p50_s": float(np.percentile(done, 50)), "p99_s": float(np.percentile(done, 99))}
+    print(f"steady served: {out['served_fp32_refined']}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = []
+    for r in trace:
+        sv = hosc.Solver(params(r, 0))
+        sv.init_fields(r["seed"], W["noise"])
+        try:
+            info = sv.run_to_steady(1e-8, 30000)
+            torch.cuda.synchronize()
+            if max(info.res) < 1e-8:
+                done.append(time.perf_counter() - t0)
+        except hosc.HoscError:
+            pass
+        sv.close()
+    wall = time.perf_counter() - t0
+    out["plain_fp64_sequential"] = {"steady": len(done), "wall_s": wall, "solves_per_s": len(done) / wall,
+                                    "p50_s": float(np.percentile(done, 50)), "p99_s": float(np.percentile(done, 99))}
+    print(f"steady plain: {out['plain_fp64_sequential']}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -432,6 +494,8 @@ def main():
     ap.add_argument("--requests", type=int, default=None)
     ap.add_argument("--capacity", type=int, default=40,
                     help="serve: requests of the saturated-queue comparison (0 = skip)")
+    ap.add_argument("--steady", type=int, default=24,
+                    help="serve: small requests marched to steady state, served and plain (0 = skip)")
     ap.add_argument("--capacity-rtol", type=float, default=None,
                     help="serve: implicit-solve tolerance of the saturated-queue comparison (default: the workload's)")
     args = ap.parse_args()
