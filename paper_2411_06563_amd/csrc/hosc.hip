@@ -1545,11 +1545,20 @@ hosc_status fused_sor(Fused &F, hosc_solver *const *cav, int n, const int *mask,
     }
     for (int i = 0; i < n; ++i)
         if (!err[i] && mask[i]) sor_skip(c[i], bn2[i]);
+    std::vector<int> order, len(n), upto(n + 1);
     for (;;) {
         int nact = 0, total = 0, nsw = 0, nj = 0;
         double bytes = 0.0;
-        for (int i = 0; i < n; ++i) {
-            if (err[i] || !c[i].active) continue;
+        // cavities still iterating, the longest batch first: the cavities sweep q
+        // reaches are then a prefix of the table, and each launch covers only
+        // their tiles (a tile's work does not depend on where it sits in the list)
+        order.clear();
+        for (int i = 0; i < n; ++i)
+            if (!err[i] && c[i].active) order.push_back(i);
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return sor_batch_sweeps(c[a]) > sor_batch_sweeps(c[b]); });
+        upto[0] = 0;
+        for (const int i : order) {
             hosc_solver *s = cav[i];
             tile_map(F.hmap()[nact], s, total);
             FusedSweepCav<TM, TM> &cv = F.hcav<FusedSweepCav<TM, TM>>()[nact];
@@ -1573,6 +1582,8 @@ hosc_status fused_sor(Fused &F, hosc_solver *const *cav, int n, const int *mask,
             F.hsrc()[nact] = s->red;
             const int ns = sor_batch_sweeps(c[i]);
             nsw = std::max(nsw, ns);
+            len[nact] = ns;
+            upto[nact + 1] = total;
             for (int q = 0; q < ns; ++q) {
                 int m;
                 unsigned a0, a1;
@@ -1583,12 +1594,15 @@ hosc_status fused_sor(Fused &F, hosc_solver *const *cav, int n, const int *mask,
         }
         if (!nact) break;
         FHIPCHK(F, hipMemcpyAsync(F.d_tab, F.h_tab, F.tab_bytes, hipMemcpyHostToDevice, F.st));
-        const int G = fused_grid(F, total);
         if (F.prof) FHIPCHK(F, hipEventRecord(F.ev[0], F.st));
-        for (int q = 0; q < nsw; ++q)
+        int reach = nact;      // cavities whose batch includes sweep q
+        for (int q = 0; q < nsw; ++q) {
+            while (reach > 0 && len[reach - 1] <= q) --reach;
+            const int tq = upto[reach], G = fused_grid(F, tq);
             for (int colour = 0; colour < 2; ++colour)
-                k_sweep_fused<TM, TM><<<G, 256, 0, F.st>>>(F.dmap(), F.dcav<FusedSweepCav<TM, TM>>(), nact, total,
+                k_sweep_fused<TM, TM><<<G, 256, 0, F.st>>>(F.dmap(), F.dcav<FusedSweepCav<TM, TM>>(), reach, tq,
                                                            colour, q);
+        }
         if (F.prof) FHIPCHK(F, hipEventRecord(F.ev[1], F.st));
         FHIPCHK(F, hipGetLastError());
         hosc_status r = fused_reduce_gather(F, nj, nact, 48);
@@ -1601,7 +1615,7 @@ hosc_status fused_sor(Fused &F, hosc_solver *const *cav, int n, const int *mask,
             F.perf.sweep_bytes += bytes;
         }
         for (int a = 0; a < nact; ++a) {
-            const int i = act[a];
+            const int i = order[a];
             r = sor_decide<TM>(cav[i], c[i], F.h_gather + 48 * a, bn2[i], o[i], args[i]);
             if (r) {
                 err[i] = r;
