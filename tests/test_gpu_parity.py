@@ -228,3 +228,24 @@ def test_noconv_is_reported_and_sticky(hosc, oracle_lib):
     assert e.value.name == "HOSC_E_STATE"
     s.init_fields(1, 1e-3)
     s.close()
+
+
+def test_bicgstab_full_size(hosc, oracle_lib):
+    """GPU BiCGSTAB (the paper's solver, the fallback of the SOR path) at the
+    benchmark size: 129^3, n = 0.75, Ra = 1e5, dt = 5e-5, seed 2, two steps with
+    every system solved by BiCGSTAB, against the oracle."""
+    N = 129
+    say("[bicgstab 129^3] 2 steps")
+    s, o = _pair(hosc, oracle_lib, N, Ra=1e5, n_pl=0.75, Pr=1.0, dt=5e-5, solve_rtol=1e-11,
+                 solver=hosc.SOLVER_BICGSTAB)
+    s.init_fields(2, 1e-3)
+    o.set_state(**initial_state(N, 2, 1e-3))
+    infos = [s.step(1) for _ in range(2)]
+    o.step(2)
+    assert all(sum(i.sweeps) == 0 and sum(i.bicg_iters) > 0 for i in infos)
+    g = s.get_state()
+    for f in ("u", "v", "w", "T", "p"):
+        e = rel(g[f], o.a[f])
+        say(f"[bicgstab 129^3] {f} rel L2 {e:.3e}")
+        assert e <= 1e-10, f
+    s.close()
