@@ -19,7 +19,10 @@ steps, earlier).  Checks, all from the mathematics rather than printed numbers:
   second order (the pressure gradient, divergence and wall closures are second
   order; the transport operator alone is fourth order);
 - the steady state does not depend on the number of pressure iterations per step,
-  and more pressure iterations reach it in fewer steps."""
+  and more pressure iterations reach it in fewer steps;
+- the paper's own case (n = 0.75, Ra = 1e4) does settle with the viscosity
+  relaxation on 51^3, 81^3 and 91^3, symmetric and within 1.06% between 51^3 and
+  91^3."""
 import sys
 import time
 
@@ -44,10 +47,10 @@ def hosc():
     return h
 
 
-def _steady(hosc, N, K=1, rate=2e-5, n_pl=1.0, Ra=1e4):
+def _steady(hosc, N, K=1, rate=2e-5, n_pl=1.0, Ra=1e4, relax=1.0):
     h = 1.0 / (N - 1)
     dt = 0.4 * h * h
-    s = hosc.Solver(hosc.params(N, Ra=Ra, n_pl=n_pl, Pr=1.0, dt=dt, solve_rtol=1e-11, p_iters=K))
+    s = hosc.Solver(hosc.params(N, Ra=Ra, n_pl=n_pl, Pr=1.0, dt=dt, solve_rtol=1e-11, p_iters=K, eta_relax=relax))
     s.init_fields(1, 1e-3)
     t = time.time()
     for _ in range(200):
@@ -117,3 +120,26 @@ def test_steady_state_independent_of_pressure_iterations(hosc):
     for f in ("u", "v", "w", "T"):
         assert np.max(np.abs(g1[f] - g4[f])) <= 1e-7 * np.max(np.abs(g1[f])), f
     assert abs(d1["nu_mean_hot"] - d4["nu_mean_hot"]) <= 1e-9 * d1["nu_mean_hot"]
+
+
+def test_grid_independence_paper_case_shear_thinning(hosc):
+    """The paper's own Table 1 case, n = 0.75 and Ra = 1e4, marched to steady state
+    with the viscosity relaxation (its steady state is that of the stated scheme;
+    the stated scheme alone stalls in a period-2 oscillation, and grids of 41^3 and
+    below diverge at dt = 0.4 h^2).  On 51^3, 81^3 and 91^3: centro-symmetry, and
+    51^3 against 91^3 within the paper's 1.06% (velocity components relative to the
+    velocity magnitude at the probe, theta relative to itself)."""
+    vals = {}
+    for N in (51, 81, 91):
+        s, info, d, pr = _steady(hosc, N, n_pl=0.75, relax=0.1)
+        for q in range(3):
+            assert abs(pr[0][q] + pr[1][q]) <= 1e-5 * max(abs(pr[0][q]), 1e-3), (N, q)
+        assert abs(pr[0][3] + pr[1][3] - 1.0) <= 1e-6, N
+        vals[N] = np.array(pr[0][:4])
+        s.close()
+    speed = np.linalg.norm(vals[91][:3])
+    dv = np.abs(vals[51][:3] - vals[91][:3]) / speed
+    dt = abs(vals[51][3] - vals[91][3]) / vals[91][3]
+    say(f"[grid] n=0.75 Ra=1e4 at (0.6, 0.6, 0.6): 51^3 {vals[51]} 91^3 {vals[91]}; "
+        f"differences {100 * dv}% (of |v|), theta {100 * dt:.3f}%")
+    assert np.max(dv) <= 0.0106 and dt <= 0.0106
