@@ -120,20 +120,30 @@ __device__ __forceinline__ void block_max_store(double (&v)[NV], double *out)
 // block of 1024 threads; op 0 = sum, 1 = max.  Thread t folds records t, t+1024, ...
 // in order, then a fixed shuffle tree inside each wavefront and a fixed-order pass
 // over the 16 wavefronts: deterministic.
-// Thread t folds records t, t + 1024, ... of every component (all NC loads of a
-// record issued together, no guard between them); per component the order is
-// that of a component-by-component pass.
+// Thread t folds records t, t + 1024, ... of every component (the loads of four
+// records issued together); per component the order is that of a
+// component-by-component pass.
 template <int NC>
 __device__ __forceinline__ void fold_records(const double *part, int nb, int op, double (&acc)[8])
 {
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = op == 0 ? 0.0 : -HUGE_VAL;
-    for (int b = threadIdx.x; b < nb; b += 1024) {
-        double x[NC];
+    // four records per pass, their loads issued together (a record past the end
+    // reads the last record and is not folded), folded in the order b, b + 1024, ...
+    for (int b = threadIdx.x; b < nb; b += 4096) {
+        double x[4][NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) x[c] = part[(size_t)b * NC + c];
+        for (int r = 0; r < 4; ++r) {
+            const int bb = min(b + 1024 * r, nb - 1);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) acc[c] = op == 0 ? acc[c] + x[c] : nanmax(acc[c], x[c]);
+            for (int c = 0; c < NC; ++c) x[r][c] = part[(size_t)bb * NC + c];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (b + 1024 * r >= nb) break;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[c] = op == 0 ? acc[c] + x[r][c] : nanmax(acc[c], x[r][c]);
+        }
     }
 }
 
@@ -256,17 +266,27 @@ __device__ __forceinline__ bool all_node(const Geo &g, const Tile &tl, int &i, i
 // ---------------------------------------------------------------------------
 // Derivatives at any node: central inside, 2nd-order one-sided on a wall normal to
 // the axis (velocity, eta, theta); the wall-normal pressure derivative is zero.
+// Branch-free: every lane reads three points at offsets and weights chosen per
+// lane (inside: f(+1) - f(-1) + 0 f(0), exactly the central difference; on a
+// wall: the one-sided weights -3, 4, -1 or 3, -4, 1), so the loads of all the
+// derivatives of a node issue together instead of the wall and interior paths of
+// a wavefront running one after the other (nearly every wavefront of an all-node
+// launch holds an x-wall lane).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double dnode(const double *f, size_t c, size_t s, int idx, int N, double inv2h)
 {
-    if (idx == 0) return (-3.0 * f[c] + 4.0 * f[c + s] - f[c + 2 * s]) * inv2h;
-    if (idx == N - 1) return (3.0 * f[c] - 4.0 * f[c - s] + f[c - 2 * s]) * inv2h;
-    return (f[c + s] - f[c - s]) * inv2h;
+    const bool lo = idx == 0, hi = idx == N - 1;
+    const ptrdiff_t t = (ptrdiff_t)s;
+    const ptrdiff_t o0 = (lo || hi) ? 0 : t, o1 = lo ? t : -t, o2 = lo ? 2 * t : (hi ? -2 * t : 0);
+    const double w0 = lo ? -3.0 : (hi ? 3.0 : 1.0), w1 = lo ? 4.0 : (hi ? -4.0 : -1.0), w2 = lo ? -1.0 : (hi ? 1.0 : 0.0);
+    const double a = f[(ptrdiff_t)c + o0], b = f[(ptrdiff_t)c + o1], e = f[(ptrdiff_t)c + o2];
+    return (w0 * a + w1 * b + w2 * e) * inv2h;
 }
 __device__ __forceinline__ double dpnode(const double *p, size_t c, size_t s, int idx, int N, double inv2h)
 {
-    if (idx == 0 || idx == N - 1) return 0.0;
-    return (p[c + s] - p[c - s]) * inv2h;
+    // on a wall both reads are the node itself: p - p = 0
+    const ptrdiff_t o = (idx == 0 || idx == N - 1) ? 0 : (ptrdiff_t)s;
+    return (p[(ptrdiff_t)c + o] - p[(ptrdiff_t)c - o]) * inv2h;
 }
 
 struct VelGrad {
