@@ -166,6 +166,39 @@ def test_power_law_steps(hosc, oracle_lib, N, n_pl, Ra, dt, solver):
     s.close()
 
 
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("N", [5, 6, 7])
+def test_smallest_grids(hosc, oracle_lib, N, precision):
+    """The smallest grids accepted: N = 5 (three interior nodes per side, one tile
+    holding every row, the five-point wall stencil of Nu spanning the cavity), N = 6
+    (even: no centre plane, Simpson's 3/8 rule on the last three intervals) and
+    N = 7; the oracle solves them exactly (dense LU).  Twelve shear-thinning steps
+    at Ra = 1e4, both precisions: fields to the FP64 bar, every diagnostic to 1e-10."""
+    say(f"[smallest] N={N} precision={precision}")
+    phys = dict(Ra=1e4, n_pl=0.75, Pr=1.0, dt=1e-3)
+    s = hosc.Solver(hosc.params(N, solve_rtol=1e-12, precision=precision, **phys))
+    o = oracle_lib.Oracle(oracle_lib.Params(N=N, dense=True, **phys))
+    s.init_fields(8, 1e-2)
+    o.set_state(**initial_state(N, 8, 1e-2))
+    for _ in range(12):
+        gi = s.step(1)
+        assert gi.status == 0
+    o.step(12)
+    g = s.get_state()
+    for f in ("u", "v", "w", "T", "p"):
+        e = rel(g[f], o.a[f])
+        say(f"[smallest] {f} rel L2 {e:.2e}")
+        assert e <= 1e-10, f
+    assert np.abs(g["v"]).max() > 1e-6
+    d = s.diagnostics()
+    r = o.diagnostics(fields=True)
+    for key in ("nu_mean_hot", "nu_mean_cold", "nu_max_hot", "nu_max_cold", "e_total", "e_ht", "e_ff", "be_global",
+                "be_mean", "nu_local_max_hot"):
+        assert abs(d[key] - r[key]) <= 1e-10 * max(abs(r[key]), 1e-300), key
+    assert np.allclose(d["nuavg_hot"], r["nuavg_hot"], rtol=1e-10, atol=1e-12)
+    s.close()
+
 def test_diagnostics_parity(hosc, oracle_lib):
     N = 17
     say("[diagnostics] N=17")
