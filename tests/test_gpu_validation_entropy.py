@@ -145,7 +145,9 @@ def test_nusselt_and_entropy_trends():
     walls as Ra rises; E_local keeps the near-diagonal (half-turn) symmetry; Be falls
     with Ra, stays above 1/2 at Ra = 1e4 for n = 1 and 1.25 and falls below it at
     Ra = 1e5.  (The paper's Be below 1/2 for n = 0.75 at Ra = 1e4 is the departure
-    of its Table 4, reported, not asserted.)"""
+    of its Table 4, reported, not asserted.)  And, from its conclusions, the
+    stream function of the mid-plane z = 1/2 (max |psi|, psi = int_0^y u dy') falls
+    as n rises at every Ra."""
     import numpy as np
     import torch
     assert torch.cuda.is_available()
@@ -164,16 +166,21 @@ def test_nusselt_and_entropy_trends():
         d = s.diagnostics(arrays=True)
         nuh, avg = d["nu_hot"], d["nuavg_hot"]            # nu_hot indexed [k, j]
         asym = float(np.abs(nuh - nuh[:, ::-1]).max() / nuh.max())
+        u_mid = s.get_state()["u"][N // 2]                  # u on the mid-plane z = 1/2, indexed [j, i]
+        h = 1.0 / (N - 1)
+        psi = np.concatenate([np.zeros((1, N)), np.cumsum(0.5 * h * (u_mid[1:] + u_mid[:-1]), axis=0)])
+        psimax = float(np.abs(psi).max())                   # psi(x, y) = int_0^y u dy' (trapezoid)
         el, _ = s.entropy_fields()                          # E_local, indexed [k, j, i]
         emax = float(el.max())
         turn = float(np.abs(el - el[:, ::-1, ::-1]).max()) / emax
         near = (el[:, :, :6].sum() + el[:, :, -6:].sum()) / el.sum()    # within 0.1 of the x walls
         out[(n, ra)] = dict(nuh=nuh, avg=avg, numax=d["nu_local_max_hot"], asym=asym, emax=emax, turn=turn,
-                            near=float(near), etot=d["e_total"], be=d["be_global"])
+                            near=float(near), etot=d["e_total"], be=d["be_global"], psi=psimax)
         print(f"[Nu trends] n={n} Ra={ra}: steady after {info.step} steps; max Nu_local {d['nu_local_max_hot']:.5f}, "
               f"y-asymmetry {asym:.2e}, Nu_avg(z) centre {avg[N // 2]:.5f} range [{avg[1:-1].min():.5f}, "
               f"{avg[1:-1].max():.5f}]; max E_local {emax:.4f}, E_total {d['e_total']:.4f}, Be {d['be_global']:.4f}, "
-              f"entropy within 0.1 of the x walls {near:.3f}, half-turn asymmetry of E_local {turn:.1e}", flush=True)
+              f"entropy within 0.1 of the x walls {near:.3f}, half-turn asymmetry of E_local {turn:.1e}; "
+              f"mid-plane max |psi| {psimax:.5f}", flush=True)
         s.close()
     ras = ["1e2", "1e3", "1e4", "1e5"]
     for n in (0.75, 1.0, 1.25):
@@ -213,6 +220,12 @@ def test_nusselt_and_entropy_trends():
         seq = [out[(n, ra)] for n in (0.75, 1.0, 1.25) if (n, ra) in out]
         for a, b in zip(seq, seq[1:]):
             assert b["emax"] < a["emax"] and b["etot"] < a["etot"]        # fall as n rises
+    for ra in ras:                                                         # conclusions: the stream function
+        seq = [out[(n, ra)]["psi"] for n in (0.75, 1.0, 1.25) if (n, ra) in out]
+        assert all(b < a for a, b in zip(seq, seq[1:]))                    # falls as n rises
+    for n in (0.75, 1.0, 1.25):
+        seq = [out[(n, ra)]["psi"] for ra in ras if (n, ra) in out]
+        assert all(b > a for a, b in zip(seq, seq[1:]))                    # and rises with Ra
     et2 = [out[(n, "1e2")]["etot"] for n in (0.75, 1.0, 1.25)]
     assert (max(et2) - min(et2)) / min(et2) < 1e-3                        # E_total nearly equal at Ra = 1e2
     for key in out:
