@@ -20,12 +20,19 @@ def test_params_default_and_validation():
     p = hosc.params(17)
     assert p.N == 17 and p.Ra == 1e3 and p.Pr == 1.0 and p.n_pl == 1.0 and p.solve_rtol == 1e-10
     assert hosc.workspace_bytes(p) > 30 * 17 ** 3 * 8
-    for N, bad in ((4, {}), (17, dict(Pr=0.0)), (17, dict(dt=-1.0)), (17, dict(n_pl=0.0)), (17, dict(omega=2.0)), (17, dict(omega=-0.5)),
-                   (17, dict(solve_rtol=0.0))):
+    for N, bad in ((4, {}), (1026, {}), (17, dict(Pr=0.0)), (17, dict(dt=-1.0)), (17, dict(n_pl=0.0)),
+                   (17, dict(n_pl=2.5)), (17, dict(omega=2.0)), (17, dict(omega=-0.5)), (17, dict(solve_rtol=0.0)),
+                   (17, dict(solve_rtol=1.0)), (17, dict(Ra=float("nan"))), (17, dict(Ra=-1.0)),
+                   (17, dict(p_iters=-1)), (17, dict(p_iters=65)), (17, dict(eta_relax=0.0)),
+                   (17, dict(eta_relax=1.5)), (17, dict(i2_floor=0.0)), (17, dict(phi=-1e-4)),
+                   (17, dict(precision=2)), (17, dict(solver=7)), (17, dict(check_every=-1)),
+                   (17, dict(solve_maxit=0)), (17, dict(theta_hot=float("inf")))):
         q = hosc.params(N, **bad)
         with pytest.raises(hosc.HoscError) as e:
             hosc.workspace_bytes(q)
-        assert e.value.name == "HOSC_E_ARG"
+        assert e.value.name == "HOSC_E_ARG", (N, bad)
+    for ok in (dict(p_iters=0), dict(p_iters=64), dict(eta_relax=1e-3), dict(eta_relax=1.0), dict(n_pl=2.0)):
+        assert hosc.workspace_bytes(hosc.params(17, **ok)) > 0
 
 
 def test_workspace_scales_with_grid():
