@@ -32,6 +32,10 @@ FP64 steps at the same Ra and dt.  After the timed run the same segment is run i
 FP64 from the same start and the relative L2 difference of every field and of the
 Nu/Be/entropy scalars is reported.
 
+`--workload sizes` reports the half-sweep bandwidth for grids from 129^3 to 385^3:
+at 129^3 part of each launch's working set stays in the 256 MB Infinity Cache
+between launches, from 257^3 on it streams from HBM.
+
 Prints one JSON line: cell-updates/s (interior nodes x steps / second), the
 roofline of the dominant kernel (the red-black sweep, HIP events around every
 launch, algorithmic bytes per launch), and the FP64 CPU oracle timed on the
@@ -79,6 +83,13 @@ WORKLOADS = {
                   p_iters=3,
                   label="HOSC cavity 129^3, n=0.75, Ra=1e5, Pr=1, dt=5e-5, FP64, rtol 1e-10, seed 2, "
                         "3 pressure iterations per step (momentum re-solved after each correction)"),
+    # half-sweep bandwidth against grid size: from a working set that partly stays in
+    # the 256 MB Infinity Cache (129^3) to ones that stream from HBM; the benchmark
+    # physics with dt = 0.82 h^2 (the benchmark's dt/h^2), FP64, SOR
+    "sizes": dict(kind="sizes", grids=(129, 161, 193, 257, 385), Ra=1e5, n_pl=0.75, Pr=1.0, dt_over_h2=0.82, seed=2,
+                  noise=1e-3, solve_rtol=1e-10,
+                  label="HOSC half-sweep bandwidth against grid size (129^3 to 385^3), n=0.75, Ra=1e5, Pr=1, "
+                        "dt=0.82 h^2, FP64, rtol 1e-10, seed 2; 3 untimed and 6 timed steps per grid"),
     "fp32r": dict(N=129, Ra=1e4, n_pl=1.25, Pr=1.0, dt=5e-5, seed=3, noise=1e-3, solve_rtol=1e-10, precision=1,
                   newtonian_start=20, segment=60,
                   label="HOSC cavity 129^3, n=1.25, Ra=1e4, Pr=1, dt=5e-5, FP32 rows/sweeps + FP64 refinement, "
@@ -173,6 +184,47 @@ def precision_check(hosc, W, kw, reset, steps):
     for k in ("nu_mean_hot", "nu_mean_cold", "nu_max_hot", "be_global", "e_total"):
         out["scalar_rel"][k] = float(abs(d1[k] - d0[k]) / abs(d0[k]))
     return out
+
+
+def bench_sizes(args, W, hosc, torch):
+    """Half-sweep bandwidth (algorithmic bytes / HIP-event launch time) for grids
+    from 129^3, whose per-launch working set (about 150 MB) partly stays in the
+    256 MB Infinity Cache between launches, to 385^3 (4.7 GB per launch), which
+    streams from HBM; plus the library's copy probe."""
+    rows = []
+    t0 = time.perf_counter()
+    for N in W["grids"]:
+        p = hosc.params(N, Ra=W["Ra"], n_pl=W["n_pl"], Pr=W["Pr"], dt=W["dt_over_h2"] / (N - 1) ** 2,
+                        solve_rtol=W["solve_rtol"], solver=hosc.SOLVER_SOR)
+        s = hosc.Solver(p, device="cuda:0")
+        s.init_fields(W["seed"], W["noise"])
+        s.step(3)
+        s.perf_enable(True)
+        s.step(6)
+        torch.cuda.synchronize()
+        c = s.perf()
+        n = max(c["sweep_launches"], 1)
+        rows.append({"grid": N, "half_sweeps": c["sweep_launches"], "mb_per_launch": c["sweep_bytes"] / n / 1e6,
+                     "us_per_launch": c["sweep_ms"] / n * 1e3,
+                     "gb_per_s": c["sweep_bytes"] / (c["sweep_ms"] * 1e-3) / 1e9})
+        print(f"[sizes] {rows[-1]}", file=sys.stderr, flush=True)
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    el = time.perf_counter() - t0
+    copy = hosc.copy_bandwidth()
+    big = rows[-1]
+    out = {
+        "metric": METRIC, "value": big["gb_per_s"], "unit": "GB/s", "n_gpus": 1, "steps": 6, "warmup": 3,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": W["label"], "grids": list(W["grids"]), "wall_s": el},
+        "roofline": {"bound": "hbm", "kernel": f"k_sweep at {big['grid']}^3", "achieved": big["gb_per_s"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": big["gb_per_s"] / HBM_PEAK_GBS, "traffic": None},
+        "sizes": rows,
+        "copy_probe_gb_per_s": copy,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def bench_batch(args, W, hosc, torch):
@@ -513,6 +565,8 @@ def main():
         return bench_batch(args, W, hosc, torch)
     if W.get("kind") == "serve":
         return bench_serve(args, W, hosc, torch)
+    if W.get("kind") == "sizes":
+        return bench_sizes(args, W, hosc, torch)
     if args.segment is None:
         args.segment = W.get("segment", SEGMENT)
     kw = dict(Ra=W["Ra"], n_pl=W["n_pl"], Pr=W["Pr"], dt=W["dt"], solve_rtol=W["solve_rtol"],

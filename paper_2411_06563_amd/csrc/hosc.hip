@@ -84,6 +84,9 @@ Launch make_launch(const Geo &g)
     L.grd_int = dim3((M + 63) / 64, (M + 3) / 4, M);
     int bx = 64;
     while (bx > 8 && bx / 2 >= g.Q) bx /= 2;
+    // rows longer than 64 entries whose last 64-wide tile would be at most half
+    // used take 32-wide tiles (161^3: 3.7 -> 4.6 TB/s per half-sweep)
+    if (bx == 64 && g.Q % 64 != 0 && g.Q % 64 <= 32) bx = 32;
     L.blk_sw = dim3(bx, 256 / bx, 1);
     L.grd_sw = dim3((g.Q + bx - 1) / bx, (M + L.blk_sw.y - 1) / L.blk_sw.y, M);
     L.blk_face = dim3(64, 4, 1);

@@ -199,6 +199,29 @@ def test_smallest_grids(hosc, oracle_lib, N, precision):
     assert np.allclose(d["nuavg_hot"], r["nuavg_hot"], rtol=1e-10, atol=1e-12)
     s.close()
 
+
+@pytest.mark.parametrize("N", [131, 161])
+def test_ragged_row_tiles(hosc, oracle_lib, N):
+    """Grids whose colour rows (65 and 80 entries) fill 32-wide sweep tiles raggedly:
+    at N = 131 the last tile of every row has one active lane.  Two benchmark-physics
+    steps against the oracle."""
+    say(f"[ragged] N={N}")
+    phys = dict(Ra=1e5, n_pl=0.75, Pr=1.0, dt=0.82 / (N - 1) ** 2)
+    s = hosc.Solver(hosc.params(N, solve_rtol=1e-12, **phys))
+    o = oracle_lib.Oracle(oracle_lib.Params(N=N, solve_tol=1e-13, **phys))
+    s.init_fields(2, 1e-3)
+    o.set_state(**initial_state(N, 2, 1e-3))
+    for q in range(2):
+        assert s.step(1).status == 0
+        o.step(1)
+        say(f"[ragged] N={N} step {q + 1} done")
+    g = s.get_state()
+    for f in ("u", "v", "w", "T", "p"):
+        e = rel(g[f], o.a[f])
+        say(f"[ragged] {f} rel L2 {e:.2e}")
+        assert e <= 1e-10, f
+    s.close()
+
 def test_diagnostics_parity(hosc, oracle_lib):
     N = 17
     say("[diagnostics] N=17")
