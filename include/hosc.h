@@ -192,10 +192,16 @@ hosc_status hosc_get_state(hosc_solver *s, double *u, double *v, double *w, doub
 
 /* Advance nsteps time steps (Sec. 2.2).  Each step ends with the Nusselt, entropy
  * and Bejan reductions of the new level (hosc_diagnostics then returns them
- * without recomputing).  info (may be NULL) reports the last step. */
+ * without recomputing).  info (may be NULL) reports the last step.  nsteps = 0
+ * takes no step; HOSC_E_ARG for nsteps < 0, HOSC_E_STATE before a state was set or
+ * after a step failed with HOSC_E_NOCONV or HOSC_E_NONFINITE (sticky until
+ * hosc_set_state or hosc_init_fields). */
 hosc_status hosc_step(hosc_solver *s, int32_t nsteps, hosc_step_info *info);
 
-/* Step until max_f res[f] < res_tol or max_steps steps were taken. */
+/* Step until max_f res[f] < res_tol or max_steps steps were taken (max_steps = 0:
+ * no step, info untouched).  HOSC_E_ARG for res_tol <= 0 or max_steps < 0,
+ * HOSC_E_STATE before a state was set or in a sticky error state; a failing step's
+ * status otherwise. */
 hosc_status hosc_run_to_steady(hosc_solver *s, double res_tol, int64_t max_steps, hosc_step_info *info);
 
 /* Nusselt, entropy and Bejan diagnostics of level n (those of the step that produced

@@ -2274,6 +2274,9 @@ hosc_status hosc_run_to_steady(hosc_solver *s, double res_tol, int64_t max_steps
 {
     if (!s) return HOSC_E_ARG;
     if (!(res_tol > 0.0)) return fail(s, HOSC_E_ARG, "res_tol must be > 0");
+    if (max_steps < 0) return fail(s, HOSC_E_ARG, "max_steps must be >= 0");
+    if (!s->has_state) return fail(s, HOSC_E_STATE, "no state set");
+    if (s->sticky) return fail(s, HOSC_E_STATE, "solver is in an error state; set a new state");
     hosc_step_info local;
     hosc_step_info *ip = info ? info : &local;
     for (int64_t q = 0; q < max_steps; ++q) {

@@ -1,0 +1,91 @@
+"""Degenerate and failing calls through the C ABI: no state yet, zero steps, bad
+counts and coordinates, and a non-finite state, which the library turns into
+HOSC_E_NONFINITE (sticky until a new state is set).  Every failure here is forced
+from the host through the inputs; every kernel runs to completion."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2411_06563_amd.inputs import initial_state
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hosc():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2411_06563_amd import hosc as h
+    return h
+
+
+def _err(hosc, fn):
+    with pytest.raises(hosc.HoscError) as e:
+        fn()
+    return e.value.name
+
+
+def test_calls_before_a_state(hosc):
+    s = hosc.Solver(hosc.params(9, Ra=1e3, dt=1e-3))
+    assert _err(hosc, lambda: s.step(1)) == "HOSC_E_STATE"
+    assert _err(hosc, lambda: s.run_to_steady(1e-8, 10)) == "HOSC_E_STATE"
+    assert _err(hosc, lambda: s.diagnostics(arrays=False)) == "HOSC_E_STATE"
+    assert _err(hosc, lambda: s.probe([(0.5, 0.5, 0.5)])) == "HOSC_E_STATE"
+    s.close()
+
+
+def test_zero_steps_and_bad_arguments(hosc):
+    N = 9
+    s = hosc.Solver(hosc.params(N, Ra=1e3, dt=1e-3, solve_rtol=1e-11))
+    s.init_fields(3, 1e-3)
+    g0 = s.get_state()
+    s.step(0)
+    s.run_to_steady(1e-8, 0)
+    g1 = s.get_state()
+    for f in g0:
+        assert np.array_equal(g0[f], g1[f]), f
+    assert _err(hosc, lambda: s.step(-1)) == "HOSC_E_ARG"
+    assert _err(hosc, lambda: s.run_to_steady(1e-8, -1)) == "HOSC_E_ARG"
+    assert _err(hosc, lambda: s.run_to_steady(0.0, 5)) == "HOSC_E_ARG"
+    assert _err(hosc, lambda: s.probe(np.zeros((0, 3)))) == "HOSC_E_ARG"
+    assert _err(hosc, lambda: s.probe([(0.5, -0.1, 0.5)])) == "HOSC_E_ARG"
+    assert _err(hosc, lambda: s.probe(np.full((N ** 3 // 8 + 1, 3), 0.5))) == "HOSC_E_ARG"
+    with pytest.raises(ValueError):
+        s.set_state(u=np.zeros(10))
+    # the failed calls left the state alone: one step still matches a fresh solver's
+    info = s.step(1)
+    t = hosc.Solver(hosc.params(N, Ra=1e3, dt=1e-3, solve_rtol=1e-11))
+    t.init_fields(3, 1e-3)
+    t.step(1)
+    a, b = s.get_state(), t.get_state()
+    for f in a:
+        assert np.array_equal(a[f], b[f]), f
+    assert info.status == 0
+    s.close()
+    t.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_non_finite_state_is_reported_and_sticky(hosc, precision):
+    N = 11
+    s = hosc.Solver(hosc.params(N, Ra=1e4, n_pl=0.75, dt=5e-4, solve_rtol=1e-11, precision=precision))
+    st = initial_state(N, 4, 1e-3)
+    st["u"] = st["u"].copy()
+    st["u"][5, 5, 5] = np.nan
+    s.set_state(**st)
+    assert _err(hosc, lambda: s.step(1)) == "HOSC_E_NONFINITE"
+    assert _err(hosc, lambda: s.step(1)) == "HOSC_E_STATE"
+    assert _err(hosc, lambda: s.run_to_steady(1e-8, 5)) == "HOSC_E_STATE"
+    s.set_state(**initial_state(N, 4, 1e-3))
+    info = s.step(2)
+    assert info.status == 0
+    g = s.get_state()
+    assert all(np.all(np.isfinite(g[f])) for f in g)
+    say(f"[edge] precision {precision}: NaN reported, sticky, cleared by a new state")
+    s.close()
