@@ -19,6 +19,11 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "hosc_oracle.c")
 LIB = os.path.join(HERE, "libhosc_oracle.so")
+# another build of the oracle (a copy with a planted mistake, for the tests that
+# show the pins catch such mistakes); never compiled over by build()
+ALT = os.environ.get("HOSC_ORACLE_LIB")
+if ALT:
+    LIB = ALT
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -45,6 +50,8 @@ class _Info(ctypes.Structure):
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain C, optional OpenMP)."""
+    if ALT:
+        return LIB
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", tmp, SRC, "-lm"])

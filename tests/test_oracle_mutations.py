@@ -1,0 +1,90 @@
+"""The pins catch plausible mistakes in the oracle.
+
+Each case plants one mistake in a copy of the oracle's C source (a dropped term, a
+flipped sign, a transposed derivative direction, a wrong stencil weight, a missing
+factor), builds it with gcc and runs the pin file that should catch it against
+that build (the oracle module loads the build HOSC_ORACLE_LIB names): the pins must
+fail.  A control build of the unmodified source must pass the same files, so a
+failure is the mistake's and not the harness's.  Everything runs on the CPU."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "hosc_oracle.c")
+
+# name: (text in the oracle, planted replacement, pin files that must catch it)
+MUTANTS = {
+    "time part of M18 dropped": (
+        "double M18 = 0.5 * dt * ((C->L[c] - C->Lp[c]) / dt);", "double M18 = 0.0;",
+        ["test_oracle_expanded_form.py"]),
+    "convective sign in the compact bracket": (
+        "s += hd2[d] / 12.0 * (D2(f, N, h, i, j, k, d) - C->V[d][c] * D1(f, N, h, i, j, k, d));",
+        "s += hd2[d] / 12.0 * (D2(f, N, h, i, j, k, d) + C->V[d][c] * D1(f, N, h, i, j, k, d));",
+        ["test_oracle_expanded_form.py"]),
+    "convective sign in B": (
+        "cd * (D2(x, N, h, i, j, k, d) - C->V[d][c] * D1(x, N, h, i, j, k, d))",
+        "cd * (D2(x, N, h, i, j, k, d) + C->V[d][c] * D1(x, N, h, i, j, k, d))",
+        ["test_oracle_expanded_form.py"]),
+    "cross term M5 dropped": ("s -= M5 * (", "s -= 0.0 * M5 * (", ["test_oracle_closed_form.py"]),
+    "derivative directions of p1 swapped": (
+        "kk * D1(C->V[0], N, h, i, j, k, 1) + hh * D1(C->V[1], N, h, i, j, k, 0)",
+        "kk * D1(C->V[0], N, h, i, j, k, 0) + hh * D1(C->V[1], N, h, i, j, k, 1)",
+        ["test_oracle_expanded_form.py"]),
+    "sign of the derivative term of alpha": (
+        "(Vd * Vd - 2.0 * D1(C->V[d], N, h, i, j, k, d))", "(Vd * Vd + 2.0 * D1(C->V[d], N, h, i, j, k, d))",
+        ["test_oracle_expanded_form.py"]),
+    "sign of the pressure correction": (
+        "S->p[ID(N, i, j, k)] -= P->lambda * div[ID(N, i, j, k)];",
+        "S->p[ID(N, i, j, k)] += P->lambda * div[ID(N, i, j, k)];",
+        ["test_oracle_pressure_iterations.py"]),
+    "weight of the one-sided Nusselt stencil": (
+        "- 36.0 * T[ID(N, 2, j, k)]", "- 35.0 * T[ID(N, 2, j, k)]", ["test_oracle_reductions.py"]),
+    "viscosity missing from E_FF": (
+        "double eff = P->phi * eta[c] * I2[c];", "double eff = P->phi * I2[c];", ["test_oracle_reductions.py"]),
+    "sign of the buoyancy": (
+        "+ P->Ra * Pr * (T[c] - P->theta_ref));", "- P->Ra * Pr * (T[c] - P->theta_ref));",
+        ["test_oracle_physics.py::test_newtonian_reduction"]),
+}
+
+
+def _build(src_text, out_dir, name):
+    c = os.path.join(out_dir, name + ".c")
+    so = os.path.join(out_dir, name + ".so")
+    with open(c, "w") as f:
+        f.write(src_text)
+    subprocess.run(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", so, c, "-lm"], check=True,
+                   capture_output=True)
+    return so
+
+
+def _pins(so, files, extra=()):
+    env = dict(os.environ, HOSC_ORACLE_LIB=so, OMP_NUM_THREADS="4")
+    p = subprocess.run([sys.executable, "-m", "pytest", *[os.path.join("tests", f) for f in files], "-q", "-m",
+                        "not gpu", "-p", "no:cacheprovider", *extra], cwd=ROOT, env=env, capture_output=True,
+                       text=True, timeout=600)
+    return p.returncode, p.stdout
+
+
+@pytest.fixture(scope="module")
+def source():
+    with open(SRC) as f:
+        return f.read()
+
+
+def test_control_build_passes(source, tmp_path):
+    so = _build(source, str(tmp_path), "control")
+    files = sorted({f for _, _, fs in MUTANTS.values() for f in fs})
+    rc, out = _pins(so, files, ("-k", "not steady_state_wall"))     # the slow steady-state pin is not needed here
+    assert rc == 0, out[-2000:]
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(source, tmp_path, name):
+    old, new, files = MUTANTS[name]
+    assert source.count(old) == 1, name
+    so = _build(source.replace(old, new), str(tmp_path), "mutant")
+    rc, out = _pins(so, files)
+    assert rc == 1 and "failed" in out, (name, out[-2000:])
