@@ -1,8 +1,8 @@
 """The pins catch plausible mistakes in the oracle.
 
 Each case plants one mistake in a copy of the oracle's C source (a dropped term, a
-flipped sign, a transposed derivative direction, a wrong stencil weight, a missing
-factor), builds it with gcc and runs the pin file that should catch it against
+flipped sign, a transposed derivative direction, a wrong stencil or quadrature
+weight, a missing factor, a wrong exponent, a first-order closure), builds it with gcc and runs the pin file that should catch it against
 that build (the oracle module loads the build HOSC_ORACLE_LIB names): the pins must
 fail.  A control build of the unmodified source must pass the same files, so a
 failure is the mistake's and not the harness's.  Everything runs on the CPU."""
@@ -47,6 +47,25 @@ MUTANTS = {
     "sign of the buoyancy": (
         "+ P->Ra * Pr * (T[c] - P->theta_ref));", "- P->Ra * Pr * (T[c] - P->theta_ref));",
         ["test_oracle_physics.py::test_newtonian_reduction"]),
+    "power-law exponent n - 1 instead of (n - 1)/2": (
+        "double ex = 0.5 * (P->n_pl - 1.0);", "double ex = (P->n_pl - 1.0);", ["test_oracle_reductions.py"]),
+    "factor 2 of the strain invariant's diagonal dropped": (
+        "return 2.0 * (ux * ux + vy * vy + wz * wz) +", "return (ux * ux + vy * vy + wz * wz) +",
+        ["test_oracle_physics.py::test_strain_invariant_is_twice_d_colon_d"]),
+    "factor 2 of the viscous source's diagonal dropped": (
+        "Pr * (2.0 * ux * ex + (uy + vx) * ey", "Pr * (ux * ex + (uy + vx) * ey",
+        ["test_oracle_physics.py::test_viscous_source_is_the_stress_divergence_part"]),
+    "first-order closure on a z wall": (
+        "f[ID(N, i, j, 0)] = (4.0 * f[ID(N, i, j, 1)] - f[ID(N, i, j, 2)]) / 3.0;",
+        "f[ID(N, i, j, 0)] = f[ID(N, i, j, 1)];", ["test_oracle_physics.py::test_symmetry_every_step"]),
+    "middle Simpson weight": (
+        "wq[q + 1] += 4.0 * h / 3.0;", "wq[q + 1] += 2.0 * h / 3.0;", ["test_oracle_reductions.py"]),
+    "Bejan ratio taken from the friction part": (
+        "double be = el > 0.0 ? eht / el : 1.0;", "double be = el > 0.0 ? (el - eht) / el : 1.0;",
+        ["test_oracle_reductions.py"]),
+    "first-order one-sided wall derivative": (
+        "if (idx == 0) return (-3.0 * f[c] + 4.0 * f[c + s] - f[c + 2 * s]) / (2.0 * h);",
+        "if (idx == 0) return (f[c + s] - f[c]) / h;", ["test_oracle_reductions.py"]),
 }
 
 

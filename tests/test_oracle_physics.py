@@ -137,3 +137,47 @@ def test_steady_state_wall_balance_and_green_identity(oracle_lib):
     gap17 = d17["e_ht"] / d17["nu_mean_hot"] - 1.0
     assert 0 < gap17 < gap9 < 0.01
     assert 3.0 < gap9 / gap17 < 5.5             # O(h^2)
+
+
+def _grad(f, h):
+    """x, y, z derivatives of an array indexed [k, j, i]: central inside, second-order
+    one-sided on the walls (numpy's gradient with second-order edges)."""
+    gz, gy, gx = np.gradient(f, h, edge_order=2)
+    return [gx, gy, gz]
+
+
+def test_strain_invariant_is_twice_d_colon_d(oracle_lib):
+    """I2 of the viscosity law (Sec. 2.1) is the second invariant 2 D:D of the rate
+    of strain D = (grad v + grad v^T)/2: formed here as a tensor contraction of the
+    velocity gradient, which the oracle writes out component by component."""
+    orc = oracle_lib
+    N = 9
+    s = random_smooth_state(N, seed=3, amp=2.0)
+    p = orc.Params(N=N, n_pl=0.6)
+    _, I2 = orc.eta_field(p, s["u"], s["v"], s["w"])
+    G = np.array([_grad(s[c], p.h) for c in ("u", "v", "w")])        # G[i, j] = d u_i / d x_j
+    D = 0.5 * (G + G.transpose(1, 0, 2, 3, 4))
+    ref = 2.0 * np.einsum("ij...,ij...->...", D, D)
+    assert ref.max() > 1.0
+    assert np.abs(I2 - ref).max() <= 1e-12 * ref.max()
+
+
+def test_viscous_source_is_the_stress_divergence_part(oracle_lib):
+    """The viscosity-gradient part of the momentum sources (Sec. 2.1, expanded
+    stress divergence): div(2 eta D) = eta lap v + 2 D grad eta for a solenoidal
+    velocity, so with p = 0 and theta = theta_ref, E*_i = sum_j (d_j u_i + d_i u_j)
+    d_j eta / eta (L = 1/(Pr eta) cancels Pr), formed here as a contraction of the
+    velocity gradient with grad eta for a non-uniform eta."""
+    orc = oracle_lib
+    N = 9
+    s = random_smooth_state(N, seed=4, amp=2.0)
+    t = random_smooth_state(N, seed=5, amp=1.0)["T"]
+    eta = 1.0 + 0.5 * (t - t.min()) / (t.max() - t.min())
+    p = orc.Params(N=N, Pr=0.71, Ra=1e4)
+    E = orc.estar_field(p, s["u"], s["v"], s["w"], np.full((N, N, N), p.theta_ref), np.zeros((N, N, N)), eta)
+    G = np.array([_grad(s[c], p.h) for c in ("u", "v", "w")])
+    ge = _grad(eta, p.h)
+    for i in range(3):
+        ref = sum((G[i, j] + G[j, i]) * ge[j] for j in range(3)) / eta
+        assert np.abs(ref).max() > 0.1
+        assert np.abs(E[i] - ref).max() <= 1e-12 * np.abs(ref).max(), i
