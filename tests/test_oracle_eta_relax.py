@@ -48,3 +48,22 @@ def test_first_step_unrelaxed_and_transient_changed():
     b.step(4)
     d = max(np.max(np.abs(a.a[f] - b.a[f])) / np.max(np.abs(a.a[f])) for f in ("u", "v", "w"))
     assert d > 1e-6
+
+
+
+def test_relaxation_continuous_at_one():
+    """The weight r belongs to the new viscosity: the relaxed march is continuous in
+    r at r = 1, its departure from the stated scheme shrinking in proportion to
+    1 - r (1e-6 and 1e-7 here, a ratio of 10).  With the weights the other way round
+    the viscosity would stay frozen near its previous level for r near 1 and the
+    march would depart by the size of the flow's change whatever 1 - r is."""
+    N = 11
+    a = _oracle(N, 0.75, 1.0, Ra=1e4)
+    a.step(6)
+    d = []
+    for eps in (1e-6, 1e-7):
+        b = _oracle(N, 0.75, 1.0 - eps, Ra=1e4)
+        b.step(6)
+        d.append(max(np.max(np.abs(a.a[f] - b.a[f])) / np.max(np.abs(a.a[f])) for f in ("u", "v", "w", "T")))
+    assert 0.0 < d[1] < 1e-3, d
+    assert 8.0 <= d[0] / d[1] <= 12.0, d

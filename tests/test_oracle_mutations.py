@@ -63,6 +63,21 @@ MUTANTS = {
     "Bejan ratio taken from the friction part": (
         "double be = el > 0.0 ? eht / el : 1.0;", "double be = el > 0.0 ? (el - eht) / el : 1.0;",
         ["test_oracle_reductions.py"]),
+    "relaxation weights the other way round": (
+        "eta[c] = P->eta_relax * eta[c] + (1.0 - P->eta_relax) * S->etap[c];",
+        "eta[c] = (1.0 - P->eta_relax) * eta[c] + P->eta_relax * S->etap[c];",
+        ["test_oracle_eta_relax.py::test_relaxation_continuous_at_one"]),
+    "source bracket without its time part": (
+        "s += 0.5 * C->dt * ((f[c] - fp[c]) / C->dt);", "s += 0.0;", ["test_oracle_expanded_form.py"]),
+    "cross term M7 dropped": ("s -= M7 * (", "s -= 0.0 * M7 * (", ["test_oracle_closed_form.py"]),
+    "E_HT without its z component": (
+        "double eht = tx * tx + ty * ty + tz * tz;", "double eht = tx * tx + ty * ty;", ["test_oracle_reductions.py"]),
+    "cold-wall Nusselt sign": ("nc[j + (size_t)N * k] = -dc;", "nc[j + (size_t)N * k] = dc;",
+                               ["test_oracle_reductions.py"]),
+    "y term of the divergence dropped": (
+        "double D = D1(trial[0], N, h, i, j, k, 0) + D1(trial[1], N, h, i, j, k, 1)",
+        "double D = D1(trial[0], N, h, i, j, k, 0) + 0.0 * D1(trial[1], N, h, i, j, k, 1)",
+        ["test_oracle_pressure_iterations.py"]),
     "first-order one-sided wall derivative": (
         "if (idx == 0) return (-3.0 * f[c] + 4.0 * f[c + s] - f[c + 2 * s]) / (2.0 * h);",
         "if (idx == 0) return (f[c + s] - f[c]) / h;", ["test_oracle_reductions.py"]),
