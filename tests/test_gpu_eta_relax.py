@@ -47,6 +47,30 @@ def test_relaxed_march_matches_oracle(hosc, oracle_lib, N, n_pl, Ra, dt):
     s.close()
 
 
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_relaxed_march_with_pressure_iterations(hosc, oracle_lib, precision):
+    """Relaxation combined with pressure iterations (three momentum solves per step,
+    each with the step's relaxed viscosity), both precisions, against the oracle
+    with the same settings: fields to the FP64 bar and the number of corrections of
+    every step equal."""
+    N, n_pl, Ra, dt = 17, 0.75, 1e4, 5e-4
+    s = hosc.Solver(hosc.params(N, Ra=Ra, n_pl=n_pl, Pr=1.0, dt=dt, eta_relax=0.3, p_iters=3, solve_rtol=1e-12,
+                                precision=precision))
+    o = oracle_lib.Oracle(oracle_lib.Params(N=N, Ra=Ra, n_pl=n_pl, Pr=1.0, dt=dt, eta_relax=0.3, p_iters=3,
+                                            solve_tol=1e-13))
+    s.init_fields(7, 1e-3)
+    o.set_state(**initial_state(N, 7, 1e-3))
+    gi = [s.step(1) for _ in range(8)]
+    oi = o.step(8)
+    assert [i.corrected for i in gi] == [i.corrected for i in oi] == [3] * 8
+    g = s.get_state()
+    for f in ("u", "v", "w", "T", "p"):
+        e = rel(g[f], o.a[f])
+        say(f"[eta-relax + p-iter] precision {precision} {f} rel L2 {e:.3e}")
+        assert e <= 1e-10, f
+    s.close()
+
 def test_relaxation_reaches_the_steady_state(hosc):
     N = 33
     h = 1.0 / (N - 1)
