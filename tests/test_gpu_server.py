@@ -127,3 +127,38 @@ def test_server_failure_is_isolated(hosc):
     assert res[ib]["status"] == -4 and res[ib]["steps"] == 0
     assert res[ig]["status"] == 0 and res[ig]["steps"] == 6
     assert res[ig]["diag"] == _solo_diag(hosc, good, 3, 6)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_server_relaxed_and_iterated_requests_equal_single_runs(hosc, precision):
+    """Requests with different viscosity relaxation factors and pressure-iteration
+    counts, admitted together and advanced in fused steps: each result's
+    diagnostics equal its single-cavity run bitwise."""
+    import numpy as np
+    specs = [(17, 1e4, 0.75, 5e-4, 0.3, 1), (18, 1e4, 1.25, 5e-4, 0.5, 2), (13, 1e3, 1.0, 1e-3, 1.0, 3),
+             (20, 1e4, 0.75, 2e-4, 0.6, 2)]
+    plist = [hosc.params(N, Ra=Ra, n_pl=n, Pr=1.0, dt=dt, eta_relax=r, p_iters=K, precision=precision,
+                         solve_rtol=1e-11) for (N, Ra, n, dt, r, K) in specs]
+    seeds = [31, 32, 33, 34]
+    steps = 8
+    solo = []
+    for p, sd in zip(plist, seeds):
+        s = hosc.Solver(p)
+        s.init_fields(sd, 1e-3)
+        s.step(steps)
+        solo.append(s.diagnostics(arrays=False))
+        s.close()
+    srv = hosc.Server(1 << 28, max_resident=4)
+    ids = {srv.submit(p, sd, res_tol=1e-30, max_steps=steps): i for i, (p, sd) in enumerate(zip(plist, seeds))}
+    res = {}
+    for _ in range(100):
+        srv.step()
+        for r in srv.poll():
+            res[ids[r["id"]]] = r
+        if len(res) == len(plist):
+            break
+    srv.close()
+    for i in range(len(plist)):
+        assert res[i]["status"] == 0 and res[i]["steps"] == steps, res[i]
+        assert res[i]["diag"] == solo[i], i
+    assert np.isfinite(solo[0]["nu_mean_hot"])
