@@ -78,6 +78,21 @@ MUTANTS = {
         "double D = D1(trial[0], N, h, i, j, k, 0) + D1(trial[1], N, h, i, j, k, 1)",
         "double D = D1(trial[0], N, h, i, j, k, 0) + 0.0 * D1(trial[1], N, h, i, j, k, 1)",
         ["test_oracle_pressure_iterations.py"]),
+    "first-order closure on every y and z wall": (
+        "static void theta_yz_closure(double *f, int N)\n{\n",
+        "static void theta_yz_closure(double *f, int N)\n{\n"
+        "    for (int i = 1; i < N - 1; ++i) {\n"
+        "        for (int j = 1; j < N - 1; ++j) {\n"
+        "            f[ID(N, i, j, 0)] = f[ID(N, i, j, 1)];\n"
+        "            f[ID(N, i, j, N - 1)] = f[ID(N, i, j, N - 2)];\n"
+        "        }\n"
+        "        for (int k = 0; k < N; ++k) {\n"
+        "            f[ID(N, i, 0, k)] = f[ID(N, i, 1, k)];\n"
+        "            f[ID(N, i, N - 1, k)] = f[ID(N, i, N - 2, k)];\n"
+        "        }\n"
+        "    }\n"
+        "    return;\n",
+        ["test_oracle_physics.py::test_theta_wall_closure_exact_on_quadratics"]),
     "first-order one-sided wall derivative": (
         "if (idx == 0) return (-3.0 * f[c] + 4.0 * f[c + s] - f[c + 2 * s]) / (2.0 * h);",
         "if (idx == 0) return (f[c + s] - f[c]) / h;", ["test_oracle_reductions.py"]),

@@ -181,3 +181,27 @@ def test_viscous_source_is_the_stress_divergence_part(oracle_lib):
         ref = sum((G[i, j] + G[j, i]) * ge[j] for j in range(3)) / eta
         assert np.abs(ref).max() > 0.1
         assert np.abs(E[i] - ref).max() <= 1e-12 * np.abs(ref).max(), i
+
+
+def test_theta_wall_closure_exact_on_quadratics(oracle_lib):
+    """The zero-normal-derivative closure of theta on the y and z walls (reading R9)
+    is second order: it reproduces exactly a field that is quadratic in the
+    wall-normal coordinate with zero normal derivative on the wall.  With theta =
+    1 - x + b q(y) + c q(z), q(s) = s^2 near s = 0 and (1 - s)^2 near s = 1, every
+    y and z wall node (edges included) must get the field's value."""
+    orc = oracle_lib
+    N = 11
+    x = np.linspace(0.0, 1.0, N)
+    q = np.where(x <= 0.5, x ** 2, (1.0 - x) ** 2)
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    Qz, Qy = q[:, None, None] * np.ones((N, N, N)), q[None, :, None] * np.ones((N, N, N))
+    exact = 1.0 - X + 0.7 * Qy - 0.4 * Qz
+    o = orc.Oracle(orc.Params(N=N))
+    T = exact.copy()
+    T[0], T[-1], T[:, 0], T[:, -1] = 99.0, 99.0, 99.0, 99.0     # wall values to be replaced
+    o.set_state(T=T)
+    got = o.a["T"]
+    inner = slice(1, N - 1)                                       # x walls are Dirichlet
+    for face in (got[0, :, inner] - exact[0, :, inner], got[-1, :, inner] - exact[-1, :, inner],
+                 got[:, 0, inner] - exact[:, 0, inner], got[:, -1, inner] - exact[:, -1, inner]):
+        assert np.abs(face).max() <= 1e-13
