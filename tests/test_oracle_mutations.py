@@ -93,6 +93,19 @@ MUTANTS = {
         "    }\n"
         "    return;\n",
         ["test_oracle_physics.py::test_theta_wall_closure_exact_on_quadratics"]),
+    "first-order closure of p on every wall": (
+        "static void pressure_closure(double *p, int N)\n{\n",
+        "static void pressure_closure(double *p, int N)\n{\n"
+        "    for (int k = 0; k < N; ++k)\n"
+        "        for (int j = 0; j < N; ++j)\n"
+        "            for (int i = 0; i < N; ++i) {\n"
+        "                const int ii = i == 0 ? 1 : (i == N - 1 ? N - 2 : i);\n"
+        "                const int jj = j == 0 ? 1 : (j == N - 1 ? N - 2 : j);\n"
+        "                const int kk = k == 0 ? 1 : (k == N - 1 ? N - 2 : k);\n"
+        "                p[ID(N, i, j, k)] = p[ID(N, ii, jj, kk)];\n"
+        "            }\n"
+        "    return;\n",
+        ["test_oracle_physics.py::test_pressure_wall_closure_exact_on_quadratics"]),
     "first-order one-sided wall derivative": (
         "if (idx == 0) return (-3.0 * f[c] + 4.0 * f[c + s] - f[c + 2 * s]) / (2.0 * h);",
         "if (idx == 0) return (f[c + s] - f[c]) / h;", ["test_oracle_reductions.py"]),

@@ -205,3 +205,22 @@ def test_theta_wall_closure_exact_on_quadratics(oracle_lib):
     for face in (got[0, :, inner] - exact[0, :, inner], got[-1, :, inner] - exact[-1, :, inner],
                  got[:, 0, inner] - exact[:, 0, inner], got[:, -1, inner] - exact[:, -1, inner]):
         assert np.abs(face).max() <= 1e-13
+
+
+def test_pressure_wall_closure_exact_on_quadratics(oracle_lib):
+    """The zero-normal-derivative closure of p on every wall (reading R9) reproduces
+    exactly a field quadratic in each wall-normal coordinate with zero normal
+    derivative on the walls: p = q(x) - 2 q(y) + 3 q(z) (q as for theta) gets its
+    own value at every wall node, edges and corners included."""
+    orc = oracle_lib
+    N = 11
+    x = np.linspace(0.0, 1.0, N)
+    q = np.where(x <= 0.5, x ** 2, (1.0 - x) ** 2)
+    exact = q[None, None, :] - 2.0 * q[None, :, None] + 3.0 * q[:, None, None] + np.zeros((N, N, N))
+    o = orc.Oracle(orc.Params(N=N))
+    p = exact.copy()
+    for sl in ((0,), (-1,), (slice(None), 0), (slice(None), -1), (slice(None), slice(None), 0),
+               (slice(None), slice(None), -1)):
+        p[sl] = 99.0                                              # wall values to be replaced
+    o.set_state(p=p)
+    assert np.abs(o.a["p"] - exact).max() <= 1e-13
