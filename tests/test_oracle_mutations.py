@@ -106,6 +106,12 @@ MUTANTS = {
         "            }\n"
         "    return;\n",
         ["test_oracle_physics.py::test_pressure_wall_closure_exact_on_quadratics"]),
+    "level n-1 sources not copied at the first step": (
+        "        memcpy(S->Eup, Eu, n3 * sizeof(double));\n", "",
+        ["test_oracle_physics.py::test_first_step_takes_level_n_minus_1_equal_to_level_n"]),
+    "level n-1 viscosity not copied at the first step": (
+        "        memcpy(S->etap, eta, n3 * sizeof(double));\n", "",
+        ["test_oracle_physics.py::test_first_step_takes_level_n_minus_1_equal_to_level_n"]),
     "first-order one-sided wall derivative": (
         "if (idx == 0) return (-3.0 * f[c] + 4.0 * f[c + s] - f[c + 2 * s]) / (2.0 * h);",
         "if (idx == 0) return (f[c + s] - f[c]) / h;", ["test_oracle_reductions.py"]),

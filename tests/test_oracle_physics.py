@@ -224,3 +224,29 @@ def test_pressure_wall_closure_exact_on_quadratics(oracle_lib):
         p[sl] = 99.0                                              # wall values to be replaced
     o.set_state(p=p)
     assert np.abs(o.a["p"] - exact).max() <= 1e-13
+
+
+def test_first_step_takes_level_n_minus_1_equal_to_level_n(oracle_lib):
+    """Reading R11: the first step after a state is set has no history, and takes
+    level n-1 equal to level n (its time differences vanish).  The same step from
+    an oracle whose level n-1 arrays were filled with level n's velocities,
+    viscosity and sources must agree bitwise."""
+    orc = oracle_lib
+    N = 9
+    s = random_smooth_state(N, seed=12, amp=3.0)
+    prm = orc.Params(N=N, Ra=1e4, n_pl=0.75, dt=5e-4, solve_tol=1e-14)
+    a = orc.Oracle(prm)
+    a.set_state(**s)
+    b = orc.Oracle(prm)
+    b.set_state(**s)
+    eta, _ = orc.eta_field(prm, b.a["u"], b.a["v"], b.a["w"])
+    E = orc.estar_field(prm, b.a["u"], b.a["v"], b.a["w"], b.a["T"], b.a["p"], eta)
+    for f, val in (("up", b.a["u"]), ("vp", b.a["v"]), ("wp", b.a["w"]), ("etap", eta), ("Eup", E[0]),
+                   ("Evp", E[1]), ("Ewp", E[2])):
+        b.a[f][...] = val
+    b.first = 0
+    a.step(1)
+    b.step(1)
+    for f in ("u", "v", "w", "T", "p"):
+        assert np.array_equal(a.a[f], b.a[f]), f
+    assert np.abs(a.a["v"]).max() > 1e-3
