@@ -112,6 +112,13 @@ MUTANTS = {
     "level n-1 viscosity not copied at the first step": (
         "        memcpy(S->etap, eta, n3 * sizeof(double));\n", "",
         ["test_oracle_physics.py::test_first_step_takes_level_n_minus_1_equal_to_level_n"]),
+    "x and y velocities swapped in the energy convection": (
+        "Ct->V[0] = S->u; Ct->V[1] = S->v;", "Ct->V[0] = S->v; Ct->V[1] = S->u;", ["test_oracle_expanded_form.py"]),
+    "momentum convection coefficient without L": (
+        "cs->Gm[q] = S->u[q] * cs->Lm[q];", "cs->Gm[q] = S->u[q];", ["test_oracle_expanded_form.py"]),
+    "energy equation with L = 1/Pr": ("cs->one[q] = 1.0;", "cs->one[q] = 1.0 / P->Pr;", ["test_oracle_expanded_form.py"]),
+    "level n-1 momentum L taken from level n": (
+        "cs->Lmp[q] = 1.0 / (P->Pr * S->etap[q]);", "cs->Lmp[q] = cs->Lm[q];", ["test_oracle_expanded_form.py"]),
     "first-order one-sided wall derivative": (
         "if (idx == 0) return (-3.0 * f[c] + 4.0 * f[c + s] - f[c + 2 * s]) / (2.0 * h);",
         "if (idx == 0) return (f[c + s] - f[c]) / h;", ["test_oracle_reductions.py"]),
