@@ -99,6 +99,9 @@ def lib() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         _build.build()
+    # torch provides the device memory and streams: its device runtime is loaded
+    # first, so that the library binds to the same runtime as the tensors it is given
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp = ctypes.c_void_p
     P = ctypes.POINTER(CParams)

@@ -89,3 +89,19 @@ def test_non_finite_state_is_reported_and_sticky(hosc, precision):
     assert all(np.all(np.isfinite(g[f])) for f in g)
     say(f"[edge] precision {precision}: NaN reported, sticky, cleared by a new state")
     s.close()
+
+
+def test_binding_works_without_importing_torch_first():
+    """A script that imports only the binding: the library must bind to the device
+    runtime that torch (which provides the workspace) uses, whatever the order in
+    which the two are first loaded."""
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("from paper_2411_06563_amd import hosc\n"
+            "p = hosc.params(9, Ra=1e3, dt=1e-3)\n"
+            "s = hosc.Solver(p)\n"
+            "s.init_fields(1, 1e-3)\n"
+            "print('status', s.step(2).status)\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0 and "status 0" in r.stdout, r.stderr[-2000:]
