@@ -105,3 +105,30 @@ def test_binding_works_without_importing_torch_first():
             "print('status', s.step(2).status)\n")
     r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=240)
     assert r.returncode == 0 and "status 0" in r.stdout, r.stderr[-2000:]
+
+
+def test_solvers_on_their_own_streams(hosc):
+    """Two solvers on caller-made streams (default priority), their steps interleaved,
+    give bitwise the results of the same runs on the default stream."""
+    import torch
+    plist = [hosc.params(13, Ra=1e4, n_pl=0.75, dt=5e-4, solve_rtol=1e-11),
+             hosc.params(15, Ra=1e3, n_pl=1.25, dt=1e-3, solve_rtol=1e-11, precision=1)]
+    ref = []
+    for p, sd in zip(plist, (41, 42)):
+        s = hosc.Solver(p)
+        s.init_fields(sd, 1e-3)
+        s.step(6)
+        ref.append(s.get_state())
+        s.close()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    solvers = [hosc.Solver(p, stream=st) for p, st in zip(plist, streams)]
+    for s, sd in zip(solvers, (41, 42)):
+        s.init_fields(sd, 1e-3)
+    for _ in range(6):
+        for s in solvers:
+            assert s.step(1).status == 0
+    for s, r in zip(solvers, ref):
+        g = s.get_state()
+        for f in g:
+            assert np.array_equal(g[f], r[f]), f
+        s.close()
