@@ -122,6 +122,22 @@ MUTANTS = {
     "first-order one-sided wall derivative": (
         "if (idx == 0) return (-3.0 * f[c] + 4.0 * f[c + s] - f[c + 2 * s]) / (2.0 * h);",
         "if (idx == 0) return (f[c + s] - f[c]) / h;", ["test_oracle_reductions.py"]),
+    "viscosity missing from the pressure term of the momentum sources": (
+        "Eu[c] = L * (-px + Pr * (2.0 * ux * ex + (uy + vx) * ey + (uz + wx) * ez));",
+        "Eu[c] = -px / Pr + L * Pr * (2.0 * ux * ex + (uy + vx) * ey + (uz + wx) * ez);",
+        ["test_oracle_physics.py::test_momentum_sources_times_pr_eta_are_the_unnormalised_right_side",
+         "test_oracle_physics.py::test_one_momentum_step_follows_the_momentum_equations"]),
+    "viscosity missing from the buoyancy": (
+        "Ev[c] = L * (-py + Pr * ((uy + vx) * ex + 2.0 * vy * ey + (vz + wy) * ez) + P->Ra * Pr * (T[c] - P->theta_ref));",
+        "Ev[c] = L * (-py + Pr * ((uy + vx) * ex + 2.0 * vy * ey + (vz + wy) * ez)) + P->Ra * (T[c] - P->theta_ref);",
+        ["test_oracle_physics.py::test_momentum_sources_times_pr_eta_are_the_unnormalised_right_side",
+         "test_oracle_physics.py::test_one_momentum_step_follows_the_momentum_equations"]),
+    "largest local Nusselt number taken on the cold wall": (
+        "if (-dh > numax_local) numax_local = -dh;", "if (-dc > numax_local) numax_local = -dc;",
+        ["test_oracle_reductions.py"]),
+    "steady residual divided by the old field": (
+        "den += b[q] * b[q]; }", "den += a[q] * a[q]; }",
+        ["test_oracle_physics.py::test_steady_residual_is_the_relative_change_of_each_field"]),
 }
 
 

@@ -250,3 +250,114 @@ def test_first_step_takes_level_n_minus_1_equal_to_level_n(oracle_lib):
     for f in ("u", "v", "w", "T", "p"):
         assert np.array_equal(a.a[f], b.a[f]), f
     assert np.abs(a.a["v"]).max() > 1e-3
+
+
+def _lap(f, h):
+    """Seven-point Laplacian at interior nodes (zero on the walls)."""
+    out = np.zeros_like(f)
+    c = f[1:-1, 1:-1, 1:-1]
+    out[1:-1, 1:-1, 1:-1] = (f[2:, 1:-1, 1:-1] + f[:-2, 1:-1, 1:-1] + f[1:-1, 2:, 1:-1] + f[1:-1, :-2, 1:-1]
+                             + f[1:-1, 1:-1, 2:] + f[1:-1, 1:-1, :-2] - 6.0 * c) / (h * h)
+    return out
+
+
+def _pressure_grad(p, h):
+    """Gradient of p: central inside; the component normal to a wall is the
+    boundary condition dp/dn = 0 on that wall (tangential ones stay central)."""
+    g = _grad(p, h)
+    for ax, gi in enumerate(g):           # gi indexed [k, j, i]; axis 0 = x is the last array axis
+        sl_lo = [slice(None)] * 3
+        sl_hi = [slice(None)] * 3
+        sl_lo[2 - ax] = 0
+        sl_hi[2 - ax] = -1
+        gi[tuple(sl_lo)] = 0.0
+        gi[tuple(sl_hi)] = 0.0
+    return g
+
+
+def test_momentum_sources_times_pr_eta_are_the_unnormalised_right_side(oracle_lib):
+    """Reading R1.  The momentum equations (Sec. 2.1, expanded form) have the
+    right-hand side -d_i p + Pr (eta lap u_i) + 2 Pr (D grad eta)_i + Ra Pr theta
+    delta_iy; mapped onto the generic PDE (Eq. 1) with L = 1/(Pr eta) the whole
+    non-Laplacian part is divided by Pr eta.  So Pr eta E*_i must equal
+    -d_i p + Pr sum_j (d_j u_i + d_i u_j) d_j eta + Ra Pr (theta - theta_ref) delta_iy,
+    formed here from numpy gradients with a non-uniform eta, a non-zero pressure
+    and theta away from theta_ref: a source that leaves eta off its pressure or its
+    buoyancy term gives Pr eta E* = -eta d_i p ... and fails."""
+    orc = oracle_lib
+    N = 11
+    s = random_smooth_state(N, seed=31, amp=2.0)
+    t = random_smooth_state(N, seed=32, amp=1.0)["T"]
+    eta = 0.4 + 1.6 * (t - t.min()) / (t.max() - t.min())          # in [0.4, 2]
+    T = random_smooth_state(N, seed=33, amp=1.0)["T"]
+    p = orc.Params(N=N, Pr=0.71, Ra=3e3, theta_ref=0.5)
+    pres = 5.0 * s["p"]
+    E = orc.estar_field(p, s["u"], s["v"], s["w"], T, pres, eta)
+    G = np.array([_grad(s[c], p.h) for c in ("u", "v", "w")])
+    ge = _grad(eta, p.h)
+    gp = _pressure_grad(pres, p.h)
+    assert np.abs(T - 0.5).max() > 0.3 and np.abs(gp[1]).max() > 1.0
+    for i in range(3):
+        ref = -gp[i] + p.Pr * sum((G[i, j] + G[j, i]) * ge[j] for j in range(3))
+        if i == 1:
+            ref = ref + p.Ra * p.Pr * (T - p.theta_ref)
+        assert np.abs(p.Pr * eta * E[i] - ref).max() <= 1e-12 * np.abs(ref).max(), i
+
+
+def test_one_momentum_step_follows_the_momentum_equations(oracle_lib):
+    """A full step of the scheme (Sec. 2.2), taken from a smooth flowing state with a
+    tiny time step, must advance the velocity at the rate the momentum equations
+    (Sec. 2.1, expanded form) give:
+        u_i,t = -v.grad u_i - d_i p + Pr eta lap u_i + 2 Pr (D grad eta)_i
+                + Ra Pr (theta - theta_ref) delta_iy,
+    all terms formed here with numpy from the state (eta from the oracle's viscosity,
+    itself pinned above).  The HOSC step is consistent with this to O(h^2) (about
+    1.6 % at 17^3 away from the walls); the pressure and buoyancy terms carry eta
+    variations of up to a factor 2.5 and each moves the rate by 10-20 % if the
+    mapping of Sec. 2.2 leaves eta off them."""
+    orc = oracle_lib
+    N = 17
+    s = random_smooth_state(N, seed=21, amp=2.0)
+    s["p"] = 30.0 * s["p"]
+    prm = orc.Params(N=N, Ra=2e3, Pr=0.7, n_pl=0.9, dt=1e-7, solve_tol=1e-14)
+    o = orc.Oracle(prm)
+    o.set_state(**s)
+    s0 = o.state()
+    eta, _ = orc.eta_field(prm, s0["u"], s0["v"], s0["w"])
+    assert eta.max() / eta.min() > 2.0
+    o.step(1)
+    s1 = o.state()
+    h = prm.h
+    vel = [s0["u"], s0["v"], s0["w"]]
+    G = np.array([_grad(c, h) for c in vel])
+    ge = _grad(eta, h)
+    gp = _pressure_grad(s0["p"], h)
+    inner = (slice(2, -2),) * 3
+    for i, name in enumerate(("u", "v", "w")):
+        rate = (-gp[i] + prm.Pr * eta * _lap(vel[i], h) + prm.Pr * sum((G[i, j] + G[j, i]) * ge[j] for j in range(3))
+                - sum(vel[j] * G[i, j] for j in range(3)))
+        if i == 1:
+            rate = rate + prm.Ra * prm.Pr * (s0["T"] - prm.theta_ref)
+        got = (s1[name] - s0[name]) / prm.dt
+        err = np.linalg.norm((got - rate)[inner]) / np.linalg.norm(rate[inner])
+        assert err < 0.04, (name, err)
+
+
+def test_steady_residual_is_the_relative_change_of_each_field(oracle_lib):
+    """Reading R17 (the paper never defines its steady state): the residual the
+    march stops on is, for each of u, v, w and theta, the 2-norm of the change over
+    one step divided by the 2-norm of the new field, over all N^3 nodes.  Checked
+    against numpy on the first step after a state is set and on a later one."""
+    orc = oracle_lib
+    N = 9
+    prm = orc.Params(N=N, Ra=1e4, n_pl=0.8, dt=1e-3, solve_tol=1e-14)
+    o = orc.Oracle(prm)
+    o.set_state(**random_smooth_state(N, seed=41, amp=2.0))
+    for _ in range(2):
+        old = o.state()
+        info = o.step(1)[0]
+        new = o.state()
+        for q, f in enumerate(("u", "v", "w", "T")):
+            ref = np.linalg.norm(new[f] - old[f]) / np.linalg.norm(new[f])
+            assert ref > 1e-6
+            assert abs(info.res[q] - ref) <= 1e-13 * ref, f

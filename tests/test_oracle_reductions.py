@@ -4,7 +4,7 @@ on fields whose integrals are known in closed form.
 - theta = 1 - x + (x - x^3) q(y, z), q = 0.3 + 0.2 y + 0.1 y^3 + 0.05 z^2: the 5-point
   one-sided difference is exact on this cubic in x, and Simpson is exact on the
   cubic in y and the quadratic in z, so
-      Nu_hot(y, z) = 1 - q,  Nu_cold(y, z) = 1 + 2 q,
+      Nu_hot(y, z) = 1 - q (largest, 0.7, at y = z = 0),  Nu_cold(y, z) = 1 + 2 q,
       Nu_avg,hot(z) = 0.575 - 0.05 z^2,  Nu_avg,cold(z) = 1.85 + 0.1 z^2.
 - theta linear and u = y (1 - y): the gradients are exact, E_HT = |grad theta|^2 is
   constant and E_FF = phi (1 - 2y)^2 at n = 1 integrates to phi/3 (Simpson exact).
@@ -33,6 +33,9 @@ def test_nusselt_exact_polynomial(oracle_lib, N):
     assert abs(d["nu_mean_cold"] - (1.85 + 0.1 / 3)) <= 1e-12
     assert abs(d["nu_max_hot"] - 0.575) <= 1e-12
     assert abs(d["nu_max_cold"] - 1.95) <= 1e-12
+    # largest local Nusselt number on the hot wall: 1 - q is largest where q is
+    # smallest, at y = z = 0 (q = 0.3)
+    assert abs(d["nu_local_max_hot"] - 0.7) <= 1e-11
 
 
 @pytest.mark.parametrize("N", [9, 12])
