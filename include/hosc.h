@@ -233,6 +233,30 @@ hosc_status hosc_probe(hosc_solver *s, const double *xyz, int32_t n, double *out
 hosc_status hosc_debug_assemble(hosc_solver *s, double *eta, double *estar, double *b, double *Bmom,
                                 double *Btheta);
 
+/* One HOSC step of the generic transport PDE (Sec. 2.2, Eq. 1 with K* = 0):
+ *     L chi_t + G* chi_x + H* chi_y + I* chi_z - lap chi = E*
+ * with coefficient fields given by the caller instead of formed from the cavity's
+ * state (the hook the momentum and energy equations are instances of; it serves
+ * convergence tests against manufactured solutions).  Host N^3 arrays, x fastest:
+ * L, G, H, I, E at level n and Lp, Gp, Hp, Ip, Ep at level n-1 (only their values at
+ * the interior nodes enter, through the time differences; pass level n again at a
+ * first step); E and Ep may both be NULL (zero source).  chi: level n, every node.
+ * chi_new: on entry its wall nodes hold the Dirichlet values of level n+1 (its
+ * interior is ignored); on return its interior holds level n+1.  The implicit
+ * system is solved as the momentum systems are (solver, solve_rtol, solve_maxit and
+ * precision of the solver's parameters; N and dt from them too; Ra, Pr, n and the
+ * other physical parameters are not used).  info (may be NULL): relres[0],
+ * sweeps[0], bicg_iters[0], omega[0], dominance[0] of the solve and res[0] =
+ * ||chi_new - chi||_2 / ||chi_new||_2 over all nodes; other entries 0.
+ * The call uses the solver's workspace for the coefficients: afterwards the solver
+ * has no state (hosc_step and hosc_get_state fail with HOSC_E_STATE until
+ * hosc_set_state or hosc_init_fields).  HOSC_E_ARG for a missing array or only one
+ * of E, Ep; HOSC_E_NOCONV / HOSC_E_NONFINITE from the solve.  Synchronous. */
+hosc_status hosc_transport_step(hosc_solver *s, const double *L, const double *G, const double *H, const double *I,
+                                const double *E, const double *Lp, const double *Gp, const double *Hp,
+                                const double *Ip, const double *Ep, const double *chi, double *chi_new,
+                                hosc_step_info *info);
+
 /* Switch kernel timing on (on != 0, counters cleared) or off.  Timing adds two
  * event records per timed launch on the solver's stream. */
 hosc_status hosc_perf_enable(hosc_solver *s, int32_t on);
@@ -292,6 +316,16 @@ hosc_status hosc_batch_init_fields(hosc_batch *b, const uint64_t *seeds, double 
  * step of each cavity.  A cavity that fails is reported by status and message
  * ("cavity i: ..."); the step of the other cavities completes. */
 hosc_status hosc_batch_step(hosc_batch *b, int32_t nsteps, hosc_step_info *info);
+
+/* Step the cavities until each reaches max_f res[f] < res_tol or has taken
+ * max_steps steps in this call (the batched form of hosc_run_to_steady).  Every
+ * fused step advances only the cavities still marching, so each cavity takes the
+ * steps, and reaches the state, of its own hosc_run_to_steady.  info (may be NULL):
+ * count entries, the last step each cavity took.  A cavity whose step fails stops
+ * (its status in its info entry) while the others go on; the call then returns the
+ * first failure, with "cavity i: ..." as the message.  HOSC_E_ARG for res_tol <= 0
+ * or max_steps < 0; HOSC_E_STATE if a cavity has no state or is in an error state. */
+hosc_status hosc_batch_run_to_steady(hosc_batch *b, double res_tol, int64_t max_steps, hosc_step_info *info);
 
 /* Autotuner: time the fused half-sweep at each candidate schedule (persistent
  * workgroup counts 256 ... 4096, or one workgroup per tile) on this batch and keep

@@ -1371,6 +1371,7 @@ struct Fused {
     struct GraphEntry {
         uint64_t sig;
         int kind;
+        std::vector<const hosc_solver *> members;   // the cavities of the captured step, in order
         hipGraphExec_t exec;
     };
     std::vector<GraphEntry> graphs;
@@ -1714,12 +1715,19 @@ uint64_t parity_sig(hosc_solver *const *cav, int n)
     return sig;
 }
 
+// The cavities (in order) a fused step covers: a captured phase replays only for
+// the same list (a batch marching to steady state drops cavities as they finish).
+std::vector<const hosc_solver *> member_list(hosc_solver *const *cav, int n)
+{
+    return std::vector<const hosc_solver *>(cav, cav + n);
+}
+
 // Replay the captured phase (kind, sig), capturing it first with record() if needed.
 template <typename Fn>
-hosc_status graph_run(Fused &F, int kind, uint64_t sig, Fn &&record)
+hosc_status graph_run(Fused &F, int kind, uint64_t sig, const std::vector<const hosc_solver *> &members, Fn &&record)
 {
     for (auto &e : F.graphs)
-        if (e.kind == kind && e.sig == sig) {
+        if (e.kind == kind && e.sig == sig && e.members == members) {
             FHIPCHK(F, hipGraphLaunch(e.exec, F.st));
             F.graph_launches += 1;
             return HOSC_OK;
@@ -1741,7 +1749,7 @@ hosc_status graph_run(Fused &F, int kind, uint64_t sig, Fn &&record)
     const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (ei != hipSuccess) return ffail(F, HOSC_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
-    F.graphs.push_back({sig, kind, exec});
+    F.graphs.push_back({sig, kind, members, exec});
     FHIPCHK(F, hipGraphLaunch(exec, F.st));
     F.graph_launches += 1;
     return HOSC_OK;
@@ -1797,9 +1805,10 @@ hosc_status fused_step(Fused &F, hosc_solver *const *cav, int n, hosc_step_info 
         graphed = graphed && s->has_state && !s->sticky && !s->first && !s->prof;
     }
     const uint64_t sig = graphed ? parity_sig(cav, n) : 0;
+    const std::vector<const hosc_solver *> members = graphed ? member_list(cav, n) : std::vector<const hosc_solver *>();
     std::vector<int> all(n, 1);
     if (graphed) {
-        hosc_status r = graph_run(F, 0, sig, [&]() {
+        hosc_status r = graph_run(F, 0, sig, members, [&]() {
             hosc_status first_err = HOSC_OK;
             std::string msg;
             hosc_status fr = fan_out(F, cav, n, all.data(), [&](int i) {
@@ -1858,7 +1867,7 @@ hosc_status fused_step(Fused &F, hosc_solver *const *cav, int n, hosc_step_info 
         if (fresh)
             FHIPCHK(F, hipMemcpyAsync(F.d_tab + F.off_src2, F.h_tab + F.off_src2, (size_t)n * sizeof(double *),
                                       hipMemcpyHostToDevice, F.st));
-        r = graph_run(F, 1, sig, [&]() {
+        r = graph_run(F, 1, sig, members, [&]() {
             hosc_status first_err = HOSC_OK;
             std::string msg;
             hosc_status fr = fan_out(F, cav, n, all.data(), [&](int i) {
@@ -2398,6 +2407,83 @@ hosc_status hosc_debug_assemble(hosc_solver *s, double *eta, double *estar, doub
     return HOSC_OK;
 }
 
+hosc_status hosc_transport_step(hosc_solver *s, const double *L, const double *G, const double *H, const double *I,
+                                const double *E, const double *Lp, const double *Gp, const double *Hp,
+                                const double *Ip, const double *Ep, const double *chi, double *chi_new,
+                                hosc_step_info *info)
+{
+    if (!s) return HOSC_E_ARG;
+    if (!L || !G || !H || !I || !Lp || !Gp || !Hp || !Ip || !chi || !chi_new)
+        return fail(s, HOSC_E_ARG, "L, G, H, I at both levels, chi and chi_new are required");
+    if (!E != !Ep) return fail(s, HOSC_E_ARG, "E and Ep must both be given or both be NULL");
+    // the workspace's natural arrays hold the coefficients: the solver's state is gone
+    s->has_state = false;
+    s->sticky = HOSC_OK;
+    const size_t nb = s->g.n3 * sizeof(double);
+    double *dL = s->eta, *dG = s->u, *dH = s->v, *dI = s->w, *dE = s->E[0];
+    double *dLp = s->etap, *dGp = s->u2, *dHp = s->v2, *dIp = s->w2, *dEp = s->Ep[0];
+    double *dchi = s->T, *dnew = s->p;
+    const double *src[12] = {L, G, H, I, E, Lp, Gp, Hp, Ip, Ep, chi, chi_new};
+    double *dst[12] = {dL, dG, dH, dI, dE, dLp, dGp, dHp, dIp, dEp, dchi, dnew};
+    for (int q = 0; q < 12; ++q)
+        if (src[q]) HIPCHK(s, hipMemcpyAsync(dst[q], src[q], nb, hipMemcpyHostToDevice, s->st));
+    // a fresh solve: zero increments, no inherited sweep plan or relaxation
+    hosc_status r = zero_colour_increments(s);
+    if (r) return r;
+    s->step = 0;
+    s->first = true;
+    s->last_sweeps[0] = s->last_sweeps[1] = 0;
+    s->last_bicg[0] = s->last_bicg[1] = 0;
+    s->bicg_until[0] = s->bicg_until[1] = -1;
+    s->om[0] = s->om[1] = s->P.omega > 0.0 ? s->P.omega : 1.0;
+    s->seeded_at = -1;
+    s->eta_ready = false;
+    s->diag_valid = false;
+    ColourArrays ca;
+    ca.ms = s->ms;
+    for (int d = 0; d < 3; ++d) {
+        ca.ma[d] = s->ma[d];
+        ca.mb[d] = s->mb[d];
+        ca.ta[d] = s->ta[d];
+    }
+    ca.tb = s->tb;
+    k_assemble_transport<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, s->P.dt, dL, dG, dH, dI, E ? dE : nullptr,
+                                                                   dLp, dGp, dHp, dIp, E ? dEp : nullptr, dchi, dnew,
+                                                                   ca, s->partR, s->partB);
+    if (s->fp32)
+        k_rows_f32<<<2048, 256, 0, s->st>>>(2 * s->g.cs, s->ms, s->ma[0], s->ma[1], s->ma[2], s->ta[0], s->ta[1],
+                                           s->ta[2], s->fms, s->fma[0], s->fma[1], s->fma[2], s->fta[0], s->fta[1],
+                                           s->fta[2]);
+    Reductions().add(s->partR, s->L.nb_int, 4, 0, s->red).add(s->partB, s->L.nb_int, 2, 1, s->red + 44).launch(s->st);
+    r = launch_check(s, "transport assembly");
+    if (r) return r;
+    SolveOut so;
+    r = solve(s, so, 1);
+    if (r) return r;
+    k_transport_update<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, dchi, s->md[0], dnew);
+    r = launch_check(s, "transport update");
+    if (r) return r;
+    HIPCHK(s, hipMemcpyAsync(chi_new, dnew, nb, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        double num = 0.0, den = 0.0;
+        for (size_t q = 0; q < s->g.n3; ++q) {
+            num += (chi_new[q] - chi[q]) * (chi_new[q] - chi[q]);
+            den += chi_new[q] * chi_new[q];
+        }
+        info->res[0] = den > 0.0 ? std::sqrt(num) / std::sqrt(den) : (num == 0.0 ? 0.0 : HUGE_VAL);
+        info->relres[0] = so.relres[0];
+        info->step = 1;
+        info->sweeps[0] = so.sweeps[0];
+        info->bicg_iters[0] = so.bicg[0];
+        info->omega[0] = s->om[0];
+        info->dominance[0] = so.dominance[0];
+        info->status = HOSC_OK;
+    }
+    return HOSC_OK;
+}
+
 hosc_status hosc_perf_enable(hosc_solver *s, int32_t on)
 {
     if (!s) return HOSC_E_ARG;
@@ -2570,6 +2656,59 @@ hosc_status hosc_batch_step(hosc_batch *b, int32_t nsteps, hosc_step_info *info)
         for (int i = 0; i < n; ++i)
             if (err[i]) return bfail(b, err[i], "cavity " + std::to_string(i) + ": " + b->cav[i]->err);
     }
+    return HOSC_OK;
+}
+
+hosc_status hosc_batch_run_to_steady(hosc_batch *b, double res_tol, int64_t max_steps, hosc_step_info *info)
+{
+    if (!b) return HOSC_E_ARG;
+    if (!(res_tol > 0.0)) return bfail(b, HOSC_E_ARG, "res_tol must be > 0");
+    if (max_steps < 0) return bfail(b, HOSC_E_ARG, "max_steps must be >= 0");
+    const int n = (int)b->cav.size();
+    for (int i = 0; i < n; ++i) {
+        if (!b->cav[i]->has_state) return bfail(b, HOSC_E_STATE, "cavity " + std::to_string(i) + ": no state set");
+        if (b->cav[i]->sticky)
+            return bfail(b, HOSC_E_STATE, "cavity " + std::to_string(i) + ": in an error state; set a new state");
+    }
+    // cavities still marching; each fused step takes only those, so a cavity's
+    // arithmetic is that of its single-cavity run whatever the others do
+    std::vector<int> running(n, max_steps > 0 ? 1 : 0);
+    std::vector<int64_t> taken(n, 0);
+    std::vector<hosc_solver *> act;
+    std::vector<int> map;
+    std::vector<hosc_status> err(n, HOSC_OK);     // indexed by position in act
+    std::vector<hosc_step_info> part(n);
+    hosc_status first = HOSC_OK;
+    std::string msg;
+    for (;;) {
+        act.clear();
+        map.clear();
+        for (int i = 0; i < n; ++i)
+            if (running[i]) {
+                act.push_back(b->cav[i]);
+                map.push_back(i);
+            }
+        if (act.empty()) break;
+        const int na = (int)act.size();
+        hosc_status r = fused_step(b->F, act.data(), na, part.data(), err.data());
+        if (r) return bfail(b, r, b->F.err);
+        for (int a = 0; a < na; ++a) {
+            const int i = map[a];
+            taken[i] += 1;
+            if (info) info[i] = part[a];
+            if (err[a]) {
+                if (!first) {
+                    first = err[a];
+                    msg = "cavity " + std::to_string(i) + ": " + b->cav[i]->err;
+                }
+                running[i] = 0;
+                continue;
+            }
+            const double m = std::max(std::max(part[a].res[0], part[a].res[1]), std::max(part[a].res[2], part[a].res[3]));
+            if (m < res_tol || taken[i] >= max_steps) running[i] = 0;
+        }
+    }
+    if (first) return bfail(b, first, msg);
     return HOSC_OK;
 }
 

@@ -463,6 +463,29 @@ struct NodeAssembly {
     double b[4];            // right-hand sides of the u, v, w, theta increments
 };
 
+// Implicit 7-point row of the generic PDE (Eq. 1, K* = 0) at an interior node, from
+// L at the 7 central points (level n), the convective coefficients at the centre and
+// L at the centre at level n-1: centre C and the weights s -+ a_d towards x_d +- h.
+__device__ __forceinline__ void implicit_row(const Geo &g, double dt, const double (&Lm)[7], double G0, double H0,
+                                             double I0, double Lp, double &C, double &s, double (&a)[3])
+{
+    const double L0 = Lm[0];
+    const double Lx = (Lm[1] - Lm[2]) * g.inv2h, Ly = (Lm[3] - Lm[4]) * g.inv2h, Lz = (Lm[5] - Lm[6]) * g.inv2h;
+    const double Lxx = (Lm[1] - 2.0 * L0 + Lm[2]) * g.invh2, Lyy = (Lm[3] - 2.0 * L0 + Lm[4]) * g.invh2,
+                 Lzz = (Lm[5] - 2.0 * L0 + Lm[6]) * g.invh2;
+    // M18 = [(dt/2) delta_t^- + sum (d_dd - V_d d_d) h_d^2/12] L
+    const double M18 = 0.5 * (L0 - Lp) + ((Lxx - G0 * Lx) + (Lyy - H0 * Ly) + (Lzz - I0 * Lz)) * g.h2_12;
+    // c = L M_1 = L h^2/12 - dt/2 (M_1 = M_2 = M_3 for h = k = l); the centre
+    // (1 + 2 M_4 M18 / dt) L with M_4 = dt/(2L) is L + M18
+    const double cc = L0 * g.h2_12 - 0.5 * dt;
+    C = L0 + M18 - 6.0 * cc * g.invh2;
+    s = cc * g.invh2;
+    // L M15 = (h^2/6) dL/dx, etc.
+    a[0] = (cc * G0 - 2.0 * g.h2_12 * Lx) * g.inv2h;
+    a[1] = (cc * H0 - 2.0 * g.h2_12 * Ly) * g.inv2h;
+    a[2] = (cc * I0 - 2.0 * g.h2_12 * Lz) * g.inv2h;
+}
+
 template <typename Tin>
 __device__ __forceinline__ void assemble_node(const Geo &g, const Phys &P, int i, int j, int k, const Tin *u,
                                               const Tin *v, const Tin *w, const Tin *T, const Tin *eta,
@@ -485,23 +508,7 @@ __device__ __forceinline__ void assemble_node(const Geo &g, const Phys &P, int i
     }
     const double Lp = 1.0 / (P.Pr * etap[c]);
     const double Gp = up[c] * Lp, Hp = vp[c] * Lp, Ip = wp[c] * Lp;
-    {
-        const double L0 = Lm[0];
-        const double Lx = (Lm[1] - Lm[2]) * g.inv2h, Ly = (Lm[3] - Lm[4]) * g.inv2h, Lz = (Lm[5] - Lm[6]) * g.inv2h;
-        const double Lxx = (Lm[1] - 2.0 * L0 + Lm[2]) * g.invh2, Lyy = (Lm[3] - 2.0 * L0 + Lm[4]) * g.invh2,
-                     Lzz = (Lm[5] - 2.0 * L0 + Lm[6]) * g.invh2;
-        // M18 = [(dt/2) delta_t^- + sum (d_dd - V_d d_d) h_d^2/12] L
-        const double M18 = 0.5 * (L0 - Lp) + ((Lxx - G[0] * Lx) + (Lyy - Hm[0] * Ly) + (Lzz - I[0] * Lz)) * g.h2_12;
-        // c = L M_1 = L h^2/12 - dt/2 (M_1 = M_2 = M_3 for h = k = l); the centre
-        // (1 + 2 M_4 M18 / dt) L with M_4 = dt/(2L) is L + M18
-        const double cc = L0 * g.h2_12 - 0.5 * dt;
-        out.Cm = L0 + M18 - 6.0 * cc * g.invh2;
-        out.sm = cc * g.invh2;
-        // L M15 = (h^2/6) dL/dx, etc.
-        out.am[0] = (cc * G[0] - 2.0 * g.h2_12 * Lx) * g.inv2h;
-        out.am[1] = (cc * Hm[0] - 2.0 * g.h2_12 * Ly) * g.inv2h;
-        out.am[2] = (cc * I[0] - 2.0 * g.h2_12 * Lz) * g.inv2h;
-    }
+    implicit_row(g, dt, Lm, G[0], Hm[0], I[0], Lp, out.Cm, out.sm, out.am);
     // ---- momentum right-hand sides
     {
         Coef19 cw;
@@ -662,6 +669,94 @@ __global__ void __launch_bounds__(256) k_assemble_debug(Geo g, Phys P, const dou
         val = a.b[what - 14];
     }
     out[nid(g, i, j, k)] = val;
+}
+
+// ---------------------------------------------------------------------------
+// One step of the generic transport PDE (Eq. 1, K* = 0) with coefficient fields
+// given at every node (L, G*, H*, I*, E* at level n; at level n-1 only their centre
+// values enter, through the time differences) and Dirichlet walls.  The row and b
+// of each interior node are those of the momentum assembly with L and V read
+// instead of formed from eta and the velocity; the known wall increments
+// chi_new - chi of the six neighbours are moved to the right-hand side.  The scaled
+// row goes to the first momentum system (the other two get b = 0, so their sweeps
+// are skipped).  E and Ep may be null (zero source).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_assemble_transport(
+    Geo g, double dt, const double *__restrict__ L, const double *__restrict__ G, const double *__restrict__ H,
+    const double *__restrict__ I, const double *__restrict__ E, const double *__restrict__ Lp,
+    const double *__restrict__ Gp, const double *__restrict__ Hp, const double *__restrict__ Ip,
+    const double *__restrict__ Ep, const double *__restrict__ chi, const double *__restrict__ chi_new,
+    ColourArrays ca, double *__restrict__ partial, double *__restrict__ partial_dom)
+{
+    const Tile tl = xcd_tile();
+    const int i = 1 + tl.x * blockDim.x + threadIdx.x, j = 1 + tl.y * blockDim.y + threadIdx.y, k = 1 + tl.z;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double dom[2] = {0.0, 0.0};
+    if (i <= g.N - 2 && j <= g.N - 2) {
+        const size_t c = nid(g, i, j, k);
+        size_t o[19];
+        offsets19(g, c, o);
+        double Lm[7], Gv[7], Hv[7], Iv[7];
+#pragma unroll
+        for (int m = 0; m < 7; ++m) {
+            Lm[m] = L[o[m]];
+            Gv[m] = G[o[m]];
+            Hv[m] = H[o[m]];
+            Iv[m] = I[o[m]];
+        }
+        double C, sw, a[3];
+        implicit_row(g, dt, Lm, Gv[0], Hv[0], Iv[0], Lp[c], C, sw, a);
+        Coef19 cw;
+        explicit_weights(g, dt, Gv, Hv, Iv, Gp[c], Hp[c], Ip[c], cw);
+        double sum = 0.0;
+#pragma unroll
+        for (int m = 0; m < 19; ++m) sum += cw.W[m] * chi[o[m]];
+        double R = 0.0;
+        if (E) {
+            double E7[7];
+#pragma unroll
+            for (int m = 0; m < 7; ++m) E7[m] = E[o[m]];
+            R = source_R(g, dt, E7, Ep[c], Gv[0], Hv[0], Iv[0]);
+        }
+        double b = dt * (R + sum);
+        // neighbours 1..6 (x+, x-, y+, y-, z+, z-) with weights s - a_d, s + a_d
+        const bool wall[6] = {i == g.N - 2, i == 1, j == g.N - 2, j == 1, k == g.N - 2, k == 1};
+#pragma unroll
+        for (int m = 0; m < 6; ++m)
+            if (wall[m]) {
+                const double wgt = (m & 1) ? sw + a[m >> 1] : sw - a[m >> 1];
+                b -= wgt * (chi_new[o[m + 1]] - chi[o[m + 1]]);
+            }
+        const size_t idx = (size_t)((i + j + k) & 1) * g.cs + rowid(g, j, k) + (i >> 1);
+        const double rc = 1.0 / C;
+        ca.ms[idx] = sw * rc;
+        double om = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            ca.ma[d][idx] = a[d] * rc;
+            om += fabs(sw - a[d]) + fabs(sw + a[d]);
+        }
+        const double bb = b * rc;
+        ca.mb[0][idx] = bb;
+        ca.mb[1][idx] = 0.0;
+        ca.mb[2][idx] = 0.0;
+        acc[0] = bb * bb;
+        dom[0] = om / fabs(C);
+    }
+    const int blk = tl.id;
+    block_sum_store<4>(acc, partial + (size_t)blk * 4);
+    block_max_store<2>(dom, partial_dom + (size_t)blk * 2);
+}
+
+// chi_new = chi + increment at interior nodes (walls of chi_new untouched).
+__global__ void __launch_bounds__(256) k_transport_update(Geo g, const double *__restrict__ chi,
+                                                          const double *__restrict__ d, double *__restrict__ chi_new)
+{
+    const Tile tl = xcd_tile();
+    const int i = 1 + tl.x * blockDim.x + threadIdx.x, j = 1 + tl.y * blockDim.y + threadIdx.y, k = 1 + tl.z;
+    if (i > g.N - 2 || j > g.N - 2) return;
+    const size_t c = nid(g, i, j, k);
+    chi_new[c] = chi[c] + d[(size_t)((i + j + k) & 1) * g.cs + rowid(g, j, k) + (i >> 1)];
 }
 
 // ---------------------------------------------------------------------------

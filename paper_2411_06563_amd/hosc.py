@@ -118,6 +118,7 @@ def lib() -> ctypes.CDLL:
     L.hosc_entropy_fields.argtypes = [vp, _dp, _dp]
     L.hosc_probe.argtypes = [vp, _dp, ctypes.c_int32, _dp]
     L.hosc_debug_assemble.argtypes = [vp, _dp, _dp, _dp, _dp, _dp]
+    L.hosc_transport_step.argtypes = [vp] + [_dp] * 12 + [ctypes.POINTER(CStepInfo)]
     L.hosc_perf_enable.argtypes = [vp, ctypes.c_int32]
     L.hosc_perf_get.argtypes = [vp, ctypes.POINTER(CPerf)]
     L.hosc_copy_bandwidth.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_double)]
@@ -129,6 +130,7 @@ def lib() -> ctypes.CDLL:
     L.hosc_batch_cavity.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(vp)]
     L.hosc_batch_init_fields.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.c_double]
     L.hosc_batch_step.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(CStepInfo)]
+    L.hosc_batch_run_to_steady.argtypes = [vp, ctypes.c_double, ctypes.c_int64, ctypes.POINTER(CStepInfo)]
     L.hosc_batch_tune.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.hosc_batch_set_grid.argtypes = [vp, ctypes.c_int32]
     L.hosc_batch_perf_enable.argtypes = [vp, ctypes.c_int32]
@@ -339,6 +341,23 @@ class Solver:
         _check(lib().hosc_debug_assemble(self.h, _ptr(eta), _ptr(E), _ptr(b), _ptr(Bm), _ptr(Bt)), self.h)
         return dict(eta=eta, E=E, b=b, Bmom=Bm, Btheta=Bt)
 
+    def transport_step(self, L, G, H, I, E, Lp, Gp, Hp, Ip, Ep, chi, chi_new_walls):
+        """One step of the generic transport PDE (hosc_transport_step): level n and
+        n-1 coefficient fields, chi at level n, Dirichlet walls of level n+1 taken from
+        ``chi_new_walls``.  Returns (chi_new, StepInfo).  The solver has no state
+        afterwards."""
+        arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+                for a in (L, G, H, I, E, Lp, Gp, Hp, Ip, Ep, chi)]
+        for a in arrs:
+            if a is not None and a.size != self.N ** 3:
+                raise ValueError("fields must hold N^3 values")
+        out = np.array(chi_new_walls, dtype=np.float64, copy=True, order="C")
+        if out.size != self.N ** 3:
+            raise ValueError("fields must hold N^3 values")
+        info = CStepInfo()
+        _check(lib().hosc_transport_step(self.h, *(_ptr(a) for a in arrs), _ptr(out), ctypes.byref(info)), self.h)
+        return out, StepInfo.of(info)
+
 
 class Batch:
     """Many cavities advanced together with fused solver launches (hosc_batch_*)."""
@@ -390,6 +409,11 @@ class Batch:
     def step(self, n: int = 1) -> list:
         infos = (CStepInfo * len(self.cavities))()
         _check(lib().hosc_batch_step(self.b, n, infos), batch=self.b)
+        return [StepInfo.of(c) for c in infos]
+
+    def run_to_steady(self, tol: float, max_steps: int) -> list:
+        infos = (CStepInfo * len(self.cavities))()
+        _check(lib().hosc_batch_run_to_steady(self.b, tol, max_steps, infos), batch=self.b)
         return [StepInfo.of(c) for c in infos]
 
     def tune(self) -> int:

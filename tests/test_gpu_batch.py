@@ -165,3 +165,36 @@ def test_batch_with_relaxation_bitwise_equal_to_solo(hosc, precision):
         assert [bi[i].sweeps for bi in binfo] == [si.sweeps for si in infos]
         say(f"[batch relax] precision {precision} cavity {i} r={relax[i]}: bitwise equal")
     b.close()
+
+
+def test_batch_run_to_steady_equals_single_runs(hosc):
+    """hosc_batch_run_to_steady: each cavity stops at its own steady residual (or
+    step cap) and ends bitwise where hosc_run_to_steady alone ends, with the same
+    number of steps, although the cavities finish at different steps."""
+    cases = [(9, 1e3, 1.0, 2e-3), (11, 2e3, 0.8, 1e-3), (12, 5e2, 1.2, 2e-3)]
+    plist = [hosc.params(N, Ra=Ra, n_pl=n, Pr=1.0, dt=dt, solve_rtol=1e-11) for (N, Ra, n, dt) in cases]
+    seeds = [21, 22, 23]
+    tol, cap = 1e-6, 3000
+    say("[batch-steady] 3 cavities to res < 1e-6")
+    b = hosc.Batch(plist)
+    b.init_fields(seeds)
+    binfo = b.run_to_steady(tol, cap)
+    steps = []
+    for i, p in enumerate(plist):
+        s = hosc.Solver(p)
+        s.init_fields(seeds[i], 1e-3)
+        si = s.run_to_steady(tol, cap)
+        g = s.get_state()
+        gb = b.cavities[i].get_state()
+        say(f"[batch-steady] cavity {i}: steps batch {binfo[i].step} solo {si.step}, res {max(binfo[i].res):.2e}")
+        assert binfo[i].step == si.step and max(si.res) < tol
+        assert binfo[i].res == si.res
+        for f in ("u", "v", "w", "T", "p"):
+            assert np.array_equal(gb[f], g[f]), (i, f)
+        steps.append(si.step)
+        s.close()
+    assert len(set(steps)) == 3        # they really finish at different steps
+    with pytest.raises(hosc.HoscError) as ei:
+        b.run_to_steady(0.0, 10)
+    assert ei.value.name == "HOSC_E_ARG"
+    b.close()
