@@ -257,6 +257,27 @@ hosc_status hosc_transport_step(hosc_solver *s, const double *L, const double *G
                                 const double *Ip, const double *Ep, const double *chi, double *chi_new,
                                 hosc_step_info *info);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the diagnostics of
+ * hosc_diagnostics (same kernels, same values) computed from the caller's device
+ * fields, with every intermediate (Simpson weights, local and z-averaged Nusselt
+ * numbers, partial sums) in one fixed device array of the library of 2.7 MB, held
+ * on each device the library is used on until the process ends.  Allocates
+ * nothing, never synchronises: launches only, on `stream` (a stream of the
+ * current device; the first call on a device looks up the array's address there).
+ * p: the cavity's parameters, validated as by hosc_create; N <= 257 (HOSC_E_ARG
+ * above: that is the array's limit); n_pl, i2_floor and phi are used.
+ * d_u, d_v, d_w, d_theta: device N^3 fields of one state (x fastest), not modified.
+ * d_out: device, 10 doubles: the hosc_diag fields in declaration order.
+ * d_nuavg_hot, d_nuavg_cold: device N doubles each (Nu_avg(z_k)), or NULL.
+ * Every call on a device shares its array, whose contents are the last call's and
+ * are fully rewritten by the next: calls that overlap on one device (different
+ * streams, or host threads) race; order them on one stream.  Errors (HOSC_E_ARG,
+ * HOSC_E_DEVICE) are reported through hosc_last_error(NULL). */
+hosc_status hosc_diagnostics_noalloc(const hosc_params *p, const double *d_u, const double *d_v, const double *d_w,
+                                     const double *d_theta, double *d_out, double *d_nuavg_hot, double *d_nuavg_cold,
+                                     hipStream_t stream);
+
 /* Switch kernel timing on (on != 0, counters cleared) or off.  Timing adds two
  * event records per timed launch on the solver's stream. */
 hosc_status hosc_perf_enable(hosc_solver *s, int32_t on);

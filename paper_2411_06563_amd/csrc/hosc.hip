@@ -14,6 +14,7 @@
 #include <chrono>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -2933,3 +2934,100 @@ hosc_status hosc_server_stats_get(const hosc_server *v, hosc_server_stats *st)
 const char *hosc_server_last_error(const hosc_server *v) { return v ? v->err.c_str() : g_create_error.c_str(); }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Diagnostics without allocation (hosc_diagnostics_noalloc): every intermediate of
+// the Nusselt and entropy reductions lives in one fixed device array of the
+// library, sized for N <= kNoAllocMaxN.  In host code `scratch` names a host-side
+// stand-in, not the device array: its device address is taken once per device with
+// hipGetSymbolAddress, and only that address is ever passed to a kernel.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kNoAllocMaxN = 257;
+constexpr size_t kNoAllocRound = 32;   // doubles per 256 bytes
+constexpr size_t round32(size_t n) { return (n + kNoAllocRound - 1) / kNoAllocRound * kNoAllocRound; }
+constexpr size_t kNaN = kNoAllocMaxN;
+constexpr size_t kNaOffWq = 0;
+constexpr size_t kNaOffAvh = kNaOffWq + round32(kNaN);
+constexpr size_t kNaOffAvc = kNaOffAvh + round32(kNaN);
+constexpr size_t kNaOffNuh = kNaOffAvc + round32(kNaN);
+constexpr size_t kNaOffNuc = kNaOffNuh + round32(kNaN * kNaN);
+constexpr size_t kNaOffNu = kNaOffNuc + round32(kNaN * kNaN);
+constexpr size_t kNaOffEnt = kNaOffNu + round32(8);
+constexpr size_t kNaOffPart = kNaOffEnt + round32(8);
+// entropy partial sums: 3 per block of the all-node launch (256 nodes per block)
+constexpr size_t kNaDoubles = kNaOffPart + round32((kNaN * kNaN * kNaN + 255) / 256 * 3);
+}  // namespace
+
+static __device__ __align__(256) double scratch[kNaDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+double *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, resolved on the first call there.
+hosc_status scratch_on_current_device(double **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(nullptr, HOSC_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(nullptr, HOSC_E_DEVICE, "device ordinal beyond 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(nullptr, HOSC_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = static_cast<double *>(ptr);
+    }
+    *out = g_scratch_dev[dev];
+    return HOSC_OK;
+}
+}  // namespace
+
+extern "C" hosc_status hosc_diagnostics_noalloc(const hosc_params *p, const double *d_u, const double *d_v,
+                                                const double *d_w, const double *d_theta, double *d_out,
+                                                double *d_nuavg_hot, double *d_nuavg_cold, hipStream_t stream)
+{
+    const char *err = check_params(p);
+    if (err) return fail(nullptr, HOSC_E_ARG, err);
+    if (p->N > kNoAllocMaxN)
+        return fail(nullptr, HOSC_E_ARG, "N above the no-allocation maximum of " + std::to_string(kNoAllocMaxN));
+    if (!d_u || !d_v || !d_w || !d_theta || !d_out)
+        return fail(nullptr, HOSC_E_ARG, "d_u, d_v, d_w, d_theta and d_out are required");
+    double *base = nullptr;
+    hosc_status r = scratch_on_current_device(&base);
+    if (r) return r;
+    const Geo g = make_geo(p->N);
+    const Launch L = make_launch(g);
+    Phys ph{};
+    ph.Ra = p->Ra;
+    ph.Pr = p->Pr;
+    ph.dt = p->dt;
+    ph.theta_hot = p->theta_hot;
+    ph.theta_cold = p->theta_cold;
+    ph.theta_ref = p->theta_ref;
+    ph.i2_floor = p->i2_floor;
+    ph.ex = 0.5 * (p->n_pl - 1.0);
+    ph.lambda = p->lambda > 0.0 ? p->lambda : g.h * g.h / (3.0 * p->dt);
+    ph.phi = p->phi;
+    double *wq = base + kNaOffWq, *nuh = base + kNaOffNuh, *nuc = base + kNaOffNuc;
+    double *nu = base + kNaOffNu, *ent = base + kNaOffEnt, *part = base + kNaOffPart;
+    double *avh = d_nuavg_hot ? d_nuavg_hot : base + kNaOffAvh;
+    double *avc = d_nuavg_cold ? d_nuavg_cold : base + kNaOffAvc;
+    const int N = g.N;
+    k_simpson_weights<<<(N + 255) / 256, 256, 0, stream>>>(N, wq);
+    dim3 b2(16, 16), g2((N + 15) / 16, (N + 15) / 16);
+    k_nu_local<<<g2, b2, 0, stream>>>(g, d_theta, nuh, nuc);
+    k_nu_avg<<<N, 256, 0, stream>>>(g, wq, nuh, nuc, avh, avc);
+    k_nu_final<<<1, 1024, 0, stream>>>(g, wq, avh, avc, nuh, nu);
+    k_entropy<<<L.grd_all, L.blk_all, 0, stream>>>(g, ph, wq, d_u, d_v, d_w, d_theta, nullptr, nullptr, nullptr,
+                                                     part);
+    k_reduce<<<1, 1024, 0, stream>>>(part, (int)L.nb_all, 3, 0, ent);
+    k_diag_pack<<<1, 64, 0, stream>>>(nu, ent, d_out);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(nullptr, HOSC_E_DEVICE, std::string("launch of the diagnostics: ") + hipGetErrorString(e));
+    return HOSC_OK;
+}

@@ -1525,6 +1525,51 @@ __global__ void __launch_bounds__(1024) k_nu_final(Geo g, const double *__restri
 // eta_out (optional) receives eta, computed exactly as k_eta computes it: run at
 // the end of a step on the new velocities, it supplies the next step's viscosity
 // (with eta_prev, relaxed: relax eta + (1 - relax) eta_prev).
+// Composite Simpson weights on the N nodes of [0, 1] (Simpson's 3/8 rule on the
+// last three intervals when N-1 is odd), one thread per node, each weight summed
+// from its panels in the order the host builds them (left panel's end first), so
+// the values are bitwise those of the host table.
+__global__ void __launch_bounds__(256) k_simpson_weights(int N, double *__restrict__ wq)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N) return;
+    const double h = 1.0 / (N - 1);
+    const int nint = N - 1;
+    const int n13 = (nint % 2 == 0) ? nint : nint - 3;
+    double w = 0.0;
+    if (q <= n13) {
+        if (q & 1) {
+            w += 4.0 * h / 3.0;
+        } else {
+            if (q >= 2) w += h / 3.0;        // right end of the panel [q-2, q]
+            if (q + 2 <= n13) w += h / 3.0;  // left end of the panel [q, q+2]
+        }
+    }
+    if (n13 != nint && q >= n13) {
+        const int r = q - n13;
+        w += (r == 0 || r == 3) ? 3.0 * h / 8.0 : 9.0 * h / 8.0;
+    }
+    wq[q] = w;
+}
+
+// The hosc_diag record (declaration order) from the Nusselt outputs nu[0..4] and
+// the entropy sums ent[0..2], with the arithmetic of the host's record.
+__global__ void k_diag_pack(const double *__restrict__ nu, const double *__restrict__ ent, double *__restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double e_total = ent[0] + ent[1];
+    out[0] = nu[0];
+    out[1] = nu[1];
+    out[2] = nu[2];
+    out[3] = nu[3];
+    out[4] = e_total;
+    out[5] = ent[0];
+    out[6] = ent[1];
+    out[7] = e_total > 0.0 ? ent[0] / e_total : 1.0;
+    out[8] = ent[2];
+    out[9] = nu[4];
+}
+
 __global__ void __launch_bounds__(256) k_entropy(Geo g, Phys P, const double *__restrict__ wq,
                                                  const double *__restrict__ u, const double *__restrict__ v,
                                                  const double *__restrict__ w, const double *__restrict__ T,

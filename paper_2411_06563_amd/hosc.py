@@ -119,6 +119,7 @@ def lib() -> ctypes.CDLL:
     L.hosc_probe.argtypes = [vp, _dp, ctypes.c_int32, _dp]
     L.hosc_debug_assemble.argtypes = [vp, _dp, _dp, _dp, _dp, _dp]
     L.hosc_transport_step.argtypes = [vp] + [_dp] * 12 + [ctypes.POINTER(CStepInfo)]
+    L.hosc_diagnostics_noalloc.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp]
     L.hosc_perf_enable.argtypes = [vp, ctypes.c_int32]
     L.hosc_perf_get.argtypes = [vp, ctypes.POINTER(CPerf)]
     L.hosc_copy_bandwidth.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_double)]
@@ -189,6 +190,20 @@ def workspace_bytes(p: CParams) -> int:
     n = ctypes.c_size_t(0)
     _check(lib().hosc_workspace_bytes(ctypes.byref(p), ctypes.byref(n)))
     return n.value
+
+
+def diagnostics_noalloc(p: CParams, u, v, w, T, out, nuavg_hot=None, nuavg_cold=None, stream=None):
+    """hosc_diagnostics_noalloc on device tensors (float64, N^3 fields; out holds 10
+    doubles; nuavg_* N doubles or None): launches only, on ``stream`` (default: torch's
+    current stream of the tensors' device)."""
+    import torch
+    for t in (u, v, w, T, out) + tuple(x for x in (nuavg_hot, nuavg_cold) if x is not None):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("device float64 contiguous tensors are required")
+    st = stream if stream is not None else torch.cuda.current_stream(u.device)
+    ptr = [ctypes.c_void_p(t.data_ptr()) if t is not None else None for t in (u, v, w, T, out, nuavg_hot, nuavg_cold)]
+    r = lib().hosc_diagnostics_noalloc(ctypes.byref(p), *ptr, ctypes.c_void_p(st.cuda_stream))
+    _check(r)
 
 
 def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 10, device: str = "cuda:0") -> float:
