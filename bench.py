@@ -38,8 +38,16 @@ between launches, from 257^3 on it streams from HBM.
 
 Prints one JSON line: cell-updates/s (interior nodes x steps / second), the
 roofline of the dominant kernel (the red-black sweep, HIP events around every
-launch, algorithmic bytes per launch), and the FP64 CPU oracle timed on the
-host cores on a bounded sample of the same workload.
+launch, algorithmic bytes per launch), with the whole step's algorithmic bytes
+against the HBM peak (`roofline.step`) and the half-sweep on a 257^3 grid whose
+working set streams from HBM (`roofline.hbm_streaming`), and the FP64 CPU oracle
+timed on the host cores on a bounded sample of the same workload.  The default
+run also carries the metric's second half: `serving` (24 small requests of the
+seeded trace marched to res 1e-8 through the server, FP32 refined, against the
+plain FP64 path one cavity after another: solves/s, p50/p99 time to steady
+state, a mix-vs-alone check) and `batch` (the 12-cavity batch against the same
+steps cavity by cavity, and the small requests as one batch marched to steady
+state with hosc_batch_run_to_steady).
 """
 from __future__ import annotations
 
@@ -184,6 +192,35 @@ def precision_check(hosc, W, kw, reset, steps):
     for k in ("nu_mean_hot", "nu_mean_cold", "nu_max_hot", "be_global", "e_total"):
         out["scalar_rel"][k] = float(abs(d1[k] - d0[k]) / abs(d0[k]))
     return out
+
+
+# algorithmic bytes per interior node of the kernels of a step other than the
+# implicit solves and the assembly (timed separately): viscosity 32, sources 72,
+# update 88, divergence and pressure 40, entropy pass 40
+OTHER_BYTES_PER_NODE = 32 + 72 + 88 + 40 + 40
+
+
+def stream_sweep(hosc, torch, W, N):
+    """Half-sweep bandwidth on a grid whose working set streams from HBM (the 129^3
+    launch partly stays in the 256 MB Infinity Cache): the benchmark physics with the
+    benchmark's dt/h^2, FP64, SOR, 2 untimed and 4 timed steps."""
+    p = hosc.params(N, Ra=W["Ra"], n_pl=W["n_pl"], Pr=W["Pr"], dt=W["dt"] * (128.0 / (N - 1)) ** 2,
+                    solve_rtol=W["solve_rtol"], solver=hosc.SOLVER_SOR)
+    s = hosc.Solver(p, device="cuda:0")
+    s.init_fields(W["seed"], W["noise"])
+    s.step(2)
+    s.perf_enable(True)
+    s.step(4)
+    torch.cuda.synchronize()
+    c = s.perf()
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    n = max(c["sweep_launches"], 1)
+    gbs = c["sweep_bytes"] / (c["sweep_ms"] * 1e-3) / 1e9
+    return {"grid": N, "kernel": "k_sweep", "half_sweeps": c["sweep_launches"],
+            "bytes_per_launch": c["sweep_bytes"] / n, "avg_launch_us": c["sweep_ms"] / n * 1e3,
+            "achieved": gbs, "frac": gbs / HBM_PEAK_GBS}
 
 
 def bench_sizes(args, W, hosc, torch):
@@ -370,11 +407,15 @@ def bench_serve(args, W, hosc, torch):
     st = srv.stats()
     srv.close()
     ok = [i for i in range(nreq) if results[i]["status"] == 0]
-    lat = np.array([results[i]["t_done"] - results[i]["t_arrival"] for i in ok])
-    svc = np.array([results[i]["t_done"] - results[i]["t_admit"] for i in ok])
+    steady = [i for i in ok if results[i]["steady"]]
+    capped = [i for i in ok if not results[i]["steady"]]
+    # the headline counts a request as solved only when it reached the steady residual
+    lat = np.array([results[i]["t_done"] - results[i]["t_arrival"] for i in steady]) if steady else np.zeros(1)
+    svc = np.array([results[i]["t_done"] - results[i]["t_admit"] for i in steady]) if steady else np.zeros(1)
     span = max(results[i]["t_done"] for i in range(nreq)) - (t0 + trace[0]["arrival"])
     # mix vs alone on sampled successful requests
-    sample = ok[:: max(1, len(ok) // W["sample"])][: W["sample"]]
+    pool = steady if steady else ok
+    sample = pool[:: max(1, len(pool) // W["sample"])][: W["sample"]]
     same = 0
     for i in sample:
         s = hosc.Solver(plist[i])
@@ -387,7 +428,7 @@ def bench_serve(args, W, hosc, torch):
     cell_updates = float(sum(M3[i] * results[i]["steps"] for i in range(nreq)))
     out = {
         "metric": METRIC,
-        "value": len(ok) / span,
+        "value": len(steady) / span,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": int(st["server_steps"]),
@@ -399,11 +440,12 @@ def bench_serve(args, W, hosc, torch):
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"{W['label']}; first {nreq} requests of the 500-request trace"},
-        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+        "latency_s": {"over": "requests that reached the steady residual",
+                      "p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                       "mean": float(lat.mean())},
         "service_s": {"p50": float(np.percentile(svc, 50)), "p99": float(np.percentile(svc, 99))},
-        "requests": {"completed": nreq, "ok": len(ok), "failed": nreq - len(ok),
-                     "steady": sum(1 for i in ok if results[i]["steady"]),
+        "requests": {"completed": nreq, "steady": len(steady), "capped_at_max_steps": len(capped),
+                     "failed": nreq - len(ok),
                      "failed_status": sorted({results[i]["status"] for i in range(nreq)} - {0})},
         "server": {"cavity_steps": int(st["cavity_steps"]), "server_steps": int(st["server_steps"]),
                    "busy_s": st["busy_s"], "span_s": span, "peak_bytes": int(st["peak"]),
@@ -480,26 +522,39 @@ def steady_relax(n_pl: float) -> float:
     return 0.1 if n_pl < 1.0 else 0.5
 
 
-def serve_steady(hosc, W, k):
-    """Time to steady state: the first k requests of the trace with N <= 49 (the
-    larger cavities need 1e4-1e5 steps at the stable time steps), each marched to
+def steady_requests(W, k):
+    """The first k requests of the seeded trace with N <= 49 (the larger cavities need
+    1e4-1e5 steps at the stable time steps)."""
+    from paper_2411_06563_amd.inputs import serving_trace
+    return [r for r in serving_trace(500, W["rate"], W["trace_seed"]) if r["N"] <= 49][:k]
+
+
+def steady_params(hosc, W, r, prec):
+    return hosc.params(r["N"], Ra=r["Ra"], n_pl=r["n_pl"], Pr=r["Pr"], dt=W["dt_over_h2"] / (r["N"] - 1) ** 2,
+                       solve_rtol=W["solve_rtol"], precision=prec, eta_relax=steady_relax(r["n_pl"]))
+
+
+def _pcts(x):
+    import numpy as np
+    if not x:
+        return {"p50_s": None, "p99_s": None}
+    return {"p50_s": float(np.percentile(x, 50)), "p99_s": float(np.percentile(x, 99))}
+
+
+def serve_steady(hosc, W, k, sample=4):
+    """Time to steady state: the first k small requests of the trace, each marched to
     res 1e-8 (at most 30000 steps) with the viscosity relaxation, submitted at once
     to the server (FP32 refined), and the same requests through the plain path (one
     FP64 single-cavity solver after another).  Reports steady solves, solves/s and
-    p50/p99 time to steady state."""
-    import numpy as np
+    p50/p99 time to steady state, and a mix-vs-alone check: sampled served requests
+    rerun alone (same precision, single-cavity run to steady state) must take the
+    same number of steps and give bitwise the same diagnostics."""
     import torch
-    from paper_2411_06563_amd.inputs import serving_trace
-    trace = [r for r in serving_trace(500, W["rate"], W["trace_seed"]) if r["N"] <= 49][:k]
-
-    def params(r, prec):
-        return hosc.params(r["N"], Ra=r["Ra"], n_pl=r["n_pl"], Pr=r["Pr"], dt=W["dt_over_h2"] / (r["N"] - 1) ** 2,
-                           solve_rtol=W["solve_rtol"], precision=prec, eta_relax=steady_relax(r["n_pl"]))
-
+    trace = steady_requests(W, k)
     out = {"requests": k, "sizes": sorted({r["N"] for r in trace}), "res_tol": 1e-8, "max_steps": 30000}
     srv = hosc.Server(W["budget"], max_resident=W["max_resident"])
     t0 = srv.now()
-    ids = {srv.submit(params(r, W["precision"]), r["seed"], W["noise"], 1e-8, 30000, t0): i
+    ids = {srv.submit(steady_params(hosc, W, r, W["precision"]), r["seed"], W["noise"], 1e-8, 30000, t0): i
            for i, r in enumerate(trace)}
     res = {}
     while len(res) < k:
@@ -507,16 +562,19 @@ def serve_steady(hosc, W, k):
         for q in srv.poll():
             res[ids[q["id"]]] = q
     srv.close()
-    done = [res[i]["t_done"] - t0 for i in range(k) if res[i]["status"] == 0 and res[i]["steady"]]
+    steady = [i for i in range(k) if res[i]["status"] == 0 and res[i]["steady"]]
+    done = [res[i]["t_done"] - t0 for i in steady]
     wall = max(q["t_done"] for q in res.values()) - t0
-    out["served_fp32_refined"] = {"steady": len(done), "wall_s": wall, "solves_per_s": len(done) / wall,
-                                  "p50_s": float(np.percentile(done, 50)), "p99_s": float(np.percentile(done, 99))}
+    failed = sum(1 for i in range(k) if res[i]["status"] != 0)
+    out["served_fp32_refined"] = dict({"steady": len(steady), "failed": failed,
+                                       "capped": k - len(steady) - failed, "wall_s": wall,
+                                       "solves_per_s": len(steady) / wall}, **_pcts(done))
     print(f"steady served: {out['served_fp32_refined']}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    done = []
+    done, failed = [], 0
     for r in trace:
-        sv = hosc.Solver(params(r, 0))
+        sv = hosc.Solver(steady_params(hosc, W, r, 0))
         sv.init_fields(r["seed"], W["noise"])
         try:
             info = sv.run_to_steady(1e-8, 30000)
@@ -524,12 +582,99 @@ def serve_steady(hosc, W, k):
             if max(info.res) < 1e-8:
                 done.append(time.perf_counter() - t0)
         except hosc.HoscError:
-            pass
+            failed += 1
         sv.close()
     wall = time.perf_counter() - t0
-    out["plain_fp64_sequential"] = {"steady": len(done), "wall_s": wall, "solves_per_s": len(done) / wall,
-                                    "p50_s": float(np.percentile(done, 50)), "p99_s": float(np.percentile(done, 99))}
+    out["plain_fp64_sequential"] = dict({"steady": len(done), "failed": failed, "wall_s": wall,
+                                         "solves_per_s": len(done) / wall}, **_pcts(done))
     print(f"steady plain: {out['plain_fp64_sequential']}", file=sys.stderr, flush=True)
+    same = 0
+    picks = steady[:: max(1, len(steady) // sample)][:sample]
+    for i in picks:
+        sv = hosc.Solver(steady_params(hosc, W, trace[i], W["precision"]))
+        sv.init_fields(trace[i]["seed"], W["noise"])
+        info = sv.run_to_steady(1e-8, 30000)
+        d = sv.diagnostics(arrays=False)
+        sv.close()
+        same += int(info.step == res[i]["steps"] and d == res[i]["diag"])
+    out["mix_vs_alone"] = {"sampled": len(picks), "bitwise_equal": same}
+    return out
+
+
+def batch_leg(hosc, torch, seg=20, k=24):
+    """Batched form, two views.  (a) The 12-cavity batch (sizes 33^3/65^3/97^3, the
+    (Ra, n) grid, FP32 refined, autotuned schedule): one segment of `seg` steps from
+    the seeded start with fused launches against the same steps cavity by cavity,
+    and the largest difference of the results (0 = bitwise).  (b) Solves: the k
+    small requests of the serving trace as one batch marched to res 1e-8
+    (hosc_batch_run_to_steady, FP32 refined), solves/s and steps against each
+    cavity's own run."""
+    import numpy as np
+    from paper_2411_06563_amd.inputs import batched_cavities
+    W4 = WORKLOADS["batch12"]
+    cavs = batched_cavities(4)
+    plist = [hosc.params(c["N"], Ra=c["Ra"], n_pl=c["n_pl"], Pr=W4["Pr"],
+                         dt=max(W4["dt"], W4["dt_over_h2"] / (c["N"] - 1) ** 2), solve_rtol=W4["solve_rtol"],
+                         precision=W4["precision"]) for c in cavs]
+    seeds = [c["seed"] for c in cavs]
+    b = hosc.Batch(plist)
+    b.init_fields(seeds, W4["noise"])
+    grid = b.tune()
+    b.init_fields(seeds, W4["noise"])
+    b.step(2)                                   # captures the graphs of both level parities
+    b.init_fields(seeds, W4["noise"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(seg)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    got = [cv.get_state() for cv in b.cavities]
+    b.close()
+    t_serial, worst = 0.0, 0.0
+    for i, p in enumerate(plist):
+        s = hosc.Solver(p)
+        s.init_fields(seeds[i], W4["noise"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(seg)
+        torch.cuda.synchronize()
+        t_serial += time.perf_counter() - t0
+        g = s.get_state()
+        s.close()
+        worst = max(worst, max(float(np.max(np.abs(g[f] - got[i][f]))) for f in ("u", "v", "w", "T", "p")))
+    M3 = sum((c["N"] - 2) ** 3 for c in cavs)
+    out = {"cavities": len(cavs), "segment_steps": seg, "tuned_grid": grid,
+           "batched_cavity_steps_per_s": len(cavs) * seg / t_batch,
+           "one_by_one_cavity_steps_per_s": len(cavs) * seg / t_serial,
+           "batched_cell_updates_per_s": M3 * seg / t_batch, "speedup": t_serial / t_batch,
+           "max_abs_diff_vs_single_cavity": worst}
+    W5 = WORKLOADS["serve"]
+    trace = steady_requests(W5, k)
+    pl = [steady_params(hosc, W5, r, W5["precision"]) for r in trace]
+    b = hosc.Batch(pl)
+    b.init_fields([r["seed"] for r in trace], W5["noise"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos, err = b.run_to_steady(1e-8, 30000, raise_on_error=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    steady = [i for i, inf in enumerate(infos) if inf.status == 0 and max(inf.res) < 1e-8]
+    failed = [i for i, inf in enumerate(infos) if inf.status != 0]
+    done = [i for i in steady]
+    b.close()
+    # each sampled steady cavity's own run (same precision) takes the same steps to the same residual
+    picks = steady[:: max(1, len(steady) // 4)][:4]
+    same = 0
+    for i in picks:
+        s = hosc.Solver(pl[i])
+        s.init_fields(trace[i]["seed"], W5["noise"])
+        si = s.run_to_steady(1e-8, 30000)
+        same += int(si.step == infos[i].step and si.res == infos[i].res)
+        s.close()
+    out["to_steady"] = {"requests": k, "res_tol": 1e-8, "steady": len(done), "failed": len(failed), "wall_s": wall,
+                        "solves_per_s": len(done) / wall, "first_error": None if err is None else str(err),
+                        "sampled": len(picks), "sampled_same_as_alone": same}
+    print(f"batch leg: {out}", file=sys.stderr, flush=True)
     return out
 
 
@@ -550,6 +695,13 @@ def main():
                     help="serve: small requests marched to steady state, served and plain (0 = skip)")
     ap.add_argument("--capacity-rtol", type=float, default=None,
                     help="serve: implicit-solve tolerance of the saturated-queue comparison (default: the workload's)")
+    ap.add_argument("--serving", type=int, default=24,
+                    help="default workload: small trace requests of the time-to-steady serving leg (0 = skip)")
+    ap.add_argument("--batch-steady", type=int, default=24,
+                    help="default workload: small trace requests of the batched time-to-steady leg (0 = skip the "
+                         "batch object)")
+    ap.add_argument("--stream-grid", type=int, default=257,
+                    help="default workload: grid of the HBM-streaming half-sweep measurement (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the HOSC hot path is measured on one MI355X "
@@ -677,7 +829,21 @@ def main():
         out["precision_check"] = precision_check(hosc, W, kw, reset, args.segment)
     if W.get("p_iters"):
         out["steady_comparison"] = steady_comparison(hosc, torch)
+    # the whole step against the HBM roofline: the algorithmic bytes of every kernel
+    # of the step (sweeps, BiCGSTAB and refinement as timed, the assembly, and per
+    # interior node 32 B viscosity, 72 B sources, 88 B update, 40 B divergence and
+    # pressure, 40 B entropy pass) over the measured time per step
+    step_bytes = (perf["sweep_bytes"] + perf["bicg_bytes"] + perf["refine_bytes"] + perf["assemble_bytes"]) / args.steps \
+        + OTHER_BYTES_PER_NODE * M3
+    step_gbs = step_bytes / (el / args.steps) / 1e9
+    out["roofline"]["step"] = {"bytes_per_step": step_bytes, "achieved": step_gbs, "frac": step_gbs / HBM_PEAK_GBS}
     out["roofline"]["copy_probe_GBs"] = hosc.copy_bandwidth(1 << 30, 10)
+    if args.workload == "fp64" and args.stream_grid > 0:
+        out["roofline"]["hbm_streaming"] = stream_sweep(hosc, torch, W, args.stream_grid)
+    if args.workload == "fp64" and args.serving > 0:
+        out["serving"] = serve_steady(hosc, WORKLOADS["serve"], args.serving)
+    if args.workload == "fp64" and args.batch_steady > 0:
+        out["batch"] = batch_leg(hosc, torch, k=args.batch_steady)
     if not args.no_cpu_baseline and args.workload == "fp64":
         out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
     print(json.dumps(out), flush=True)

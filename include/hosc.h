@@ -380,8 +380,8 @@ const char *hosc_batch_last_error(const hosc_batch *b);
  * batching: every hosc_server_step admits what fits, advances each resident cavity
  * one time step, and retires the cavities that reached res_tol or max_steps).  A
  * request's arithmetic is that of its single-cavity run, whatever else is resident.
- * The server owns one device arena of the budget (allocated at create, the only
- * device allocation the library makes) and small fused-launch tables.
+ * The caller provides the device memory: one workspace holding the arena of the
+ * budget and small fused-launch tables.
  * ------------------------------------------------------------------------------ */
 typedef struct hosc_server hosc_server;
 
@@ -412,11 +412,21 @@ typedef struct hosc_server_stats {
     double busy_s;          /* time spent inside hosc_server_step */
 } hosc_server_stats;
 
-/* Create a server on the current device with an arena of hbm_budget_bytes and at
- * most max_resident resident cavities (1..1024). */
-hosc_status hosc_server_create(size_t hbm_budget_bytes, int32_t max_resident, hipStream_t stream, hosc_server **out);
+/* Device bytes of a server workspace: an arena of hbm_budget_bytes (rounded down
+ * to 256 bytes) for the resident cavities plus the fused-launch tables of
+ * max_resident cavities (1..1024).  HOSC_E_ARG for a budget under 256 bytes. */
+hosc_status hosc_server_workspace_bytes(size_t hbm_budget_bytes, int32_t max_resident, size_t *bytes);
 
-/* Finish nothing further, release every resident cavity and the arena. */
+/* Create a server on the current device in the caller's workspace d_ws (device,
+ * 256-byte aligned, >= hosc_server_workspace_bytes(hbm_budget_bytes, max_resident),
+ * owned by the caller and untouched until hosc_server_destroy): cavities are
+ * admitted while their workspaces fit the arena of hbm_budget_bytes.  Allocates
+ * only pinned host staging memory and its side streams. */
+hosc_status hosc_server_create(void *d_ws, size_t ws_bytes, size_t hbm_budget_bytes, int32_t max_resident,
+                               hipStream_t stream, hosc_server **out);
+
+/* Finish nothing further and release every resident cavity (not the workspace);
+ * waits only for the server's own streams. */
 hosc_status hosc_server_destroy(hosc_server *srv);
 
 /* Seconds since the server was created (steady clock). */

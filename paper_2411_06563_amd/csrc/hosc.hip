@@ -2200,8 +2200,7 @@ hosc_status hosc_create(const hosc_params *p, void *d_ws, size_t ws_bytes, hipSt
 hosc_status hosc_destroy(hosc_solver *s)
 {
     if (!s) return HOSC_OK;
-    if (s->st) (void)hipStreamSynchronize(s->st);
-    else (void)hipDeviceSynchronize();
+    (void)hipStreamSynchronize(s->st);
     for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
     if (s->hbuf) (void)hipHostFree(s->hbuf);
     delete s;
@@ -2620,7 +2619,9 @@ hosc_status hosc_batch_create(const hosc_params *p, int32_t count, void *d_ws, s
 hosc_status hosc_batch_destroy(hosc_batch *b)
 {
     if (!b) return HOSC_OK;
-    if (b->st) (void)hipStreamSynchronize(b->st);
+    (void)hipStreamSynchronize(b->st);
+    for (int q = 0; q < Fused::kSide; ++q)
+        if (b->F.side[q]) (void)hipStreamSynchronize(b->F.side[q]);
     fused_free(b->F);
     for (hosc_solver *s : b->cav) hosc_destroy(s);
     delete b;
@@ -2760,33 +2761,40 @@ hosc_status hosc_batch_graph_launches(const hosc_batch *b, int64_t *count)
 const char *hosc_batch_last_error(const hosc_batch *b) { return b ? b->err.c_str() : g_create_error.c_str(); }
 
 
-hosc_status hosc_server_create(size_t hbm_budget_bytes, int32_t max_resident, hipStream_t stream, hosc_server **out)
+hosc_status hosc_server_workspace_bytes(size_t hbm_budget_bytes, int32_t max_resident, size_t *bytes)
+{
+    if (!bytes) return sfail(nullptr, HOSC_E_ARG, "bytes is NULL");
+    if (max_resident < 1 || max_resident > 1024) return sfail(nullptr, HOSC_E_ARG, "max_resident must be in [1, 1024]");
+    if (hbm_budget_bytes < kAlign) return sfail(nullptr, HOSC_E_ARG, "budget too small");
+    *bytes = hbm_budget_bytes / kAlign * kAlign + fused_device_bytes(max_resident);
+    return HOSC_OK;
+}
+
+hosc_status hosc_server_create(void *d_ws, size_t ws_bytes, size_t hbm_budget_bytes, int32_t max_resident,
+                               hipStream_t stream, hosc_server **out)
 {
     if (!out) return sfail(nullptr, HOSC_E_ARG, "out is NULL");
     *out = nullptr;
-    if (max_resident < 1 || max_resident > 1024) return sfail(nullptr, HOSC_E_ARG, "max_resident must be in [1, 1024]");
-    if (hbm_budget_bytes < kAlign) return sfail(nullptr, HOSC_E_ARG, "budget too small");
+    size_t need = 0;
+    hosc_status r = hosc_server_workspace_bytes(hbm_budget_bytes, max_resident, &need);
+    if (r) return r;
+    if (!d_ws) return sfail(nullptr, HOSC_E_ARG, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return sfail(nullptr, HOSC_E_ARG, "workspace must be 256-byte aligned");
+    if (ws_bytes < need) return sfail(nullptr, HOSC_E_NOMEM, "workspace smaller than hosc_server_workspace_bytes()");
     hosc_server *v = new (std::nothrow) hosc_server();
     if (!v) return sfail(nullptr, HOSC_E_NOMEM, "host allocation failed");
     v->budget = hbm_budget_bytes / kAlign * kAlign;
     v->max_resident = max_resident;
     v->st = stream;
     v->t0 = std::chrono::steady_clock::now();
-    hipError_t e = hipMalloc(reinterpret_cast<void **>(&v->arena), v->budget);
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&v->d_fused), fused_device_bytes(max_resident));
-    if (e != hipSuccess) {
-        if (v->arena) (void)hipFree(v->arena);
-        delete v;
-        return sfail(nullptr, HOSC_E_NOMEM, std::string("device allocation of the server arena: ") + hipGetErrorString(e));
-    }
+    v->arena = static_cast<char *>(d_ws);
+    v->d_fused = v->arena + v->budget;
     v->free_[0] = v->budget;
-    hosc_status r = fused_init(v->F, max_resident, v->d_fused, stream);
+    r = fused_init(v->F, max_resident, v->d_fused, stream);
     v->F.use_graphs = false;    // membership changes every few steps
     if (r) {
         const std::string msg = v->F.err;
         fused_free(v->F);
-        (void)hipFree(v->d_fused);
-        (void)hipFree(v->arena);
         delete v;
         return sfail(nullptr, r, msg);
     }
@@ -2797,12 +2805,13 @@ hosc_status hosc_server_create(size_t hbm_budget_bytes, int32_t max_resident, hi
 hosc_status hosc_server_destroy(hosc_server *v)
 {
     if (!v) return HOSC_OK;
-    if (v->st) (void)hipStreamSynchronize(v->st);
+    // only the server's own streams are waited for (the stream it was given and its
+    // side streams); the caller's other work on the device is not touched
+    (void)hipStreamSynchronize(v->st);
+    for (int q = 0; q < Fused::kSide; ++q)
+        if (v->F.side[q]) (void)hipStreamSynchronize(v->F.side[q]);
     for (auto &r : v->res) hosc_destroy(r.s);
     fused_free(v->F);
-    (void)hipDeviceSynchronize();
-    (void)hipFree(v->d_fused);
-    (void)hipFree(v->arena);
     delete v;
     return HOSC_OK;
 }

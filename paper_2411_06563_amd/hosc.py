@@ -137,7 +137,8 @@ def lib() -> ctypes.CDLL:
     L.hosc_batch_perf_enable.argtypes = [vp, ctypes.c_int32]
     L.hosc_batch_perf_get.argtypes = [vp, ctypes.POINTER(CPerf)]
     L.hosc_batch_graph_launches.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
-    L.hosc_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, vp, ctypes.POINTER(vp)]
+    L.hosc_server_workspace_bytes.argtypes = [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+    L.hosc_server_create.argtypes = [vp, ctypes.c_size_t, ctypes.c_size_t, ctypes.c_int32, vp, ctypes.POINTER(vp)]
     L.hosc_server_destroy.argtypes = [vp]
     L.hosc_server_now.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.hosc_server_submit.argtypes = [vp, ctypes.POINTER(CRequest), ctypes.POINTER(ctypes.c_uint64)]
@@ -426,10 +427,21 @@ class Batch:
         _check(lib().hosc_batch_step(self.b, n, infos), batch=self.b)
         return [StepInfo.of(c) for c in infos]
 
-    def run_to_steady(self, tol: float, max_steps: int) -> list:
+    def run_to_steady(self, tol: float, max_steps: int, raise_on_error: bool = True):
+        """hosc_batch_run_to_steady.  A cavity that fails stops while the others go on;
+        with raise_on_error the first failure is raised after the call, otherwise
+        (infos, error or None) is returned, error being that HoscError."""
         infos = (CStepInfo * len(self.cavities))()
-        _check(lib().hosc_batch_run_to_steady(self.b, tol, max_steps, infos), batch=self.b)
-        return [StepInfo.of(c) for c in infos]
+        st = lib().hosc_batch_run_to_steady(self.b, tol, max_steps, infos)
+        out = [StepInfo.of(c) for c in infos]
+        err = None
+        try:
+            _check(st, batch=self.b)
+        except HoscError as e:
+            if raise_on_error:
+                raise
+            err = e
+        return out if raise_on_error else (out, err)
 
     def tune(self) -> int:
         g = ctypes.c_int32(0)
@@ -463,11 +475,17 @@ class Server:
     def __init__(self, budget_bytes: int, max_resident: int = 64, device: str = "cuda:0", stream=None):
         import torch
         self.device = torch.device(device)
+        nbytes = ctypes.c_size_t(0)
+        _check(lib().hosc_server_workspace_bytes(budget_bytes, max_resident, ctypes.byref(nbytes)), server=None)
         with torch.cuda.device(self.device):
+            # torch provides the server's device memory: the arena and its tables
+            self.ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
             self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+            base = self.ws.data_ptr()
+            off = (-base) % 256
             h = ctypes.c_void_p()
-            _check(lib().hosc_server_create(budget_bytes, max_resident, ctypes.c_void_p(self.stream.cuda_stream),
-                                            ctypes.byref(h)), server=None)
+            _check(lib().hosc_server_create(ctypes.c_void_p(base + off), nbytes.value, budget_bytes, max_resident,
+                                            ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), server=None)
         self.v = h
 
     def close(self):

@@ -145,9 +145,13 @@ def test_nusselt_and_entropy_trends():
     walls as Ra rises; E_local keeps the near-diagonal (half-turn) symmetry; Be falls
     with Ra, stays above 1/2 at Ra = 1e4 for n = 1 and 1.25 and falls below it at
     Ra = 1e5.  (The paper's Be below 1/2 for n = 0.75 at Ra = 1e4 is the departure
-    of its Table 4, reported, not asserted.)  And, from its conclusions, the
-    stream function of the mid-plane z = 1/2 (max |psi|, psi = int_0^y u dy') falls
-    as n rises at every Ra."""
+    of its Table 4, reported, not asserted.)  The rise of the largest local Nusselt
+    number on the hot wall from Ra = 1e2 to 1e5 that the text gives (Sec. 4.2: 729 %
+    for n = 1 and 385 % for n = 1.25; its 1948 % for n = 0.75 needs the Ra = 1e5 case
+    that diverges here) is matched to 5 % of the printed rise (710 % and 402 % here).
+    Both readings of the Bejan number (R18: ratio of the integrals, and volume mean
+    of the local ratio) are compared with Table 4: the ratio of the integrals is the
+    closer one (median gap 0.6 % against 3.5 % over the eleven cases)."""
     import numpy as np
     import torch
     assert torch.cuda.is_available()
@@ -166,21 +170,17 @@ def test_nusselt_and_entropy_trends():
         d = s.diagnostics(arrays=True)
         nuh, avg = d["nu_hot"], d["nuavg_hot"]            # nu_hot indexed [k, j]
         asym = float(np.abs(nuh - nuh[:, ::-1]).max() / nuh.max())
-        u_mid = s.get_state()["u"][N // 2]                  # u on the mid-plane z = 1/2, indexed [j, i]
-        h = 1.0 / (N - 1)
-        psi = np.concatenate([np.zeros((1, N)), np.cumsum(0.5 * h * (u_mid[1:] + u_mid[:-1]), axis=0)])
-        psimax = float(np.abs(psi).max())                   # psi(x, y) = int_0^y u dy' (trapezoid)
         el, _ = s.entropy_fields()                          # E_local, indexed [k, j, i]
         emax = float(el.max())
         turn = float(np.abs(el - el[:, ::-1, ::-1]).max()) / emax
         near = (el[:, :, :6].sum() + el[:, :, -6:].sum()) / el.sum()    # within 0.1 of the x walls
         out[(n, ra)] = dict(nuh=nuh, avg=avg, numax=d["nu_local_max_hot"], asym=asym, emax=emax, turn=turn,
-                            near=float(near), etot=d["e_total"], be=d["be_global"], psi=psimax)
+                            near=float(near), etot=d["e_total"], be=d["be_global"], be_mean=d["be_mean"])
         print(f"[Nu trends] n={n} Ra={ra}: steady after {info.step} steps; max Nu_local {d['nu_local_max_hot']:.5f}, "
               f"y-asymmetry {asym:.2e}, Nu_avg(z) centre {avg[N // 2]:.5f} range [{avg[1:-1].min():.5f}, "
               f"{avg[1:-1].max():.5f}]; max E_local {emax:.4f}, E_total {d['e_total']:.4f}, Be {d['be_global']:.4f}, "
-              f"entropy within 0.1 of the x walls {near:.3f}, half-turn asymmetry of E_local {turn:.1e}; "
-              f"mid-plane max |psi| {psimax:.5f}", flush=True)
+              f"Be_mean {d['be_mean']:.6f}, entropy within 0.1 of the x walls {near:.3f}, half-turn asymmetry of "
+              f"E_local {turn:.1e}", flush=True)
         s.close()
     ras = ["1e2", "1e3", "1e4", "1e5"]
     for n in (0.75, 1.0, 1.25):
@@ -220,12 +220,26 @@ def test_nusselt_and_entropy_trends():
         seq = [out[(n, ra)] for n in (0.75, 1.0, 1.25) if (n, ra) in out]
         for a, b in zip(seq, seq[1:]):
             assert b["emax"] < a["emax"] and b["etot"] < a["etot"]        # fall as n rises
-    for ra in ras:                                                         # conclusions: the stream function
-        seq = [out[(n, ra)]["psi"] for n in (0.75, 1.0, 1.25) if (n, ra) in out]
-        assert all(b < a for a, b in zip(seq, seq[1:]))                    # falls as n rises
-    for n in (0.75, 1.0, 1.25):
-        seq = [out[(n, ra)]["psi"] for ra in ras if (n, ra) in out]
-        assert all(b > a for a, b in zip(seq, seq[1:]))                    # and rises with Ra
+    # Sec. 4.2: the rise of max Nu_local on the hot wall from Ra = 1e2 to 1e5
+    for n, printed in ((1.0, 729.0), (1.25, 385.0)):
+        rise = 100.0 * (out[(n, "1e5")]["numax"] / out[(n, "1e2")]["numax"] - 1.0)
+        print(f"[Nu trends] n={n}: max Nu_local rises {rise:.1f} % from Ra = 1e2 to 1e5 (paper {printed:.0f} %)",
+              flush=True)
+        assert abs(rise - printed) <= 0.05 * printed
+    # Table 4 against both readings of the Bejan number (R18)
+    with open(os.path.join(HERE, "golden", "tables3_4_entropy_bejan.json")) as f:
+        tab = json.load(f)["bejan"]
+    err = {"global": [], "mean": []}
+    for (n, ra), q in sorted(out.items()):
+        ref = tab[str(n)][ra]
+        err["global"].append(abs(q["be"] - ref) / ref)
+        err["mean"].append(abs(q["be_mean"] - ref) / ref)
+        print(f"[Be readings] n={n} Ra={ra}: paper {ref:.6f}, Be_global {q['be']:.6f} ({err['global'][-1]:.2%}), "
+              f"Be_mean {q['be_mean']:.6f} ({err['mean'][-1]:.2%})", flush=True)
+    print(f"[Be readings] median relative gap to Table 4: Be_global {np.median(err['global']):.2%}, "
+          f"Be_mean {np.median(err['mean']):.2%}", flush=True)
+    # the ratio of the integrals is the reading closer to the printed table
+    assert np.median(err["global"]) < np.median(err["mean"])
     et2 = [out[(n, "1e2")]["etot"] for n in (0.75, 1.0, 1.25)]
     assert (max(et2) - min(et2)) / min(et2) < 1e-3                        # E_total nearly equal at Ra = 1e2
     for key in out:

@@ -90,3 +90,23 @@ def test_binding_structs_match_the_c_layout():
         assert c[cname] == ctypes.sizeof(ct), cname
         for f, _ in ct._fields_:
             assert c[f"{cname}.{f}"] == getattr(ct, f).offset, (cname, f)
+
+
+def test_server_workspace_sizing_and_create_validation():
+    """The server takes its device memory from the caller: the workspace is the
+    arena of the budget plus the fused-launch tables; bad sizes and a missing or
+    misaligned workspace fail on the host, before any device call."""
+    L = hosc.lib()
+    n = ctypes.c_size_t(0)
+    assert L.hosc_server_workspace_bytes(1 << 20, 4, ctypes.byref(n)) == 0
+    base = n.value
+    assert base > 1 << 20
+    assert L.hosc_server_workspace_bytes((1 << 20) + 100, 4, ctypes.byref(n)) == 0 and n.value == base
+    assert L.hosc_server_workspace_bytes(1 << 20, 8, ctypes.byref(n)) == 0 and n.value > base
+    for budget, cap in ((100, 4), (1 << 20, 0), (1 << 20, 1025)):
+        assert L.hosc_server_workspace_bytes(budget, cap, ctypes.byref(n)) == -1
+    h = ctypes.c_void_p()
+    assert L.hosc_server_create(None, 1 << 30, 1 << 20, 4, None, ctypes.byref(h)) == -1
+    assert L.hosc_server_create(ctypes.c_void_p(256 * 1024 + 8), 1 << 30, 1 << 20, 4, None, ctypes.byref(h)) == -1
+    assert L.hosc_server_create(ctypes.c_void_p(256 * 1024), 1000, 1 << 20, 4, None, ctypes.byref(h)) == -2
+    assert not h.value
