@@ -40,7 +40,8 @@ struct Launch {
     dim3 blk_sw, grd_sw;        // one colour of the interior (colour layout)
     dim3 blk_face, grd_face;    // wall nodes, 6 faces
     dim3 grd_bc;                // both colours of the interior (BiCGSTAB)
-    size_t nb_int, nb_sw, nb_face, nb_all, nb_bc;
+    dim3 blk_sp, grd_sp;        // one colour of the interior, two colour-row entries per thread (sweeps)
+    size_t nb_int, nb_sw, nb_face, nb_all, nb_bc, nb_sp;
 };
 
 // Workspace map (element counts in doubles, each region 256-byte aligned).
@@ -59,6 +60,7 @@ Geo make_geo(int N)
     Geo g;
     g.N = N;
     g.H = (N + 1) / 2;
+    g.H += g.H & 1;     // even row length: the sweeps load entries in aligned pairs
     g.Q = ((N - 2) >> 1) + 1;
     g.pad = 0;
     g.h = 1.0 / (N - 1);
@@ -98,6 +100,15 @@ Launch make_launch(const Geo &g)
     L.nb_face = (size_t)L.grd_face.x * L.grd_face.y * L.grd_face.z;
     L.grd_bc = dim3(L.grd_sw.x, L.grd_sw.y, 2 * M);
     L.nb_bc = (size_t)L.grd_bc.x * L.grd_bc.y * L.grd_bc.z;
+    // sweeps: pairs of colour-row entries, P per row; the same narrowing of the
+    // tile for short or ragged rows
+    const int P = (g.Q + 1) / 2;
+    int px = 64;
+    while (px > 8 && px / 2 >= P) px /= 2;
+    if (px == 64 && P % 64 != 0 && P % 64 <= 32) px = 32;
+    L.blk_sp = dim3(px, 256 / px, 1);
+    L.grd_sp = dim3((P + px - 1) / px, (M + L.blk_sp.y - 1) / L.blk_sp.y, M);
+    L.nb_sp = (size_t)L.grd_sp.x * L.grd_sp.y * L.grd_sp.z;
     return L;
 }
 
@@ -108,7 +119,7 @@ Layout make_layout(const Geo &g, const Launch &L, int solver, int precision)
     y.n3 = g.n3;
     y.cs = g.cs;
     y.bicg_arrays = solver == HOSC_SOLVER_SOR ? 0 : 28;
-    const size_t recs = std::max({L.nb_int * 8, L.nb_sw * 4, L.nb_face * 2, L.nb_all * 3, L.nb_bc * 8});
+    const size_t recs = std::max({L.nb_int * 8, L.nb_sw * 4, L.nb_face * 2, L.nb_all * 3, L.nb_bc * 8, L.nb_sp * 4});
     y.partial = recs;
     size_t b = 0;
     b += y.natural_arrays * align_up(g.n3 * sizeof(double));
@@ -804,7 +815,7 @@ hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *f
             sor_sweep_flags(c, q, m, store, store0);
             bytes += 2.0 * sweep_bytes(s->g, m, sizeof(TM));
             for (int colour = 0; colour < 2; ++colour)
-                k_sweep<TM, TM><<<s->L.grd_sw, s->L.blk_sw, 0, s->st>>>(
+                k_sweep<TM, TM><<<s->L.grd_sp, s->L.blk_sp, 0, s->st>>>(
                     s->g, colour, m, (TM)s->om[0], (TM)s->om[1], (TM)st, a, colour ? s->partB : s->partR, store,
                     colour ? s->partB0 : s->partR0, store0);
         }
@@ -813,10 +824,10 @@ hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *f
         r = launch_check(s, "sweep");
         if (r) return r;
         Reductions()
-            .add(s->partR, s->L.nb_sw, 4, 0, s->red + 4)
-            .add(s->partB, s->L.nb_sw, 4, 0, s->red + 8)
-            .add(s->partR0, s->L.nb_sw, 4, 0, s->red + 32)
-            .add(s->partB0, s->L.nb_sw, 4, 0, s->red + 36)
+            .add(s->partR, s->L.nb_sp, 4, 0, s->red + 4)
+            .add(s->partB, s->L.nb_sp, 4, 0, s->red + 8)
+            .add(s->partR0, s->L.nb_sp, 4, 0, s->red + 32)
+            .add(s->partB0, s->L.nb_sp, 4, 0, s->red + 36)
             .launch(s->st);
         HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red, 48 * sizeof(double), hipMemcpyDeviceToHost, s->st));
         HIPCHK(s, wait_stream(s->st));
@@ -1468,16 +1479,20 @@ void fused_free(Fused &F)
     F.h_gather = nullptr;
 }
 
-void tile_map(TileMap &m, const hosc_solver *s, int &total)
+void tile_map_of(TileMap &m, dim3 grd, dim3 blk, int &total)
 {
     m.tile0 = total;
-    m.tiles_x = (int)s->L.grd_sw.x;
-    m.tiles_y = (int)s->L.grd_sw.y;
-    m.tiles = m.tiles_x * m.tiles_y * (int)s->L.grd_sw.z;
-    m.tx = (int)s->L.blk_sw.x;
-    m.ty = (int)s->L.blk_sw.y;
+    m.tiles_x = (int)grd.x;
+    m.tiles_y = (int)grd.y;
+    m.tiles = m.tiles_x * m.tiles_y * (int)grd.z;
+    m.tx = (int)blk.x;
+    m.ty = (int)blk.y;
     total += m.tiles;
 }
+// tiles of the refinement residual launch (one colour-row entry per thread)
+void tile_map(TileMap &m, const hosc_solver *s, int &total) { tile_map_of(m, s->L.grd_sw, s->L.blk_sw, total); }
+// tiles of the sweep launch (two colour-row entries per thread)
+void tile_map_sweep(TileMap &m, const hosc_solver *s, int &total) { tile_map_of(m, s->L.grd_sp, s->L.blk_sp, total); }
 
 int fused_grid(const Fused &F, int total) { return F.grid > 0 ? std::min(F.grid, total) : total; }
 
@@ -1565,7 +1580,7 @@ hosc_status fused_sor(Fused &F, hosc_solver *const *cav, int n, const int *mask,
         upto[0] = 0;
         for (const int i : order) {
             hosc_solver *s = cav[i];
-            tile_map(F.hmap()[nact], s, total);
+            tile_map_sweep(F.hmap()[nact], s, total);
             FusedSweepCav<TM, TM> &cv = F.hcav<FusedSweepCav<TM, TM>>()[nact];
             cv.g = s->g;
             cv.a = args[i];
@@ -1579,7 +1594,7 @@ hosc_status fused_sor(Fused &F, hosc_solver *const *cav, int n, const int *mask,
             cv.part[1] = s->partB;
             cv.part0[0] = s->partR0;
             cv.part0[1] = s->partB0;
-            const int nb = (int)s->L.nb_sw;
+            const int nb = (int)s->L.nb_sp;
             add_job(F.hjobs(), nj, s->partR, nb, 4, 0, s->red + 4);
             add_job(F.hjobs(), nj, s->partB, nb, 4, 0, s->red + 8);
             add_job(F.hjobs(), nj, s->partR0, nb, 4, 0, s->red + 32);
@@ -1929,7 +1944,7 @@ hosc_status fused_tune(Fused &F, hosc_solver *const *cav, int n, int *best_grid)
     int total = 0;
     for (int i = 0; i < n; ++i) {
         hosc_solver *s = cav[i];
-        tile_map(F.hmap()[i], s, total);
+        tile_map_sweep(F.hmap()[i], s, total);
         FusedSweepCav<TM, TM> &cv = F.hcav<FusedSweepCav<TM, TM>>()[i];
         cv.g = s->g;
         cv.a = cavity_sweep_args<TM>(s);

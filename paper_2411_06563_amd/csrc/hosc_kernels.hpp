@@ -842,53 +842,129 @@ struct SweepArgs {
     TM *td;
 };
 
-// One SOR update of the node at colour-row entry q of row (j, k); the squared
-// pre-update residuals go to r2.  mask: bit 0 momentum, bit 1 energy, bits 2..4
-// momentum fields u, v, w to leave alone (a zero right-hand side: zero increment).
-template <typename TM, typename TA>
-__device__ __forceinline__ void sweep_node(const Geo &g, int colour, int mask, TA omega_m, TA omega_t, TA st,
-                                           const SweepArgs<TM> &a, int q, int j, int k, double (&r2)[4])
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+
+// Two consecutive entries of a colour array, 2 x sizeof(T) bytes at an even index
+// (colour rows have an even length, so such a pair is aligned to its size).
+template <typename T>
+__device__ __forceinline__ typename Vec2<T>::type ld_pair(const T *x, size_t o)
 {
-    RowIdx r;
-    if (row_index(g, colour, q, j, k, r)) {
-        if (mask & 1) {
-            const TA s = (TA)a.ms[r.me], ax = (TA)a.ma[0][r.me], ay = (TA)a.ma[1][r.me], az = (TA)a.ma[2][r.me];
+    return *reinterpret_cast<const typename Vec2<T>::type *>(x + o);
+}
+template <typename T>
+__device__ __forceinline__ void st_pair(T *x, size_t o, T a, T b)
+{
+    typename Vec2<T>::type v;
+    v.x = a;
+    v.y = b;
+    *reinterpret_cast<typename Vec2<T>::type *>(x + o) = v;
+}
+
+// SOR updates of the two nodes at colour-row entries q0 = 2p and q0 + 1 of row
+// (j, k) (nodes i = 2q + par, par = (colour + j + k) & 1), with loads of both
+// entries at once: own-colour rows, right-hand sides and increments as pairs, the
+// y and z neighbours as pairs of the other colour's rows, the three x neighbours
+// (q0 + par - 1 .. q0 + par + 1) as one pair and one single value.  Each node's
+// update is the same expression, in the same order, as for a node on its own.
+// The squared pre-update residuals of both nodes go to r2.  mask: bit 0 momentum,
+// bit 1 energy, bits 2..4 momentum fields u, v, w to leave alone (a zero
+// right-hand side: zero increment).  An entry that holds no interior node keeps
+// its stored value.
+template <typename TM, typename TA>
+__device__ __forceinline__ void sweep_pair(const Geo &g, int colour, int mask, TA omega_m, TA omega_t, TA st,
+                                           const SweepArgs<TM> &a, int p, int j, int k, double (&r2)[4])
+{
+    const int N = g.N, q0 = 2 * p;
+    if (q0 >= g.Q || j > N - 2 || k > N - 2) return;
+    const int par = (colour + j + k) & 1;
+    const int i0 = 2 * q0 + par;
+    const bool v0 = i0 >= 1 && i0 <= N - 2;
+    const bool v1 = q0 + 1 < g.Q && i0 + 2 <= N - 2;
+    const size_t row = rowid(g, j, k), ob = (size_t)(1 - colour) * g.cs;
+    const size_t me = (size_t)colour * g.cs + row + q0, xb = ob + row + q0;
+    const size_t yp = ob + rowid(g, j + 1, k) + q0, ym = ob + rowid(g, j - 1, k) + q0;
+    const size_t zp = ob + rowid(g, j, k + 1) + q0, zm = ob + rowid(g, j, k - 1) + q0;
+    // neighbour codes of mom_off / theta_off: 0 x+, 1 x-, 2 y+, 3 y-, 4 z+, 5 z-
+    RowIdx code;
+    code.me = 6;
+    code.xp = 0;
+    code.xm = 1;
+    code.yp = 2;
+    code.ym = 3;
+    code.zp = 4;
+    code.zm = 5;
+    // the other colour's values around the pair: x neighbours (x- of entry 0, the
+    // shared one, x+ of entry 1), then y+, y-, z+, z- of both entries
+    auto around = [&](const TM *d, TA (&n0)[6], TA (&n1)[6]) {
+        TA xlo, xmid, xhi;
+        if (par) {
+            const auto t = ld_pair(d, xb);
+            xlo = (TA)t.x;
+            xmid = (TA)t.y;
+            xhi = (TA)d[xb + 2];
+        } else {
+            xlo = (TA)d[xb - 1];
+            const auto t = ld_pair(d, xb);
+            xmid = (TA)t.x;
+            xhi = (TA)t.y;
+        }
+        const auto y1 = ld_pair(d, yp), y0 = ld_pair(d, ym), z1 = ld_pair(d, zp), z0 = ld_pair(d, zm);
+        n0[0] = xmid; n0[1] = xlo; n0[2] = (TA)y1.x; n0[3] = (TA)y0.x; n0[4] = (TA)z1.x; n0[5] = (TA)z0.x;
+        n1[0] = xhi; n1[1] = xmid; n1[2] = (TA)y1.y; n1[3] = (TA)y0.y; n1[4] = (TA)z1.y; n1[5] = (TA)z0.y;
+    };
+    if (mask & 1) {
+        const auto sv = ld_pair(a.ms, me), axv = ld_pair(a.ma[0], me), ayv = ld_pair(a.ma[1], me),
+                   azv = ld_pair(a.ma[2], me);
+        const TA s0 = (TA)sv.x, s1 = (TA)sv.y, ax0 = (TA)axv.x, ax1 = (TA)axv.y, ay0 = (TA)ayv.x, ay1 = (TA)ayv.y,
+                 az0 = (TA)azv.x, az1 = (TA)azv.y;
 #pragma unroll
-            for (int f = 0; f < 3; ++f) {
-                if ((mask >> (2 + f)) & 1) continue;
-                TM *d = a.md[f];
-                const TA sum = mom_off<TA>(s, ax, ay, az, r, [&](size_t x) { return (TA)d[x]; });
-                const TA old = (TA)d[r.me];
-                const TA dlt = (TA)a.mb[f][r.me] - sum - old;
-                d[r.me] = (TM)(old + omega_m * dlt);
-                r2[f] = (double)dlt * (double)dlt;
-            }
+        for (int f = 0; f < 3; ++f) {
+            if ((mask >> (2 + f)) & 1) continue;
+            TM *d = a.md[f];
+            TA n0[6], n1[6];
+            around(d, n0, n1);
+            const TA sum0 = mom_off<TA>(s0, ax0, ay0, az0, code, [&](size_t x) { return n0[x]; });
+            const TA sum1 = mom_off<TA>(s1, ax1, ay1, az1, code, [&](size_t x) { return n1[x]; });
+            const auto oldv = ld_pair(d, me), bv = ld_pair(a.mb[f], me);
+            const TA old0 = (TA)oldv.x, old1 = (TA)oldv.y;
+            const TA dlt0 = (TA)bv.x - sum0 - old0, dlt1 = (TA)bv.y - sum1 - old1;
+            st_pair(d, me, v0 ? (TM)(old0 + omega_m * dlt0) : oldv.x, v1 ? (TM)(old1 + omega_m * dlt1) : oldv.y);
+            r2[f] = (v0 ? (double)dlt0 * (double)dlt0 : 0.0) + (v1 ? (double)dlt1 * (double)dlt1 : 0.0);
         }
-        if (mask & 2) {
-            const TA ax = (TA)a.ta[0][r.me], ay = (TA)a.ta[1][r.me], az = (TA)a.ta[2][r.me];
-            TM *d = a.td;
-            TA den;
-            const TA sum = theta_off<TA>(st, ax, ay, az, j, k, g.N, r, [&](size_t x) { return (TA)d[x]; }, den);
-            const TA old = (TA)d[r.me];
-            const TA gs = ((TA)a.tb[r.me] - sum) / den;
-            const TA dlt = gs - old;
-            d[r.me] = (TM)(old + omega_t * dlt);
-            const double rr = (double)den * (double)dlt;
-            r2[3] = rr * rr;
-        }
+    }
+    if (mask & 2) {
+        const auto axv = ld_pair(a.ta[0], me), ayv = ld_pair(a.ta[1], me), azv = ld_pair(a.ta[2], me);
+        TM *d = a.td;
+        TA n0[6], n1[6];
+        around(d, n0, n1);
+        TA den0, den1;
+        const TA sum0 = theta_off<TA>(st, (TA)axv.x, (TA)ayv.x, (TA)azv.x, j, k, N, code,
+                                      [&](size_t x) { return n0[x]; }, den0);
+        const TA sum1 = theta_off<TA>(st, (TA)axv.y, (TA)ayv.y, (TA)azv.y, j, k, N, code,
+                                      [&](size_t x) { return n1[x]; }, den1);
+        const auto oldv = ld_pair(d, me), bv = ld_pair(a.tb, me);
+        const TA old0 = (TA)oldv.x, old1 = (TA)oldv.y;
+        const TA gs0 = ((TA)bv.x - sum0) / den0, gs1 = ((TA)bv.y - sum1) / den1;
+        const TA dlt0 = gs0 - old0, dlt1 = gs1 - old1;
+        st_pair(d, me, v0 ? (TM)(old0 + omega_t * dlt0) : oldv.x, v1 ? (TM)(old1 + omega_t * dlt1) : oldv.y);
+        const double rr0 = (double)den0 * (double)dlt0, rr1 = (double)den1 * (double)dlt1;
+        r2[3] = (v0 ? rr0 * rr0 : 0.0) + (v1 ? rr1 * rr1 : 0.0);
     }
 }
 
+// One launch = one colour: every thread updates two entries of a colour row.
 template <typename TM, typename TA>
 __global__ void __launch_bounds__(256) k_sweep(Geo g, int colour, int mask, TA omega_m, TA omega_t, TA st,
                                                SweepArgs<TM> a, double *__restrict__ partial, unsigned store,
                                                double *__restrict__ partial0, unsigned store0)
 {
     const Tile tl = xcd_tile();
-    const int q = tl.x * blockDim.x + threadIdx.x;
+    const int p = tl.x * blockDim.x + threadIdx.x;
     const int j = 1 + tl.y * blockDim.y + threadIdx.y, k = 1 + tl.z;
     double r2[4] = {0.0, 0.0, 0.0, 0.0};
-    sweep_node<TM, TA>(g, colour, mask, omega_m, omega_t, st, a, q, j, k, r2);
+    sweep_pair<TM, TA>(g, colour, mask, omega_m, omega_t, st, a, p, j, k, r2);
     if (store | store0) {
         const int blk = tl.id;
         block_sum_store2<4>(r2, partial + (size_t)blk * 4, store, partial0 + (size_t)blk * 4, store0);
@@ -955,9 +1031,9 @@ __global__ void __launch_bounds__(256) k_sweep_fused(const TileMap *__restrict__
         const int bx = lt % m.tiles_x, rest = lt / m.tiles_x;
         const int by = rest % m.tiles_y, bz = rest / m.tiles_y;
         const int tx = threadIdx.x % m.tx, ty = threadIdx.x / m.tx;
-        const int q = bx * m.tx + tx, j = 1 + by * m.ty + ty, k = 1 + bz;
+        const int p = bx * m.tx + tx, j = 1 + by * m.ty + ty, k = 1 + bz;
         double r2[4] = {0.0, 0.0, 0.0, 0.0};
-        sweep_node<TM, TA>(cv.g, colour, mask, cv.omega_m, cv.omega_t, cv.st, cv.a, q, j, k, r2);
+        sweep_pair<TM, TA>(cv.g, colour, mask, cv.omega_m, cv.omega_t, cv.st, cv.a, p, j, k, r2);
         if (store | store0)
             block_sum_store2<4>(r2, cv.part[colour] + (size_t)lt * 4, store, cv.part0[colour] + (size_t)lt * 4,
                                 store0);
