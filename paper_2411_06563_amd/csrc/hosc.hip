@@ -51,6 +51,7 @@ struct Layout {
     size_t colour_arrays = 15;    // ms ma3 mb3 md3 ta3 tb td (each 2 colours)
     size_t bicg_arrays = 0;       // r rh p pn v vn t for 4 systems (BiCGSTAB enabled)
     size_t fp32_arrays = 0;       // precision mode: FP32 rows (7), residuals and corrections of 4 systems
+    size_t alt_arrays = 0;        // precision mode: second FP64 increment buffers of the refinement (4 systems)
     size_t partial;               // partial-sum records
     size_t total_bytes;
 };
@@ -116,6 +117,7 @@ Layout make_layout(const Geo &g, const Launch &L, int solver, int precision)
 {
     Layout y;
     y.fp32_arrays = precision == HOSC_FP32_REFINED ? 15 : 0;
+    y.alt_arrays = precision == HOSC_FP32_REFINED ? 4 : 0;
     y.n3 = g.n3;
     y.cs = g.cs;
     y.bicg_arrays = solver == HOSC_SOLVER_SOR ? 0 : 28;
@@ -123,7 +125,7 @@ Layout make_layout(const Geo &g, const Launch &L, int solver, int precision)
     y.partial = recs;
     size_t b = 0;
     b += y.natural_arrays * align_up(g.n3 * sizeof(double));
-    b += (y.colour_arrays + y.bicg_arrays) * align_up(2 * g.cs * sizeof(double));
+    b += (y.colour_arrays + y.bicg_arrays + y.alt_arrays) * align_up(2 * g.cs * sizeof(double));
     b += y.fp32_arrays * align_up(2 * g.cs * sizeof(float));
     b += 4 * align_up(recs * sizeof(double));                 // partial buffers: red / black half, last and first sweep
     b += align_up(kRed * sizeof(double));                      // reduction outputs
@@ -220,12 +222,18 @@ struct hosc_solver {
     bool fp32 = false;
     float *fms = nullptr, *fma[3] = {nullptr, nullptr, nullptr}, *fta[3] = {nullptr, nullptr, nullptr};
     float *fr[4] = {nullptr, nullptr, nullptr, nullptr}, *fe[4] = {nullptr, nullptr, nullptr, nullptr};
+    double *dalt[4] = {nullptr, nullptr, nullptr, nullptr};   // second increment buffers of the refinement
     double *hbuf = nullptr;   // pinned host staging for scalars
     int64_t step = 0;
     bool first = true;
     bool has_state = false;
     int sticky = HOSC_OK;
     int last_sweeps[2] = {0, 0};
+    // precision mode: sweeps that sufficed in the first inner solve of a step and in
+    // the later ones (their right-hand sides differ by decades), and which of the two
+    // the next inner solve plans from
+    int inner_sweeps[2][2] = {{0, 0}, {0, 0}};
+    int inner_slot = 0;
     int last_bicg[2] = {0, 0};
     double om[2] = {1.0, 1.0};          // SOR relaxation of each group (adaptive when P.omega == 0)
     int64_t seeded_at = -1;             // step whose dominance bound was last applied to om
@@ -324,6 +332,7 @@ void carve(hosc_solver *s, char *base)
         for (int d = 0; d < 3; ++d) s->fta[d] = reinterpret_cast<float *>(take(fcol));
         for (int f = 0; f < 4; ++f) s->fr[f] = reinterpret_cast<float *>(take(fcol));
         for (int f = 0; f < 4; ++f) s->fe[f] = reinterpret_cast<float *>(take(fcol));
+        for (int f = 0; f < 4; ++f) s->dalt[f] = take(col);
     }
     if (s->Y.bicg_arrays)
         for (int f = 0; f < 4; ++f) {
@@ -346,15 +355,20 @@ double sweep_bytes(const Geo &g, int mask, size_t elem = sizeof(double))
     return nodes * per;
 }
 
-// Algorithmic bytes of one refinement-residual launch (one colour): FP64 rows,
-// FP64 right-hand side, FP64 increment read + written, FP32 correction read + zeroed,
-// FP32 residual written, and the other colour's increment and correction read once.
-double refine_bytes(const Geo &g, int mask)
+// Algorithmic bytes of one refinement pass (both colours, every interior node):
+// FP64 rows and right-hand sides, FP64 increment, FP32 residual written, and for
+// the systems in emask the FP32 correction read and the folded FP64 increment
+// written.  The neighbours are the other colour's entries of the same pass.
+double refine_bytes(const Geo &g, int mask, int emask)
 {
-    const double nodes = 0.5 * (double)(g.N - 2) * (g.N - 2) * (g.N - 2);
+    const double nodes = (double)(g.N - 2) * (g.N - 2) * (g.N - 2);
     double per = 0.0;
-    if (mask & 1) per += 4 * 8 + 3 * (8 + 8 + 8 + 4 + 4 + 4 + 8 + 4);
-    if (mask & 2) per += 3 * 8 + (8 + 8 + 8 + 4 + 4 + 4 + 8 + 4);
+    if (mask & 1) per += 4 * 8;
+    if (mask & 2) per += 3 * 8;
+    for (int f = 0; f < 4; ++f) {
+        if (!((f < 3) ? (mask & 1) : (mask & 2))) continue;
+        per += 8 + 8 + 4 + (((emask >> f) & 1) ? 4 + 8 : 0);
+    }
     return nodes * per;
 }
 
@@ -433,6 +447,7 @@ hosc_status zero_colour_increments(hosc_solver *s)
         for (int f = 0; f < 4; ++f) {
             HIPCHK(s, hipMemsetAsync(s->fr[f], 0, 2 * s->g.cs * sizeof(float), s->st));
             HIPCHK(s, hipMemsetAsync(s->fe[f], 0, 2 * s->g.cs * sizeof(float), s->st));
+            HIPCHK(s, hipMemsetAsync(s->dalt[f], 0, b, s->st));
         }
     return HOSC_OK;
 }
@@ -455,6 +470,7 @@ hosc_status reset_state(hosc_solver *s)
     s->has_state = true;
     s->sticky = HOSC_OK;
     s->last_sweeps[0] = s->last_sweeps[1] = 0;
+    for (auto &h : s->inner_sweeps) h[0] = h[1] = 0;
     s->last_bicg[0] = s->last_bicg[1] = 0;
     s->bicg_until[0] = s->bicg_until[1] = -1;
     s->om[0] = s->om[1] = s->P.omega > 0.0 ? s->P.omega : 1.0;
@@ -593,9 +609,11 @@ struct SorCtl {
     int active = 0, failed = 0, batch = 0, soft_cap = 0;
     int skip = 0;       // momentum fields with a zero right-hand side (bits 0..2): not swept
     bool inner = false, adapt = false, autom = false;
+    bool zero_start = false;    // the first sweep starts from the zero increment without reading it
     double rtol = 0.0;
     double ref[2] = {-1.0, -1.0};
     int ref_at[2] = {0, 0}, plan[2] = {0, 0}, swept[2] = {0, 0}, first_plan[2] = {0, 0};
+    int *hist = nullptr;        // sweep history this solve plans from and updates
 };
 
 // inner solves of the refinement: at most 200 sweeps, and no relaxation update
@@ -611,17 +629,19 @@ void sor_skip(SorCtl &c, const double bn2[4])
             if (bn2[f] == 0.0) c.skip |= 1 << f;
 }
 
-void sor_begin(const hosc_solver *s, SorCtl &c, int mask, double rtol, bool inner)
+void sor_begin(hosc_solver *s, SorCtl &c, int mask, double rtol, bool inner)
 {
     c = SorCtl();
     c.active = mask;
     c.rtol = rtol;
     c.inner = inner;
+    c.zero_start = inner;
     c.soft_cap = inner ? 200 : 0;
     c.adapt = s->P.omega == 0.0;
     c.autom = s->P.solver == HOSC_SOLVER_AUTO;
+    c.hist = inner ? s->inner_sweeps[s->inner_slot] : s->last_sweeps;
     for (int grp = 0; grp < 2; ++grp)
-        c.plan[grp] = s->P.check_every > 0 ? s->P.check_every : std::max(2, s->last_sweeps[grp]);
+        c.plan[grp] = s->P.check_every > 0 ? s->P.check_every : std::max(2, c.hist[grp]);
     c.first_plan[0] = c.plan[0];
     c.first_plan[1] = c.plan[1];
 }
@@ -663,6 +683,7 @@ void sor_sweep_flags(const SorCtl &c, int q, int &m, unsigned &store, unsigned &
     for (int grp = 0; grp < 2; ++grp) {
         if (!(c.active & (1 << grp)) || q >= c.plan[grp]) continue;
         m |= grp == 0 ? 1 | (c.skip << 2) : 2;
+        if (c.zero_start && c.batch == 0 && q == 0) m |= 32;
         if (q == c.plan[grp] - 1) store |= kStore[grp];
         if (q == 0 && c.plan[grp] > 1) store0 |= kStore[grp];
     }
@@ -734,7 +755,7 @@ hosc_status sor_decide(hosc_solver *s, SorCtl &c, const double *hb, double bn2[4
             int suff = done == c.first_plan[grp] ? std::max(1, done / 2) : done;
             if (rate > 0.0 && rate < 1.0 && worst > 0.0)    // r_done / r_needed = rate^(done - needed)
                 suff = done - (int)std::floor(std::log(worst / rtol) / std::log(rate));
-            s->last_sweeps[grp] = std::max(1, std::min(done, suff));
+            c.hist[grp] = std::max(1, std::min(done, suff));
             c.active &= ~(1 << grp);
             continue;
         }
@@ -976,18 +997,35 @@ hosc_status run_bicg(hosc_solver *s, int mask, double bn2[4], SolveOut &o, BicgA
 }
 
 // Solve the momentum (3 right-hand sides) and energy systems of the step.
-// Precision mode: iterative refinement.  Each outer pass folds the FP32 correction
-// into the FP64 increment and forms the FP64 residual of the scaled rows (one
-// launch per colour); converged groups stop, the others solve B e = r for the FP32
-// correction with FP32 red-black sweeps to a relative 1e-5 or what the tolerance
-// still needs.  Groups whose inner solve fails (auto mode) are returned in *to_bicg.
-// Iterative refinement of the precision mode: FP64 residual of the FP64 rows, FP32
-// inner red-black solve of B e = r, fold, until the FP64 residual meets rtol.
+// Precision mode: iterative refinement.  Each outer pass (one launch over both
+// colours) forms the FP64 residual of the scaled FP64 rows at the current iterate
+// and folds the FP32 correction of the last inner solve into the FP64 increment;
+// converged groups stop, the others solve B e = r for the FP32 correction with
+// FP32 red-black sweeps to a relative 1e-5 or what the tolerance still needs.
+// Groups whose inner solve fails (auto mode) are returned in *to_bicg.
+//
+// The fold writes d + e to the other of two FP64 increment buffers (cur / oth
+// swap per system); when the solve ends, a system whose increment is in the
+// second buffer is copied back, so the rest of the step sees one buffer.
 struct RefCtl {
     int active = 0, outer = 0, to_bicg = 0;
+    int emask = 0;                  // systems whose FP32 correction is not yet folded
+    double *cur[4] = {nullptr, nullptr, nullptr, nullptr}, *oth[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
-RefineArgs<double> refine_args(hosc_solver *s)
+double *primary_increment(hosc_solver *s, int f) { return f < 3 ? s->md[f] : s->td; }
+
+void refine_begin(hosc_solver *s, RefCtl &c, int mask)
+{
+    c = RefCtl();
+    c.active = mask;
+    for (int f = 0; f < 4; ++f) {
+        c.cur[f] = primary_increment(s, f);
+        c.oth[f] = s->dalt[f];
+    }
+}
+
+RefineArgs<double> refine_args(hosc_solver *s, const RefCtl &c)
 {
     RefineArgs<double> ra;
     ra.ms = s->ms;
@@ -995,15 +1033,35 @@ RefineArgs<double> refine_args(hosc_solver *s)
         ra.ma[d] = s->ma[d];
         ra.ta[d] = s->ta[d];
         ra.b[d] = s->mb[d];
-        ra.d[d] = s->md[d];
     }
     ra.b[3] = s->tb;
-    ra.d[3] = s->td;
     for (int f = 0; f < 4; ++f) {
+        ra.d[f] = c.cur[f];
+        ra.dn[f] = c.oth[f];
         ra.e[f] = s->fe[f];
         ra.r[f] = s->fr[f];
     }
     return ra;
+}
+
+// After a pass is launched: the folded systems now live in their other buffer.
+void refine_folded(RefCtl &c)
+{
+    for (int f = 0; f < 4; ++f)
+        if (((c.emask >> f) & 1) && (c.active & (f < 3 ? 1 : 2))) std::swap(c.cur[f], c.oth[f]);
+    c.emask = 0;
+}
+
+// Systems whose increment sits in the second buffer are copied back (stream order).
+hosc_status refine_end(hosc_solver *s, RefCtl &c, hipStream_t st)
+{
+    const size_t b = 2 * s->g.cs * sizeof(double);
+    for (int f = 0; f < 4; ++f)
+        if (c.cur[f] != primary_increment(s, f)) {
+            HIPCHK(s, hipMemcpyAsync(primary_increment(s, f), c.cur[f], b, hipMemcpyDeviceToDevice, st));
+            std::swap(c.cur[f], c.oth[f]);
+        }
+    return HOSC_OK;
 }
 
 // Decisions after a residual pass, from the reduction block hb (the cavity's
@@ -1052,8 +1110,9 @@ hosc_status refine_decide(hosc_solver *s, RefCtl &c, const double *hb, double bn
 }
 
 // After an inner solve: groups whose FP32 solve failed leave the refinement and go
-// to the BiCGSTAB fallback.
-hosc_status refine_after_inner(hosc_solver *s, RefCtl &c, int failed)
+// to the BiCGSTAB fallback; the others' swept systems (momentum fields with a zero
+// residual are left out of the sweeps) carry a correction to fold.
+hosc_status refine_after_inner(hosc_solver *s, RefCtl &c, int failed, const double inner_bn2[4])
 {
     if (failed) {
         for (int grp = 0; grp < 2; ++grp) {
@@ -1067,28 +1126,28 @@ hosc_status refine_after_inner(hosc_solver *s, RefCtl &c, int failed)
         c.to_bicg |= failed;
         c.active &= ~failed;
     }
+    c.emask = 0;
+    for (int f = 0; f < 4; ++f)
+        if ((c.active & (f < 3 ? 1 : 2)) && (f == 3 || inner_bn2[f] != 0.0)) c.emask |= 1 << f;
     c.outer += 1;
     return HOSC_OK;
 }
 
-hosc_status solve_refined(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *to_bicg)
+hosc_status refine_loop(hosc_solver *s, RefCtl &c, double bn2[4], SolveOut &o)
 {
     const double st = theta_st(s);
-    const RefineArgs<double> ra = refine_args(s);
-    RefCtl c;
-    c.active = mask;
-    *to_bicg = 0;
     while (c.active) {
         hosc_status r = timed_begin(s);
         if (r) return r;
-        for (int colour = 0; colour < 2; ++colour)
-            k_refine_residual<double><<<s->L.grd_sw, s->L.blk_sw, 0, s->st>>>(s->g, colour, c.active, st, ra,
-                                                                            colour ? s->partB : s->partR);
-        r = timed_end(s, 3, 2.0 * refine_bytes(s->g, c.active), 2);
+        const dim3 grd(s->L.grd_sp.x, s->L.grd_sp.y, 2 * s->L.grd_sp.z);
+        k_refine_pass<double><<<grd, s->L.blk_sp, 0, s->st>>>(s->g, c.active, c.emask, st, refine_args(s, c),
+                                                              s->partR, s->partB);
+        r = timed_end(s, 3, refine_bytes(s->g, c.active, c.emask), 1);
         if (r) return r;
-        r = launch_check(s, "refine residual");
+        r = launch_check(s, "refinement pass");
         if (r) return r;
-        Reductions().add(s->partR, s->L.nb_sw, 4, 0, s->red + 48).add(s->partB, s->L.nb_sw, 4, 0, s->red + 52).launch(s->st);
+        refine_folded(c);
+        Reductions().add(s->partR, s->L.nb_sp, 4, 0, s->red + 48).add(s->partB, s->L.nb_sp, 4, 0, s->red + 52).launch(s->st);
         HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red, 56 * sizeof(double), hipMemcpyDeviceToHost, s->st));
         HIPCHK(s, wait_stream(s->st));
         r = harvest_events(s);
@@ -1098,11 +1157,24 @@ hosc_status solve_refined(hosc_solver *s, int mask, double bn2[4], SolveOut &o, 
         if (r) return r;
         if (!c.active) break;
         int failed = 0;
+        s->inner_slot = std::min(c.outer, 1);
         r = run_sor<float>(s, c.active, inner_bn2, o, &failed, sweep_args_fp32(s), inner_rtol, true);
         if (r) return r;
-        r = refine_after_inner(s, c, failed);
+        r = refine_after_inner(s, c, failed, inner_bn2);
         if (r) return r;
     }
+    return HOSC_OK;
+}
+
+hosc_status solve_refined(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *to_bicg)
+{
+    RefCtl c;
+    refine_begin(s, c, mask);
+    *to_bicg = 0;
+    const hosc_status r = refine_loop(s, c, bn2, o);
+    const hosc_status r2 = refine_end(s, c, s->st);
+    if (r) return r;
+    if (r2) return r2;
     *to_bicg = c.to_bicg;
     return HOSC_OK;
 }
@@ -1489,8 +1561,6 @@ void tile_map_of(TileMap &m, dim3 grd, dim3 blk, int &total)
     m.ty = (int)blk.y;
     total += m.tiles;
 }
-// tiles of the refinement residual launch (one colour-row entry per thread)
-void tile_map(TileMap &m, const hosc_solver *s, int &total) { tile_map_of(m, s->L.grd_sw, s->L.blk_sw, total); }
 // tiles of the sweep launch (two colour-row entries per thread)
 void tile_map_sweep(TileMap &m, const hosc_solver *s, int &total) { tile_map_of(m, s->L.grd_sp, s->L.blk_sp, total); }
 
@@ -1590,6 +1660,7 @@ hosc_status fused_sor(Fused &F, hosc_solver *const *cav, int n, const int *mask,
             cv.plan_m = (c[i].active & 1) ? c[i].plan[0] : 0;
             cv.plan_t = (c[i].active & 2) ? c[i].plan[1] : 0;
             cv.skip = c[i].skip;
+            cv.zs = c[i].zero_start && c[i].batch == 0;
             cv.part[0] = s->partR;
             cv.part[1] = s->partB;
             cv.part0[0] = s->partR0;
@@ -1648,41 +1719,40 @@ hosc_status fused_sor(Fused &F, hosc_solver *const *cav, int n, const int *mask,
 }
 
 // Batched iterative refinement (precision mode), the control of solve_refined.
-hosc_status fused_refined(Fused &F, hosc_solver *const *cav, int n, const int *mask, double (*bn2)[4], SolveOut *o,
-                          int *to_bicg, hosc_status *err)
+hosc_status fused_refined_loop(Fused &F, hosc_solver *const *cav, int n, std::vector<RefCtl> &rc, double (*bn2)[4],
+                               SolveOut *o, hosc_status *err)
 {
-    std::vector<RefCtl> rc(n);
     std::vector<int> act(n), imask(n), ifailed(n);
     std::vector<double> irtol(n);
     std::vector<std::array<double, 4>> ibn2(n);
-    for (int i = 0; i < n; ++i) rc[i].active = err[i] ? 0 : mask[i];
     for (;;) {
         int nact = 0, total = 0, nj = 0;
         double bytes = 0.0;
         for (int i = 0; i < n; ++i) {
             if (err[i] || !rc[i].active) continue;
             hosc_solver *s = cav[i];
-            tile_map(F.hmap()[nact], s, total);
+            tile_map_sweep(F.hmap()[nact], s, total);
             FusedRefineCav<double> &cv = F.hcav<FusedRefineCav<double>>()[nact];
             cv.g = s->g;
-            cv.a = refine_args(s);
+            cv.a = refine_args(s, rc[i]);
             cv.st = theta_st(s);
             cv.mask = rc[i].active;
+            cv.emask = rc[i].emask;
             cv.part[0] = s->partR;
             cv.part[1] = s->partB;
-            const int nb = (int)s->L.nb_sw;
+            const int nb = (int)s->L.nb_sp;
             add_job(F.hjobs(), nj, s->partR, nb, 4, 0, s->red + 48);
             add_job(F.hjobs(), nj, s->partB, nb, 4, 0, s->red + 52);
             F.hsrc()[nact] = s->red;
-            bytes += 2.0 * refine_bytes(s->g, rc[i].active);
+            bytes += refine_bytes(s->g, rc[i].active, rc[i].emask);
+            refine_folded(rc[i]);
             act[nact++] = i;
         }
         if (!nact) break;
         FHIPCHK(F, hipMemcpyAsync(F.d_tab, F.h_tab, F.tab_bytes, hipMemcpyHostToDevice, F.st));
-        const int G = fused_grid(F, total);
+        const int G = fused_grid(F, 2 * total);
         if (F.prof) FHIPCHK(F, hipEventRecord(F.ev[0], F.st));
-        for (int colour = 0; colour < 2; ++colour)
-            k_refine_fused<double><<<G, 256, 0, F.st>>>(F.dmap(), F.dcav<FusedRefineCav<double>>(), nact, total, colour);
+        k_refine_fused<double><<<G, 256, 0, F.st>>>(F.dmap(), F.dcav<FusedRefineCav<double>>(), nact, total);
         if (F.prof) FHIPCHK(F, hipEventRecord(F.ev[1], F.st));
         FHIPCHK(F, hipGetLastError());
         hosc_status r = fused_reduce_gather(F, nj, nact, 56);
@@ -1690,7 +1760,7 @@ hosc_status fused_refined(Fused &F, hosc_solver *const *cav, int n, const int *m
         if (F.prof) {
             float ms = 0.0f;
             FHIPCHK(F, hipEventElapsedTime(&ms, F.ev[0], F.ev[1]));
-            F.perf.refine_launches += 2;
+            F.perf.refine_launches += 1;
             F.perf.refine_ms += ms;
             F.perf.refine_bytes += bytes;
         }
@@ -1704,6 +1774,7 @@ hosc_status fused_refined(Fused &F, hosc_solver *const *cav, int n, const int *m
                 continue;
             }
             imask[i] = rc[i].active;
+            cav[i]->inner_slot = std::min(rc[i].outer, 1);
         }
         std::vector<double> flat(4 * (size_t)n);
         for (int i = 0; i < n; ++i)
@@ -1713,10 +1784,25 @@ hosc_status fused_refined(Fused &F, hosc_solver *const *cav, int n, const int *m
         if (r) return r;
         for (int i = 0; i < n; ++i) {
             if (!imask[i] || err[i]) continue;
-            r = refine_after_inner(cav[i], rc[i], ifailed[i]);
+            r = refine_after_inner(cav[i], rc[i], ifailed[i], ibn2[i].data());
             if (r) err[i] = r;
         }
     }
+    return HOSC_OK;
+}
+
+// Batched iterative refinement (precision mode), the control of solve_refined.
+hosc_status fused_refined(Fused &F, hosc_solver *const *cav, int n, const int *mask, double (*bn2)[4], SolveOut *o,
+                          int *to_bicg, hosc_status *err)
+{
+    std::vector<RefCtl> rc(n);
+    for (int i = 0; i < n; ++i) refine_begin(cav[i], rc[i], err[i] ? 0 : mask[i]);
+    const hosc_status r = fused_refined_loop(F, cav, n, rc, bn2, o, err);
+    for (int i = 0; i < n; ++i) {
+        const hosc_status r2 = refine_end(cav[i], rc[i], F.st);
+        if (r2 && !err[i]) err[i] = r2;
+    }
+    if (r) return r;
     for (int i = 0; i < n; ++i) to_bicg[i] = rc[i].to_bicg;
     return HOSC_OK;
 }
@@ -1952,6 +2038,7 @@ hosc_status fused_tune(Fused &F, hosc_solver *const *cav, int n, int *best_grid)
         cv.st = (TM)theta_st(s);
         cv.plan_m = cv.plan_t = 1;
         cv.skip = 0;
+        cv.zs = 0;
         cv.part[0] = s->partR;
         cv.part[1] = s->partB;
         cv.part0[0] = s->partR0;
@@ -2448,6 +2535,7 @@ hosc_status hosc_transport_step(hosc_solver *s, const double *L, const double *G
     s->step = 0;
     s->first = true;
     s->last_sweeps[0] = s->last_sweeps[1] = 0;
+    for (auto &h : s->inner_sweeps) h[0] = h[1] = 0;
     s->last_bicg[0] = s->last_bicg[1] = 0;
     s->bicg_until[0] = s->bicg_until[1] = -1;
     s->om[0] = s->om[1] = s->P.omega > 0.0 ? s->P.omega : 1.0;

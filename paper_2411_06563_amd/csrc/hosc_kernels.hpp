@@ -862,6 +862,46 @@ __device__ __forceinline__ void st_pair(T *x, size_t o, T a, T b)
     *reinterpret_cast<typename Vec2<T>::type *>(x + o) = v;
 }
 
+// The other colour's values around the colour-row entries q0, q0 + 1 (par =
+// (colour + j + k) & 1): the x neighbours (x- of entry 0, the shared one, x+ of
+// entry 1) as one pair and one single value at xb = other colour's row + q0, then
+// the y+, y-, z+, z- pairs; n0 / n1 in the neighbour order of mom_off / theta_off
+// (0 x+, 1 x-, 2 y+, 3 y-, 4 z+, 5 z-).
+template <typename T, typename TA>
+__device__ __forceinline__ void pair_around(const T *d, int par, size_t xb, size_t yp, size_t ym, size_t zp, size_t zm,
+                                            TA (&n0)[6], TA (&n1)[6])
+{
+    TA xlo, xmid, xhi;
+    if (par) {
+        const auto t = ld_pair(d, xb);
+        xlo = (TA)t.x;
+        xmid = (TA)t.y;
+        xhi = (TA)d[xb + 2];
+    } else {
+        xlo = (TA)d[xb - 1];
+        const auto t = ld_pair(d, xb);
+        xmid = (TA)t.x;
+        xhi = (TA)t.y;
+    }
+    const auto y1 = ld_pair(d, yp), y0 = ld_pair(d, ym), z1 = ld_pair(d, zp), z0 = ld_pair(d, zm);
+    n0[0] = xmid; n0[1] = xlo; n0[2] = (TA)y1.x; n0[3] = (TA)y0.x; n0[4] = (TA)z1.x; n0[5] = (TA)z0.x;
+    n1[0] = xhi; n1[1] = xmid; n1[2] = (TA)y1.y; n1[3] = (TA)y0.y; n1[4] = (TA)z1.y; n1[5] = (TA)z0.y;
+}
+
+// neighbour codes of mom_off / theta_off for values held in n0 / n1
+__device__ __forceinline__ RowIdx pair_codes()
+{
+    RowIdx code;
+    code.me = 6;
+    code.xp = 0;
+    code.xm = 1;
+    code.yp = 2;
+    code.ym = 3;
+    code.zp = 4;
+    code.zm = 5;
+    return code;
+}
+
 // SOR updates of the two nodes at colour-row entries q0 = 2p and q0 + 1 of row
 // (j, k) (nodes i = 2q + par, par = (colour + j + k) & 1), with loads of both
 // entries at once: own-colour rows, right-hand sides and increments as pairs, the
@@ -870,8 +910,10 @@ __device__ __forceinline__ void st_pair(T *x, size_t o, T a, T b)
 // update is the same expression, in the same order, as for a node on its own.
 // The squared pre-update residuals of both nodes go to r2.  mask: bit 0 momentum,
 // bit 1 energy, bits 2..4 momentum fields u, v, w to leave alone (a zero
-// right-hand side: zero increment).  An entry that holds no interior node keeps
-// its stored value.
+// right-hand side: zero increment), bit 5 the first sweep of a solve that starts
+// from the zero increment (the stored values are not read: the colour-0 half
+// takes its own and its neighbours' as zero, the colour-1 half its own).  An entry
+// that holds no interior node keeps its stored value.
 template <typename TM, typename TA>
 __device__ __forceinline__ void sweep_pair(const Geo &g, int colour, int mask, TA omega_m, TA omega_t, TA st,
                                            const SweepArgs<TM> &a, int p, int j, int k, double (&r2)[4])
@@ -886,33 +928,15 @@ __device__ __forceinline__ void sweep_pair(const Geo &g, int colour, int mask, T
     const size_t me = (size_t)colour * g.cs + row + q0, xb = ob + row + q0;
     const size_t yp = ob + rowid(g, j + 1, k) + q0, ym = ob + rowid(g, j - 1, k) + q0;
     const size_t zp = ob + rowid(g, j, k + 1) + q0, zm = ob + rowid(g, j, k - 1) + q0;
-    // neighbour codes of mom_off / theta_off: 0 x+, 1 x-, 2 y+, 3 y-, 4 z+, 5 z-
-    RowIdx code;
-    code.me = 6;
-    code.xp = 0;
-    code.xm = 1;
-    code.yp = 2;
-    code.ym = 3;
-    code.zp = 4;
-    code.zm = 5;
-    // the other colour's values around the pair: x neighbours (x- of entry 0, the
-    // shared one, x+ of entry 1), then y+, y-, z+, z- of both entries
+    const RowIdx code = pair_codes();
+    const bool zs = (mask >> 5) & 1, nz = zs && colour == 0;
     auto around = [&](const TM *d, TA (&n0)[6], TA (&n1)[6]) {
-        TA xlo, xmid, xhi;
-        if (par) {
-            const auto t = ld_pair(d, xb);
-            xlo = (TA)t.x;
-            xmid = (TA)t.y;
-            xhi = (TA)d[xb + 2];
-        } else {
-            xlo = (TA)d[xb - 1];
-            const auto t = ld_pair(d, xb);
-            xmid = (TA)t.x;
-            xhi = (TA)t.y;
+        pair_around<TM, TA>(d, par, xb, yp, ym, zp, zm, n0, n1);
+#pragma unroll
+        for (int x = 0; x < 6; ++x) {
+            n0[x] = nz ? (TA)0 : n0[x];
+            n1[x] = nz ? (TA)0 : n1[x];
         }
-        const auto y1 = ld_pair(d, yp), y0 = ld_pair(d, ym), z1 = ld_pair(d, zp), z0 = ld_pair(d, zm);
-        n0[0] = xmid; n0[1] = xlo; n0[2] = (TA)y1.x; n0[3] = (TA)y0.x; n0[4] = (TA)z1.x; n0[5] = (TA)z0.x;
-        n1[0] = xhi; n1[1] = xmid; n1[2] = (TA)y1.y; n1[3] = (TA)y0.y; n1[4] = (TA)z1.y; n1[5] = (TA)z0.y;
     };
     if (mask & 1) {
         const auto sv = ld_pair(a.ms, me), axv = ld_pair(a.ma[0], me), ayv = ld_pair(a.ma[1], me),
@@ -928,7 +952,7 @@ __device__ __forceinline__ void sweep_pair(const Geo &g, int colour, int mask, T
             const TA sum0 = mom_off<TA>(s0, ax0, ay0, az0, code, [&](size_t x) { return n0[x]; });
             const TA sum1 = mom_off<TA>(s1, ax1, ay1, az1, code, [&](size_t x) { return n1[x]; });
             const auto oldv = ld_pair(d, me), bv = ld_pair(a.mb[f], me);
-            const TA old0 = (TA)oldv.x, old1 = (TA)oldv.y;
+            const TA old0 = zs ? (TA)0 : (TA)oldv.x, old1 = zs ? (TA)0 : (TA)oldv.y;
             const TA dlt0 = (TA)bv.x - sum0 - old0, dlt1 = (TA)bv.y - sum1 - old1;
             st_pair(d, me, v0 ? (TM)(old0 + omega_m * dlt0) : oldv.x, v1 ? (TM)(old1 + omega_m * dlt1) : oldv.y);
             r2[f] = (v0 ? (double)dlt0 * (double)dlt0 : 0.0) + (v1 ? (double)dlt1 * (double)dlt1 : 0.0);
@@ -945,7 +969,7 @@ __device__ __forceinline__ void sweep_pair(const Geo &g, int colour, int mask, T
         const TA sum1 = theta_off<TA>(st, (TA)axv.y, (TA)ayv.y, (TA)azv.y, j, k, N, code,
                                       [&](size_t x) { return n1[x]; }, den1);
         const auto oldv = ld_pair(d, me), bv = ld_pair(a.tb, me);
-        const TA old0 = (TA)oldv.x, old1 = (TA)oldv.y;
+        const TA old0 = zs ? (TA)0 : (TA)oldv.x, old1 = zs ? (TA)0 : (TA)oldv.y;
         const TA gs0 = ((TA)bv.x - sum0) / den0, gs1 = ((TA)bv.y - sum1) / den1;
         const TA dlt0 = gs0 - old0, dlt1 = gs1 - old1;
         st_pair(d, me, v0 ? (TM)(old0 + omega_t * dlt0) : oldv.x, v1 ? (TM)(old1 + omega_t * dlt1) : oldv.y);
@@ -1008,7 +1032,8 @@ struct FusedSweepCav {
     SweepArgs<TM> a;
     TA omega_m, omega_t, st;
     int plan_m, plan_t;             // sweeps of this batch per group (0: group idle)
-    int skip, pad;                  // momentum fields left alone (bits 0..2)
+    int skip;                       // momentum fields left alone (bits 0..2)
+    int zs;                         // 1: sweep 0 of this batch starts the solve from zero
     double *part[2], *part0[2];     // partial records per colour: last sweep, first sweep
 };
 
@@ -1023,7 +1048,8 @@ __global__ void __launch_bounds__(256) k_sweep_fused(const TileMap *__restrict__
         const int c = find_cavity(map, ncav, t);
         const TileMap m = map[c];
         const FusedSweepCav<TM, TA> &cv = cav[c];
-        const int mask = (qs < cv.plan_m ? 1 | (cv.skip << 2) : 0) | (qs < cv.plan_t ? 2 : 0);
+        const int mask = (qs < cv.plan_m ? 1 | (cv.skip << 2) : 0) | (qs < cv.plan_t ? 2 : 0)
+                         | (qs == 0 && cv.zs ? 32 : 0);
         if (!(mask & 3)) continue;    // uniform over the workgroup
         const unsigned store = (qs == cv.plan_m - 1 ? 0x7u : 0u) | (qs == cv.plan_t - 1 ? 0x8u : 0u);
         const unsigned store0 = (qs == 0 && cv.plan_m > 1 ? 0x7u : 0u) | (qs == 0 && cv.plan_t > 1 ? 0x8u : 0u);
@@ -1189,65 +1215,109 @@ __global__ void __launch_bounds__(1024) k_bicg_scalars(int phase, int mask, cons
 }
 
 // ---------------------------------------------------------------------------
-// Iterative refinement of the precision mode.  For the nodes of one colour:
-// fold the FP32 correction into the FP64 increment (d <- d + e, e <- 0) and form
-// the FP64 residual r = b - B d of the scaled FP64 rows (so the refinement
-// converges to the FP64 solution); r goes to FP32 for the next inner solve.  Neighbours contribute d + e:
-// before their colour is folded that is the corrected value, afterwards e = 0.
-// Per-block partial sums of ||r||^2 for the systems in `mask`.
+// Iterative refinement of the precision mode, one launch per outer pass over both
+// colours.  The current iterate is d + e (FP64 increment plus the FP32 correction
+// of the last inner solve) for the systems in `emask` (bit f: system f's
+// correction is valid) and d alone for the others.  Every node forms the FP64
+// residual r = b - B (d + e) of the scaled FP64 rows (so the refinement converges
+// to the FP64 solution, not to that of the FP32 rows) and stores it in FP32 for
+// the next inner solve, which starts from e = 0 without reading e.  A system in
+// emask also has its folded iterate d + e written to the second increment buffer
+// dn: folded in place, a neighbour could read a node's d + e after its fold.
+// Two colour-row entries per thread as in the sweeps; per-block partial sums of
+// ||r||^2 per colour.
 // ---------------------------------------------------------------------------
 template <typename TR>
 struct RefineArgs {
     const TR *ms, *ma[3], *ta[3];   // rows (FP64)
     const double *b[4];             // right-hand sides (u, v, w, theta)
-    double *d[4];                   // increments (FP64)
-    float *e[4];                    // corrections from the inner solve
+    const double *d[4];             // increments (FP64)
+    double *dn[4];                  // folded increments (systems in emask)
+    const float *e[4];              // corrections from the inner solve
     float *r[4];                    // residuals for the inner solve
 };
 
 template <typename TR>
-__device__ __forceinline__ void refine_node(const Geo &g, int colour, int mask, double st, const RefineArgs<TR> &a,
-                                            int q, int j, int k, double (&acc)[4])
+__device__ __forceinline__ void refine_pair(const Geo &g, int colour, int mask, int emask, double st,
+                                            const RefineArgs<TR> &a, int p, int j, int k, double (&acc)[4])
 {
-    RowIdx r;
-    if (row_index(g, colour, q, j, k, r)) {
+    const int N = g.N, q0 = 2 * p;
+    if (q0 >= g.Q || j > N - 2 || k > N - 2) return;
+    const int par = (colour + j + k) & 1;
+    const int i0 = 2 * q0 + par;
+    const bool v0 = i0 >= 1 && i0 <= N - 2;
+    const bool v1 = q0 + 1 < g.Q && i0 + 2 <= N - 2;
+    const size_t row = rowid(g, j, k), ob = (size_t)(1 - colour) * g.cs;
+    const size_t me = (size_t)colour * g.cs + row + q0, xb = ob + row + q0;
+    const size_t yp = ob + rowid(g, j + 1, k) + q0, ym = ob + rowid(g, j - 1, k) + q0;
+    const size_t zp = ob + rowid(g, j, k + 1) + q0, zm = ob + rowid(g, j, k - 1) + q0;
+    const RowIdx code = pair_codes();
+    double2 sv{0.0, 0.0}, axv{0.0, 0.0}, ayv{0.0, 0.0}, azv{0.0, 0.0};
+    if (mask & 1) {
+        sv = ld_pair(a.ms, me);
+        axv = ld_pair(a.ma[0], me);
+        ayv = ld_pair(a.ma[1], me);
+        azv = ld_pair(a.ma[2], me);
+    }
 #pragma unroll
-        for (int f = 0; f < 4; ++f) {
-            if (!((f < 3) ? (mask & 1) : (mask & 2))) continue;
-            const double *D = a.d[f];
-            const float *Ec = a.e[f];
-            auto val = [&](size_t i) { return D[i] + (double)Ec[i]; };
-            const double own = val(r.me);
-            double bx;
-            if (f < 3) {
-                bx = own + mom_off<double>((double)a.ms[r.me], (double)a.ma[0][r.me], (double)a.ma[1][r.me],
-                                           (double)a.ma[2][r.me], r, val);
-            } else {
-                double den;
-                const double off = theta_off<double>(st, (double)a.ta[0][r.me], (double)a.ta[1][r.me],
-                                                     (double)a.ta[2][r.me], j, k, g.N, r, val, den);
-                bx = den * own + off;
+    for (int f = 0; f < 4; ++f) {
+        if (!((f < 3) ? (mask & 1) : (mask & 2))) continue;
+        const bool fold = (emask >> f) & 1;
+        double n0[6], n1[6];
+        pair_around<double, double>(a.d[f], par, xb, yp, ym, zp, zm, n0, n1);
+        const auto dv = ld_pair(a.d[f], me);
+        double own0 = dv.x, own1 = dv.y;
+        if (fold) {
+            double e0[6], e1[6];
+            pair_around<float, double>(a.e[f], par, xb, yp, ym, zp, zm, e0, e1);
+#pragma unroll
+            for (int x = 0; x < 6; ++x) {
+                n0[x] += e0[x];
+                n1[x] += e1[x];
             }
-            const double rr = a.b[f][r.me] - bx;
-            a.d[f][r.me] = own;
-            a.e[f][r.me] = 0.0f;
-            a.r[f][r.me] = (float)rr;
-            acc[f] = rr * rr;
+            const auto ev = ld_pair(a.e[f], me);
+            own0 += (double)ev.x;
+            own1 += (double)ev.y;
         }
+        double bx0, bx1;
+        if (f < 3) {
+            bx0 = own0 + mom_off<double>((double)sv.x, (double)axv.x, (double)ayv.x, (double)azv.x, code,
+                                         [&](size_t x) { return n0[x]; });
+            bx1 = own1 + mom_off<double>((double)sv.y, (double)axv.y, (double)ayv.y, (double)azv.y, code,
+                                         [&](size_t x) { return n1[x]; });
+        } else {
+            const auto axv = ld_pair(a.ta[0], me), ayv = ld_pair(a.ta[1], me), azv = ld_pair(a.ta[2], me);
+            double den0, den1;
+            const double off0 = theta_off<double>(st, (double)axv.x, (double)ayv.x, (double)azv.x, j, k, N, code,
+                                                  [&](size_t x) { return n0[x]; }, den0);
+            const double off1 = theta_off<double>(st, (double)axv.y, (double)ayv.y, (double)azv.y, j, k, N, code,
+                                                  [&](size_t x) { return n1[x]; }, den1);
+            bx0 = den0 * own0 + off0;
+            bx1 = den1 * own1 + off1;
+        }
+        const auto bv = ld_pair(a.b[f], me);
+        const double rr0 = bv.x - bx0, rr1 = bv.y - bx1;
+        st_pair(a.r[f], me, v0 ? (float)rr0 : 0.0f, v1 ? (float)rr1 : 0.0f);
+        if (fold) st_pair(a.dn[f], me, v0 ? own0 : dv.x, v1 ? own1 : dv.y);
+        acc[f] = (v0 ? rr0 * rr0 : 0.0) + (v1 ? rr1 * rr1 : 0.0);
     }
 }
 
+// Tiles of the sweep launch's shape for both colours: tile z = 2 (k - 1) + colour,
+// so the run of tiles an XCD takes holds both colours of its planes.  The record
+// of a tile is its index within its colour.
 template <typename TR>
-__global__ void __launch_bounds__(256) k_refine_residual(Geo g, int colour, int mask, double st, RefineArgs<TR> a,
-                                                         double *__restrict__ partial)
+__global__ void __launch_bounds__(256) k_refine_pass(Geo g, int mask, int emask, double st, RefineArgs<TR> a,
+                                                     double *__restrict__ part_r, double *__restrict__ part_b)
 {
     const Tile tl = xcd_tile();
-    const int q = tl.x * blockDim.x + threadIdx.x;
-    const int j = 1 + tl.y * blockDim.y + threadIdx.y, k = 1 + tl.z;
+    const int colour = tl.z & 1, kz = tl.z >> 1;
+    const int p = tl.x * blockDim.x + threadIdx.x;
+    const int j = 1 + tl.y * blockDim.y + threadIdx.y, k = 1 + kz;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    refine_node<TR>(g, colour, mask, st, a, q, j, k, acc);
-    const int blk = tl.id;
-    block_sum_store<4>(acc, partial + (size_t)blk * 4);
+    refine_pair<TR>(g, colour, mask, emask, st, a, p, j, k, acc);
+    const int blk = tl.x + (int)gridDim.x * (tl.y + (int)gridDim.y * kz);
+    block_sum_store<4>(acc, (colour ? part_b : part_r) + (size_t)blk * 4);
 }
 
 template <typename TR>
@@ -1256,27 +1326,30 @@ struct FusedRefineCav {
     RefineArgs<TR> a;
     double st;
     int mask;                       // groups refined (0: cavity idle)
-    int pad;
+    int emask;                      // systems whose correction is folded
     double *part[2];                // partial records per colour
 };
 
+// One outer pass over every cavity: global tile t is colour t & 1 of the sweep
+// tile t >> 1 of the batch's tile list.
 template <typename TR>
 __global__ void __launch_bounds__(256) k_refine_fused(const TileMap *__restrict__ map,
-                                                      const FusedRefineCav<TR> *__restrict__ cav, int ncav, int total,
-                                                      int colour)
+                                                      const FusedRefineCav<TR> *__restrict__ cav, int ncav, int total)
 {
     const int G = gridDim.x;
-    for (int t = persistent_slot(blockIdx.x, G); t < total; t += G) {
-        const int c = find_cavity(map, ncav, t);
+    for (int t = persistent_slot(blockIdx.x, G); t < 2 * total; t += G) {
+        const int base = t >> 1, colour = t & 1;
+        const int c = find_cavity(map, ncav, base);
         const TileMap m = map[c];
         const FusedRefineCav<TR> &cv = cav[c];
         if (!cv.mask) continue;
-        const int lt = t - m.tile0;
+        const int lt = base - m.tile0;
         const int bx = lt % m.tiles_x, rest = lt / m.tiles_x;
         const int by = rest % m.tiles_y, bz = rest / m.tiles_y;
         const int tx = threadIdx.x % m.tx, ty = threadIdx.x / m.tx;
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        refine_node<TR>(cv.g, colour, cv.mask, cv.st, cv.a, bx * m.tx + tx, 1 + by * m.ty + ty, 1 + bz, acc);
+        refine_pair<TR>(cv.g, colour, cv.mask, cv.emask, cv.st, cv.a, bx * m.tx + tx, 1 + by * m.ty + ty, 1 + bz,
+                        acc);
         block_sum_store<4>(acc, cv.part[colour] + (size_t)lt * 4);
         __syncthreads();
     }
