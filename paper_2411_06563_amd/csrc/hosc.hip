@@ -1242,7 +1242,8 @@ hosc_status assemble(hosc_solver *s, bool rows32)
     ca.tb = s->tb;
     hosc_status r = timed_begin(s);
     if (r) return r;
-    k_assemble<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(
+    const unsigned slab_blocks = s->L.grd_int.x * ((s->L.grd_int.y + 7) / 8) * s->L.grd_int.z * 8;
+    k_assemble<<<slab_blocks, s->L.blk_int, 0, s->st>>>(
         s->g, s->ph, s->u, s->v, s->w, s->T, s->eta, s->E[0], s->E[1], s->E[2], s->u2, s->v2, s->w2, s->etap,
         s->Ep[0], s->Ep[1], s->Ep[2], ca, s->partR, s->partB);
     if (s->fp32 && rows32)    // a streaming pass: cheaper than the FP32 stores inside the assembly (register budget)

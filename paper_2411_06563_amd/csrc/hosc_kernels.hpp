@@ -247,6 +247,26 @@ __device__ __forceinline__ Tile xcd_tile()
     return t;
 }
 
+// Slab-ordered tiles of the interior launch (64 x 4 threads, one plane per tile
+// row): the gy y-tiles are cut into eight slabs of ys = ceil(gy/8), one per XCD,
+// and an XCD walks its slab plane after plane (x fastest, then y within the slab,
+// then z), so the planes k-1, k, k+1 that a 19-point stencil reads are still in its
+// L2 when the next plane needs them.  The launch is 1D with gx * ys * gz * 8
+// workgroups; those past the last y-tile return at once (all their threads).  The
+// tile id (and its partial-sum record) is the plain linear order.
+__device__ __forceinline__ bool slab_tile(int gx, int gy, int gz, Tile &t)
+{
+    const int ys = (gy + 7) >> 3, per = gx * ys * gz;
+    const int id = persistent_slot((int)blockIdx.x, 8 * per);
+    const int slab = id / per, r = id - slab * per;
+    t.x = r % gx;
+    const int rest = r / gx;
+    t.z = rest / ys;
+    t.y = slab * ys + (rest - t.z * ys);
+    t.id = t.x + gx * (t.y + gy * t.z);
+    return t.y < gy;
+}
+
 // Node of a thread in a launch over every node: one thread per node in storage
 // order (x fastest), 256-thread blocks of a 1D grid taken in XCD-grouped order, so
 // no wave idles on the partial x-rows a 2D tiling leaves when N is not a multiple
@@ -581,7 +601,9 @@ __global__ void __launch_bounds__(256) k_assemble(Geo g, Phys P, const double *_
                                                   ColourArrays ca, double *__restrict__ partial,
                                                   double *__restrict__ partial_dom)
 {
-    const Tile tl = xcd_tile();
+    const int M = g.N - 2;
+    Tile tl;
+    if (!slab_tile((M + 63) >> 6, (M + 3) >> 2, M, tl)) return;
     const int i = 1 + tl.x * blockDim.x + threadIdx.x, j = 1 + tl.y * blockDim.y + threadIdx.y, k = 1 + tl.z;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     double dom[2] = {0.0, 0.0};     // off-diagonal sum / |centre| of the momentum and energy rows
