@@ -490,13 +490,24 @@ hosc_status stage_sources(hosc_solver *s, bool consume_first)
     hosc_status r = launch_check(s, "eta/estar");
     if (r) return r;
     if (s->first) {
-        const size_t b = s->g.n3 * sizeof(double);
-        HIPCHK(s, hipMemcpyAsync(s->u2, s->u, b, hipMemcpyDeviceToDevice, s->st));
-        HIPCHK(s, hipMemcpyAsync(s->v2, s->v, b, hipMemcpyDeviceToDevice, s->st));
-        HIPCHK(s, hipMemcpyAsync(s->w2, s->w, b, hipMemcpyDeviceToDevice, s->st));
-        HIPCHK(s, hipMemcpyAsync(s->etap, s->eta, b, hipMemcpyDeviceToDevice, s->st));
-        for (int d = 0; d < 3; ++d)
-            HIPCHK(s, hipMemcpyAsync(s->Ep[d], s->E[d], b, hipMemcpyDeviceToDevice, s->st));
+        // level n-1 := level n for u, v, w, eta and E*, in two copy launches (each
+        // natural array is 256-byte aligned and padded, so an odd n3 rounds up to
+        // whole 16-byte pairs inside its region)
+        const double *src[7] = {s->u, s->v, s->w, s->eta, s->E[0], s->E[1], s->E[2]};
+        double *dst[7] = {s->u2, s->v2, s->w2, s->etap, s->Ep[0], s->Ep[1], s->Ep[2]};
+        const size_t n = (s->g.n3 + 1) / 2;
+        const unsigned blocks = (unsigned)std::min<size_t>(2048, (n + 255) / 256);
+        for (int a0 = 0; a0 < 7; a0 += 4) {
+            Copies4 cp{};
+            for (int a = a0; a < std::min(7, a0 + 4); ++a) {
+                cp.src[cp.count] = reinterpret_cast<const double2 *>(src[a]);
+                cp.dst[cp.count] = reinterpret_cast<double2 *>(dst[a]);
+                cp.count += 1;
+            }
+            k_copy4<<<blocks, 256, 0, s->st>>>(cp, n);
+        }
+        r = launch_check(s, "level copies");
+        if (r) return r;
         if (consume_first) s->first = false;
     }
     return HOSC_OK;
@@ -1052,16 +1063,23 @@ void refine_folded(RefCtl &c)
     c.emask = 0;
 }
 
-// Systems whose increment sits in the second buffer are copied back (stream order).
+// Systems whose increment sits in the second buffer are copied back, in one launch
+// (stream order; the colour arrays hold 2 cs doubles, an even count, 256-byte aligned).
 hosc_status refine_end(hosc_solver *s, RefCtl &c, hipStream_t st)
 {
-    const size_t b = 2 * s->g.cs * sizeof(double);
+    Copies4 cp{};
     for (int f = 0; f < 4; ++f)
         if (c.cur[f] != primary_increment(s, f)) {
-            HIPCHK(s, hipMemcpyAsync(primary_increment(s, f), c.cur[f], b, hipMemcpyDeviceToDevice, st));
+            cp.src[cp.count] = reinterpret_cast<const double2 *>(c.cur[f]);
+            cp.dst[cp.count] = reinterpret_cast<double2 *>(primary_increment(s, f));
+            cp.count += 1;
             std::swap(c.cur[f], c.oth[f]);
         }
-    return HOSC_OK;
+    if (!cp.count) return HOSC_OK;
+    const size_t n = s->g.cs;     // 2 cs doubles = cs pairs
+    const unsigned blocks = (unsigned)std::min<size_t>(2048, (n + 255) / 256);
+    k_copy4<<<blocks, 256, 0, st>>>(cp, n);
+    return launch_check(s, "increment copy");
 }
 
 // Decisions after a residual pass, from the reduction block hb (the cavity's

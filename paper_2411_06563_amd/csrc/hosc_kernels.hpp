@@ -1782,4 +1782,17 @@ __global__ void __launch_bounds__(256) k_copy(const double2 *__restrict__ src, d
         dst[q] = src[q];
 }
 
+// Up to four device-to-device copies of n 16-byte elements in one grid-stride launch.
+struct Copies4 {
+    const double2 *src[4];
+    double2 *dst[4];
+    int count;
+};
+__global__ void __launch_bounds__(256) k_copy4(Copies4 c, size_t n)
+{
+    for (int a = 0; a < c.count; ++a)
+        for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x)
+            c.dst[a][q] = c.src[a][q];
+}
+
 }  // namespace hosc
