@@ -151,7 +151,7 @@ typedef struct hosc_perf {
     int64_t bicg_launches;      /* BiCGSTAB vector-phase launches (matrix-vector products and updates) */
     double bicg_ms;
     double bicg_bytes;          /* per launch: rows of the active systems once, each vector read or written once */
-    int64_t refine_launches;    /* precision mode: FP64 refinement-residual launches (one colour each) */
+    int64_t refine_launches;    /* precision mode: FP64 refinement passes (one launch over both colours each) */
     double refine_ms;
     double refine_bytes;
 } hosc_perf;
@@ -304,8 +304,8 @@ const char *hosc_status_string(hosc_status st);
  * Batches: many cavities (any mix of N, Ra, Pr, n, dt; one precision) advanced
  * together on one stream.  Each cavity is an hosc_solver carved from the batch
  * workspace; the implicit solves of all cavities run as fused launches (one
- * persistent launch per red-black half-sweep and per refinement-residual colour
- * over every cavity still iterating, one launch for all reductions and one host
+ * persistent launch per red-black half-sweep and per refinement pass (both
+ * colours) over every cavity still iterating, one launch for all reductions and one host
  * copy per convergence check), while each cavity keeps exactly the arithmetic and
  * solver decisions of its single-cavity run, so a cavity's results do not depend
  * on the batch it is in.

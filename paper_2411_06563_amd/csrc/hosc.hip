@@ -1456,7 +1456,7 @@ hosc_status one_step(hosc_solver *s, hosc_step_info *info)
 // Fused multi-cavity execution (batches and the server).  The per-cavity phases
 // above are reused unchanged; the solver phases, which dominate, run as fused
 // launches over every cavity that still iterates: one persistent launch per
-// half-sweep, one per refinement-residual colour, one launch for all the
+// half-sweep, one per refinement pass (both colours), one launch for all the
 // reductions and one gather + host copy per convergence check.
 // ---------------------------------------------------------------------------
 constexpr size_t kCavEntry = 512;     // bytes reserved per cavity for a fused-launch descriptor
