@@ -131,7 +131,7 @@ Layout make_layout(const Geo &g, const Launch &L, int solver, int precision)
     b += align_up(kRed * sizeof(double));                      // reduction outputs
     b += align_up((size_t)g.N * sizeof(double));               // Simpson weights
     b += 2 * align_up((size_t)g.N * g.N * sizeof(double));     // Nu_local hot / cold
-    b += 2 * align_up((size_t)g.N * sizeof(double));           // Nu_avg hot / cold
+    b += 3 * align_up((size_t)g.N * sizeof(double));           // Nu_avg hot / cold, hot-wall row maxima
     b += align_up(8 * sizeof(double));                         // Nu scalars
     b += align_up(32 * sizeof(double));                        // BiCGSTAB scalars
     y.total_bytes = b;
@@ -212,7 +212,7 @@ struct hosc_solver {
     double *u_first = nullptr;      // the buffer u had at creation (level parity of the swapped pointers)
     // colour layout
     double *ms, *ma[3], *mb[3], *md[3], *ta[3], *tb, *td;
-    double *partR, *partB, *partR0, *partB0, *red, *wq, *nuh, *nuc, *avh, *avc, *nuout;
+    double *partR, *partB, *partR0, *partB0, *red, *wq, *nuh, *nuc, *avh, *avc, *mxh, *nuout;
     // BiCGSTAB vectors (4 systems) and scalars
     double *br[4], *brh[4], *bp[4], *bpn[4], *bv[4], *bvn[4], *bt[4];
     double *bsc;
@@ -321,6 +321,7 @@ void carve(hosc_solver *s, char *base)
     s->nuc = take(align_up((size_t)s->g.N * s->g.N * sizeof(double)));
     s->avh = take(align_up((size_t)s->g.N * sizeof(double)));
     s->avc = take(align_up((size_t)s->g.N * sizeof(double)));
+    s->mxh = take(align_up((size_t)s->g.N * sizeof(double)));
     s->nuout = take(align_up(8 * sizeof(double)));
     s->bsc = take(align_up(32 * sizeof(double)));
     for (int f = 0; f < 4; ++f) s->br[f] = s->brh[f] = s->bp[f] = s->bpn[f] = s->bv[f] = s->bvn[f] = s->bt[f] = nullptr;
@@ -1325,35 +1326,36 @@ hosc_status pressure_iterations(hosc_solver *s, bool first, SolveOut &so)
 }
 
 // Update, theta walls, divergence (with the correction and the pressure walls when
-// the correction is not gated) and their reductions into red[12..22]; launches only.
+// the correction is not gated), the diagnostics of the new level and the step's
+// reductions into red[12..26] and red[56..60], in four launches; launches only.
 hosc_status post_launch(hosc_solver *s)
 {
     // update: u, v, w into the level n-1 buffers (which become level n+1)
     k_update<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, s->u, s->v, s->w, s->u2, s->v2, s->w2, s->T, s->md[0],
                                                        s->md[1], s->md[2], s->td, s->partR);
-    k_theta_walls<<<s->L.grd_face, s->L.blk_face, 0, s->st>>>(s->g, s->ph, s->T, s->partB);
+    // divergence (and the correction when it is not gated) with the theta walls;
+    // then the entropy pass, which also leaves eta of level n+1 in the level n-1
+    // buffer (level n at the swap), with the pressure walls and the Nusselt rows of
+    // level n+1; then every reduction of the step and the Nusselt means (red[12..26],
+    // red[56..60])
     const bool gate = s->P.div_tol > 0.0;
-    k_divergence<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, s->ph, s->u2, s->v2, s->w2, s->p,
-                                                           gate ? s->dbg : nullptr, gate ? 0 : 1, s->partR0);
-    if (!gate) k_p_walls<<<s->L.grd_face, s->L.blk_face, 0, s->st>>>(s->g, s->p);
-    // the step finishes with the Nusselt, entropy and Bejan reductions of level n+1
-    // (red[56..60] and red[24..26]); the entropy pass also leaves eta of level n+1 in
-    // the level n-1 buffer, which becomes level n at the swap
     const Geo &g = s->g;
-    dim3 b2(16, 16), g2((g.N + 15) / 16, (g.N + 15) / 16);
-    k_nu_local<<<g2, b2, 0, s->st>>>(g, s->T, s->nuh, s->nuc);
-    k_nu_avg<<<g.N, 256, 0, s->st>>>(g, s->wq, s->nuh, s->nuc, s->avh, s->avc);
-    k_nu_final<<<1, 1024, 0, s->st>>>(g, s->wq, s->avh, s->avc, s->nuh, s->red + 56);
+    const int nd = (int)s->L.nb_int, nf = (int)s->L.nb_face, ne = (int)s->L.nb_all;
+    k_tail_div_walls<<<nd + nf, 256, 0, s->st>>>(g, s->ph, s->u2, s->v2, s->w2, s->p, gate ? s->dbg : nullptr,
+                                                 gate ? 0 : 1, s->partR0, (int)s->L.grd_int.x, (int)s->L.grd_int.y,
+                                                 nd, s->T, s->partB, (int)s->L.grd_face.x, (int)s->L.grd_face.y);
     const bool relax = s->P.eta_relax < 1.0;     // level n's viscosity is s->eta until the swap
-    k_entropy<<<s->L.grd_all, s->L.blk_all, 0, s->st>>>(g, s->ph, s->wq, s->u2, s->v2, s->w2, s->T, nullptr, nullptr,
-                                                         s->etap, s->partB0, relax ? s->eta : nullptr,
-                                                         s->P.eta_relax);
-    Reductions()
-        .add(s->partR, s->L.nb_int, 8, 0, s->red + 12)
+    const int nfp = gate ? 0 : nf;               // gated: the pressure walls follow the correction (post_finish)
+    k_tail_diag<<<ne + nfp + g.N, 256, 0, s->st>>>(g, s->ph, s->wq, s->u2, s->v2, s->w2, s->T, s->etap, s->partB0,
+                                                   relax ? s->eta : nullptr, s->P.eta_relax, ne, s->p, nfp,
+                                                   (int)s->L.grd_face.x, (int)s->L.grd_face.y, s->nuh, s->nuc,
+                                                   s->avh, s->avc, s->mxh);
+    Reductions rd;
+    rd.add(s->partR, s->L.nb_int, 8, 0, s->red + 12)
         .add(s->partB, s->L.nb_face, 2, 0, s->red + 20)
         .add(s->partR0, s->L.nb_int, 1, 1, s->red + 22)
-        .add(s->partB0, s->L.nb_all, 3, 0, s->red + 24)
-        .launch(s->st);
+        .add(s->partB0, s->L.nb_all, 3, 0, s->red + 24);
+    k_tail_reduce<<<rd.n + 1, 1024, 0, s->st>>>(rd.r, rd.n, g, s->wq, s->avh, s->avc, s->mxh, s->red + 56);
     return launch_check(s, "update/divergence/diagnostics");
 }
 
@@ -2434,10 +2436,8 @@ hosc_status hosc_diagnostics(hosc_solver *s, hosc_diag *d, double *nuavg_hot, do
         if (nuavg_hot || nuavg_cold || nu_hot || nu_cold) HIPCHK(s, hipStreamSynchronize(s->st));
         return HOSC_OK;
     }
-    dim3 b2(16, 16), g2((g.N + 15) / 16, (g.N + 15) / 16);
-    k_nu_local<<<g2, b2, 0, s->st>>>(g, s->T, s->nuh, s->nuc);
-    k_nu_avg<<<g.N, 256, 0, s->st>>>(g, s->wq, s->nuh, s->nuc, s->avh, s->avc);
-    k_nu_final<<<1, 1024, 0, s->st>>>(g, s->wq, s->avh, s->avc, s->nuh, s->nuout);
+    k_nu_rows<<<g.N, 256, 0, s->st>>>(g, s->wq, s->T, s->nuh, s->nuc, s->avh, s->avc, s->mxh);
+    k_nu_final<<<1, 1024, 0, s->st>>>(g, s->wq, s->avh, s->avc, s->mxh, s->nuout);
     k_entropy<<<s->L.grd_all, s->L.blk_all, 0, s->st>>>(g, s->ph, s->wq, s->u, s->v, s->w, s->T, nullptr, nullptr,
                                                          nullptr, s->partR);
     k_reduce<<<1, 1024, 0, s->st>>>(s->partR, (int)s->L.nb_all, 3, 0, s->red + 24);
@@ -3083,7 +3083,8 @@ constexpr size_t kNaOffAvh = kNaOffWq + round32(kNaN);
 constexpr size_t kNaOffAvc = kNaOffAvh + round32(kNaN);
 constexpr size_t kNaOffNuh = kNaOffAvc + round32(kNaN);
 constexpr size_t kNaOffNuc = kNaOffNuh + round32(kNaN * kNaN);
-constexpr size_t kNaOffNu = kNaOffNuc + round32(kNaN * kNaN);
+constexpr size_t kNaOffMx = kNaOffNuc + round32(kNaN * kNaN);
+constexpr size_t kNaOffNu = kNaOffMx + round32(kNaN);
 constexpr size_t kNaOffEnt = kNaOffNu + round32(8);
 constexpr size_t kNaOffPart = kNaOffEnt + round32(8);
 // entropy partial sums: 3 per block of the all-node launch (256 nodes per block)
@@ -3144,15 +3145,13 @@ extern "C" hosc_status hosc_diagnostics_noalloc(const hosc_params *p, const doub
     ph.lambda = p->lambda > 0.0 ? p->lambda : g.h * g.h / (3.0 * p->dt);
     ph.phi = p->phi;
     double *wq = base + kNaOffWq, *nuh = base + kNaOffNuh, *nuc = base + kNaOffNuc;
-    double *nu = base + kNaOffNu, *ent = base + kNaOffEnt, *part = base + kNaOffPart;
+    double *nu = base + kNaOffNu, *ent = base + kNaOffEnt, *part = base + kNaOffPart, *mxh = base + kNaOffMx;
     double *avh = d_nuavg_hot ? d_nuavg_hot : base + kNaOffAvh;
     double *avc = d_nuavg_cold ? d_nuavg_cold : base + kNaOffAvc;
     const int N = g.N;
     k_simpson_weights<<<(N + 255) / 256, 256, 0, stream>>>(N, wq);
-    dim3 b2(16, 16), g2((N + 15) / 16, (N + 15) / 16);
-    k_nu_local<<<g2, b2, 0, stream>>>(g, d_theta, nuh, nuc);
-    k_nu_avg<<<N, 256, 0, stream>>>(g, wq, nuh, nuc, avh, avc);
-    k_nu_final<<<1, 1024, 0, stream>>>(g, wq, avh, avc, nuh, nu);
+    k_nu_rows<<<N, 256, 0, stream>>>(g, wq, d_theta, nuh, nuc, avh, avc, mxh);
+    k_nu_final<<<1, 1024, 0, stream>>>(g, wq, avh, avc, mxh, nu);
     k_entropy<<<L.grd_all, L.blk_all, 0, stream>>>(g, ph, wq, d_u, d_v, d_w, d_theta, nullptr, nullptr, nullptr,
                                                      part);
     k_reduce<<<1, 1024, 0, stream>>>(part, (int)L.nb_all, 3, 0, ent);

@@ -234,17 +234,23 @@ __device__ __forceinline__ int persistent_slot(int b, int G)
 struct Tile {
     int x, y, z, id;
 };
+// Tile of block b of a launch of G = gx * gy * gz blocks (gx, gy: the grid's x and y
+// extents), in the XCD-grouped order.
+__device__ __forceinline__ Tile xcd_tile_of(int b, int G, int gx, int gy)
+{
+    Tile t;
+    t.id = persistent_slot(b, G);
+    t.x = t.id % gx;
+    const int rest = t.id / gx;
+    t.y = rest % gy;
+    t.z = rest / gy;
+    return t;
+}
 __device__ __forceinline__ Tile xcd_tile()
 {
     const int G = gridDim.x * gridDim.y * gridDim.z;
     const int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-    Tile t;
-    t.id = persistent_slot(b, G);
-    t.x = t.id % gridDim.x;
-    const int rest = t.id / gridDim.x;
-    t.y = rest % gridDim.y;
-    t.z = rest / gridDim.y;
-    return t;
+    return xcd_tile_of(b, G, gridDim.x, gridDim.y);
 }
 
 // Slab-ordered tiles of the interior launch (64 x 4 threads, one plane per tile
@@ -1439,9 +1445,10 @@ __device__ __forceinline__ double theta_closed(const Geo &g, const double *T, in
 }
 
 // Impose the theta walls; partial sums of (new - old)^2 and new^2 over wall nodes.
-__global__ void __launch_bounds__(256) k_theta_walls(Geo g, Phys P, double *__restrict__ T, double *__restrict__ partial)
+// One 64 x 4 block of the face launch: its node (a, b) on face f, its record blk.
+__device__ __forceinline__ void theta_walls_block(const Geo &g, const Phys &P, double *__restrict__ T,
+                                                  double *__restrict__ partial, int a, int b, int f, int blk)
 {
-    const int a = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y * blockDim.y + threadIdx.y, f = blockIdx.z;
     double acc[2] = {0.0, 0.0};
     int i, j, k;
     if (a < g.N && b < g.N && face_node(g.N, a, b, f, i, j, k)) {
@@ -1455,8 +1462,12 @@ __global__ void __launch_bounds__(256) k_theta_walls(Geo g, Phys P, double *__re
         acc[0] = d * d;
         acc[1] = nv * nv;
     }
-    const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
     block_sum_store<2>(acc, partial + (size_t)blk * 2);
+}
+__global__ void __launch_bounds__(256) k_theta_walls(Geo g, Phys P, double *__restrict__ T, double *__restrict__ partial)
+{
+    theta_walls_block(g, P, T, partial, blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y * blockDim.y + threadIdx.y,
+                      blockIdx.z, blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z));
 }
 
 // p walls: x faces at interior (j,k), then y faces at every x and interior z, then z
@@ -1483,11 +1494,14 @@ __device__ __forceinline__ double p_closed(const Geo &g, const double *p, int i,
     return p_y_closed(g, p, i, j, k);
 }
 
-__global__ void __launch_bounds__(256) k_p_walls(Geo g, double *__restrict__ p)
+__device__ __forceinline__ void p_walls_node(const Geo &g, double *__restrict__ p, int a, int b, int f)
 {
-    const int a = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y * blockDim.y + threadIdx.y, f = blockIdx.z;
     int i, j, k;
     if (a < g.N && b < g.N && face_node(g.N, a, b, f, i, j, k)) p[nid(g, i, j, k)] = p_closed(g, p, i, j, k);
+}
+__global__ void __launch_bounds__(256) k_p_walls(Geo g, double *__restrict__ p)
+{
+    p_walls_node(g, p, blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y * blockDim.y + threadIdx.y, blockIdx.z);
 }
 
 // No-slip walls (velocity 0) for set_state with boundary conditions.
@@ -1506,13 +1520,13 @@ __global__ void __launch_bounds__(256) k_zero_walls(Geo g, double *__restrict__ 
 // Modified artificial compressibility (Sec. 2.2): D = div v^{n+1} by central
 // differences at interior nodes, p <- p - lambda D (when apply != 0); partial max |D|.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_divergence(Geo g, Phys P, const double *__restrict__ u,
-                                                    const double *__restrict__ v, const double *__restrict__ w,
-                                                    double *__restrict__ p, double *__restrict__ dstore, int apply,
-                                                    double *__restrict__ partial)
+// One 64 x 4 tile of the interior launch (thread (tx, ty) of it).
+__device__ __forceinline__ void divergence_tile(const Geo &g, const Phys &P, const Tile &tl, int tx, int ty,
+                                                const double *__restrict__ u, const double *__restrict__ v,
+                                                const double *__restrict__ w, double *__restrict__ p,
+                                                double *__restrict__ dstore, int apply, double *__restrict__ partial)
 {
-    const Tile tl = xcd_tile();
-    const int i = 1 + tl.x * blockDim.x + threadIdx.x, j = 1 + tl.y * blockDim.y + threadIdx.y, k = 1 + tl.z;
+    const int i = 1 + tl.x * 64 + tx, j = 1 + tl.y * 4 + ty, k = 1 + tl.z;
     double acc[1] = {0.0};
     if (i <= g.N - 2 && j <= g.N - 2) {
         const size_t c = nid(g, i, j, k), sy = (size_t)g.N, sz = (size_t)g.N * g.N;
@@ -1608,60 +1622,64 @@ __global__ void __launch_bounds__(256) k_probe(Geo g, const double *__restrict__
     for (int f = 0; f < 5; ++f) out[5 * q + f] = acc[f];
 }
 
-// ---------------------------------------------------------------------------
-// Nusselt numbers (Sec. 4.2): Nu = -d theta/dx on x = 0 and x = 1 by the 5-point
-// 4th-order one-sided difference; Simpson over y gives Nu_avg(z); Simpson over z
-// the mean; the max over z of Nu_avg is the quantity of Table 2.
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_nu_local(Geo g, const double *__restrict__ T, double *__restrict__ nuh,
-                                                  double *__restrict__ nuc)
+// Nusselt numbers of one z-row k of both x-walls (Sec. 4.2): Nu_local = -dtheta/dx by
+// the 5-point one-sided 4th-order formula at every y-node j (stored at j + N k),
+// Nu_avg(z_k) = the Simpson-weighted sum over y, and the row's largest hot-wall
+// Nu_local.  One block of 256 threads per row; thread t takes j = t, t + 256, ... in
+// order, then fixed-order trees over the block: deterministic.
+__device__ __forceinline__ void nu_row_block(const Geo &g, const double *__restrict__ wq, const double *__restrict__ T,
+                                             double *__restrict__ nuh, double *__restrict__ nuc,
+                                             double *__restrict__ avh, double *__restrict__ avc,
+                                             double *__restrict__ mxh, int k)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x, k = blockIdx.y * blockDim.y + threadIdx.y;
-    if (j >= g.N || k >= g.N) return;
-    const int N = g.N;
+    __shared__ double sh[3][256];
+    const int t = threadIdx.x, N = g.N;
     const double inv12h = 1.0 / (12.0 * g.h);
-    const double dh = (-25.0 * T[nid(g, 0, j, k)] + 48.0 * T[nid(g, 1, j, k)] - 36.0 * T[nid(g, 2, j, k)]
-                       + 16.0 * T[nid(g, 3, j, k)] - 3.0 * T[nid(g, 4, j, k)]) * inv12h;
-    const double dc = (25.0 * T[nid(g, N - 1, j, k)] - 48.0 * T[nid(g, N - 2, j, k)] + 36.0 * T[nid(g, N - 3, j, k)]
-                       - 16.0 * T[nid(g, N - 4, j, k)] + 3.0 * T[nid(g, N - 5, j, k)]) * inv12h;
-    nuh[j + (size_t)N * k] = -dh;
-    nuc[j + (size_t)N * k] = -dc;
-}
-
-// Nu_avg(z_k) for both walls: one block of 256 threads per k, fixed-order tree
-// over the Simpson-weighted values along y.
-__global__ void __launch_bounds__(256) k_nu_avg(Geo g, const double *__restrict__ wq, const double *__restrict__ nuh,
-                                                const double *__restrict__ nuc, double *__restrict__ avh,
-                                                double *__restrict__ avc)
-{
-    __shared__ double sh[2][256];
-    const int k = blockIdx.x, t = threadIdx.x;
-    double a = 0.0, c = 0.0;
-    for (int j = t; j < g.N; j += 256) {
-        a += wq[j] * nuh[j + (size_t)g.N * k];
-        c += wq[j] * nuc[j + (size_t)g.N * k];
+    double a = 0.0, c = 0.0, m = -HUGE_VAL;
+    for (int j = t; j < N; j += 256) {
+        const double dh = (-25.0 * T[nid(g, 0, j, k)] + 48.0 * T[nid(g, 1, j, k)] - 36.0 * T[nid(g, 2, j, k)]
+                           + 16.0 * T[nid(g, 3, j, k)] - 3.0 * T[nid(g, 4, j, k)]) * inv12h;
+        const double dc = (25.0 * T[nid(g, N - 1, j, k)] - 48.0 * T[nid(g, N - 2, j, k)]
+                           + 36.0 * T[nid(g, N - 3, j, k)] - 16.0 * T[nid(g, N - 4, j, k)]
+                           + 3.0 * T[nid(g, N - 5, j, k)]) * inv12h;
+        const double nh = -dh, nc = -dc;
+        nuh[j + (size_t)N * k] = nh;
+        nuc[j + (size_t)N * k] = nc;
+        a += wq[j] * nh;
+        c += wq[j] * nc;
+        m = nanmax(m, nh);
     }
     sh[0][t] = a;
     sh[1][t] = c;
+    sh[2][t] = m;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (t < w) {
             sh[0][t] += sh[0][t + w];
             sh[1][t] += sh[1][t + w];
+            sh[2][t] = nanmax(sh[2][t], sh[2][t + w]);
         }
         __syncthreads();
     }
     if (t == 0) {
         avh[k] = sh[0][0];
         avc[k] = sh[1][0];
+        mxh[k] = sh[2][0];
     }
+}
+__global__ void __launch_bounds__(256) k_nu_rows(Geo g, const double *__restrict__ wq, const double *__restrict__ T,
+                                                 double *__restrict__ nuh, double *__restrict__ nuc,
+                                                 double *__restrict__ avh, double *__restrict__ avc,
+                                                 double *__restrict__ mxh)
+{
+    nu_row_block(g, wq, T, nuh, nuc, avh, avc, mxh, blockIdx.x);
 }
 
 // Means over z (Simpson), maxima over z of Nu_avg, and the max of the local
-// hot-wall Nu: one block of 256 threads, fixed-order trees.
-__global__ void __launch_bounds__(1024) k_nu_final(Geo g, const double *__restrict__ wq, const double *__restrict__ avh,
-                                                   const double *__restrict__ avc, const double *__restrict__ nuh,
-                                                   double *__restrict__ out)
+// hot-wall Nu (over the rows' maxima): one block of 1024 threads, fixed-order trees.
+__device__ __forceinline__ void nu_final_block(const Geo &g, const double *__restrict__ wq,
+                                               const double *__restrict__ avh, const double *__restrict__ avc,
+                                               const double *__restrict__ mxh, double *__restrict__ out)
 {
     __shared__ double sh[5][16];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -1671,8 +1689,8 @@ __global__ void __launch_bounds__(1024) k_nu_final(Geo g, const double *__restri
         v[1] += wq[k] * avc[k];
         v[2] = nanmax(v[2], avh[k]);
         v[3] = nanmax(v[3], avc[k]);
+        v[4] = nanmax(v[4], mxh[k]);
     }
-    for (size_t q = t; q < (size_t)g.N * g.N; q += 1024) v[4] = nanmax(v[4], nuh[q]);
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
         double x = v[c];
@@ -1688,6 +1706,12 @@ __global__ void __launch_bounds__(1024) k_nu_final(Geo g, const double *__restri
         for (int w = 1; w < 16; ++w) x = t < 2 ? x + sh[t][w] : nanmax(x, sh[t][w]);
         out[t] = x;
     }
+}
+__global__ void __launch_bounds__(1024) k_nu_final(Geo g, const double *__restrict__ wq, const double *__restrict__ avh,
+                                                   const double *__restrict__ avc, const double *__restrict__ mxh,
+                                                   double *__restrict__ out)
+{
+    nu_final_block(g, wq, avh, avc, mxh, out);
 }
 
 // Entropy generation (Sec. 4.3): E_HT = |grad theta|^2, E_FF = phi eta I2 with eta
@@ -1741,14 +1765,14 @@ __global__ void k_diag_pack(const double *__restrict__ nu, const double *__restr
     out[9] = nu[4];
 }
 
-__global__ void __launch_bounds__(256) k_entropy(Geo g, Phys P, const double *__restrict__ wq,
-                                                 const double *__restrict__ u, const double *__restrict__ v,
-                                                 const double *__restrict__ w, const double *__restrict__ T,
-                                                 double *__restrict__ el, double *__restrict__ bl,
-                                                 double *__restrict__ eta_out, double *__restrict__ partial,
-                                                 const double *__restrict__ eta_prev = nullptr, double relax = 1.0)
+// One 256-node block (tile tl) of the all-node launch.
+__device__ __forceinline__ void entropy_block(const Geo &g, const Phys &P, const Tile &tl, const double *__restrict__ wq,
+                                             const double *__restrict__ u, const double *__restrict__ v,
+                                             const double *__restrict__ w, const double *__restrict__ T,
+                                             double *__restrict__ el, double *__restrict__ bl,
+                                             double *__restrict__ eta_out, double *__restrict__ partial,
+                                             const double *__restrict__ eta_prev, double relax)
 {
-    const Tile tl = xcd_tile();
     int i, j, k;
     double acc[3] = {0.0, 0.0, 0.0};
     if (all_node(g, tl, i, j, k)) {
@@ -1772,6 +1796,82 @@ __global__ void __launch_bounds__(256) k_entropy(Geo g, Phys P, const double *__
     }
     const int blk = tl.id;
     block_sum_store<3>(acc, partial + (size_t)blk * 3);
+}
+__global__ void __launch_bounds__(256) k_entropy(Geo g, Phys P, const double *__restrict__ wq,
+                                                 const double *__restrict__ u, const double *__restrict__ v,
+                                                 const double *__restrict__ w, const double *__restrict__ T,
+                                                 double *__restrict__ el, double *__restrict__ bl,
+                                                 double *__restrict__ eta_out, double *__restrict__ partial,
+                                                 const double *__restrict__ eta_prev = nullptr, double relax = 1.0)
+{
+    entropy_block(g, P, xcd_tile(), wq, u, v, w, T, el, bl, eta_out, partial, eta_prev, relax);
+}
+
+// ---------------------------------------------------------------------------
+// The end of a step in three launches.  The blocks of one launch take different
+// roles, each block computing exactly what the same block of that role's own
+// launch computes (same tile, same thread layout, same partial record), so the
+// results are bitwise those of the separate launches; the roles of one launch do
+// not read what another role of it writes.
+// ---------------------------------------------------------------------------
+
+// Blocks [0, nd): divergence of the new velocity and, with apply, p <- p - lambda D
+// (the 64 x 4 interior tiles, grid dgx x dgy x (N-2)); blocks [nd, nd + nf): the
+// theta walls (the 64 x 4 face blocks, grid fgx x fgy x 6).
+__global__ void __launch_bounds__(256) k_tail_div_walls(Geo g, Phys P, const double *__restrict__ u,
+                                                        const double *__restrict__ v, const double *__restrict__ w,
+                                                        double *__restrict__ p, double *__restrict__ dstore, int apply,
+                                                        double *__restrict__ part_div, int dgx, int dgy, int nd,
+                                                        double *__restrict__ T, double *__restrict__ part_walls,
+                                                        int fgx, int fgy)
+{
+    const int b = blockIdx.x, t = threadIdx.x;
+    if (b < nd) {
+        divergence_tile(g, P, xcd_tile_of(b, nd, dgx, dgy), t & 63, t >> 6, u, v, w, p, dstore, apply, part_div);
+    } else {
+        const int q = b - nd, bx = q % fgx, by = (q / fgx) % fgy, f = q / (fgx * fgy);
+        theta_walls_block(g, P, T, part_walls, bx * 64 + (t & 63), by * 4 + (t >> 6), f, q);
+    }
+}
+
+// Blocks [0, ne): the entropy pass over every node (it also writes the next step's
+// viscosity); [ne, ne + nf): the pressure walls (when the correction was applied
+// in the previous launch; nf = 0 otherwise); then one block per z-row of the
+// Nusselt numbers.
+__global__ void __launch_bounds__(256) k_tail_diag(Geo g, Phys P, const double *__restrict__ wq,
+                                                   const double *__restrict__ u, const double *__restrict__ v,
+                                                   const double *__restrict__ w, const double *__restrict__ T,
+                                                   double *__restrict__ eta_out, double *__restrict__ part_ent,
+                                                   const double *__restrict__ eta_prev, double relax, int ne,
+                                                   double *__restrict__ p, int nf, int fgx, int fgy,
+                                                   double *__restrict__ nuh, double *__restrict__ nuc,
+                                                   double *__restrict__ avh, double *__restrict__ avc,
+                                                   double *__restrict__ mxh)
+{
+    const int b = blockIdx.x, t = threadIdx.x;
+    if (b < ne) {
+        entropy_block(g, P, xcd_tile_of(b, ne, ne, 1), wq, u, v, w, T, nullptr, nullptr, eta_out, part_ent, eta_prev,
+                      relax);
+    } else if (b < ne + nf) {
+        const int q = b - ne, bx = q % fgx, by = (q / fgx) % fgy, f = q / (fgx * fgy);
+        p_walls_node(g, p, bx * 64 + (t & 63), by * 4 + (t >> 6), f);
+    } else {
+        nu_row_block(g, wq, T, nuh, nuc, avh, avc, mxh, b - ne - nf);
+    }
+}
+
+// Blocks [0, n): the reductions of the step's partial sums; block n: the Nusselt
+// means and maxima.
+__global__ void __launch_bounds__(1024) k_tail_reduce(ReduceJobs4 jobs, int n, Geo g, const double *__restrict__ wq,
+                                                      const double *__restrict__ avh, const double *__restrict__ avc,
+                                                      const double *__restrict__ mxh, double *__restrict__ nu_out)
+{
+    if ((int)blockIdx.x < n) {
+        const ReduceJob &jb = jobs.j[blockIdx.x];
+        reduce_block(jb.part, jb.nb, jb.nc, jb.op, jb.out);
+    } else {
+        nu_final_block(g, wq, avh, avc, mxh, nu_out);
+    }
 }
 
 // STREAM-style copy (16-byte accesses, grid-stride): measures the achievable
