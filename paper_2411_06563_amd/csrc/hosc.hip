@@ -224,6 +224,10 @@ struct hosc_solver {
     float *fr[4] = {nullptr, nullptr, nullptr, nullptr}, *fe[4] = {nullptr, nullptr, nullptr, nullptr};
     double *dalt[4] = {nullptr, nullptr, nullptr, nullptr};   // second increment buffers of the refinement
     double *hbuf = nullptr;   // pinned host staging for scalars
+    // mapped, coherent pinned host mirror of the reduction block red[0..kRed): the
+    // reductions whose results the host reads write them here too (hmir_dev is its
+    // device address), so a convergence check needs no device-to-host copy
+    double *hmir = nullptr, *hmir_dev = nullptr;
     int64_t step = 0;
     bool first = true;
     bool has_state = false;
@@ -550,7 +554,7 @@ SweepArgs<float> sweep_args_fp32(hosc_solver *s)
 struct Reductions {
     ReduceJobs4 r{};
     int n = 0;
-    Reductions &add(const double *part, size_t nb, int nc, int op, double *out)
+    Reductions &add(const double *part, size_t nb, int nc, int op, double *out, double *out_host = nullptr)
     {
         ReduceJob &j = r.j[n++];
         j.part = part;
@@ -558,11 +562,15 @@ struct Reductions {
         j.nc = nc;
         j.op = op;
         j.out = out;
+        j.out_host = out_host;
         j.pad = 0;
         return *this;
     }
     void launch(hipStream_t st) const { k_reduce4<<<n, 1024, 0, st>>>(r); }
 };
+
+// Device address of the host mirror of red[i] for out = red + i.
+double *mir(const hosc_solver *s, const double *out) { return s->hmir_dev + (out - s->red); }
 
 // Algorithmic bytes of one BiCGSTAB phase launch over both colours.
 double bicg_bytes(const Geo &g, int phase, int mask)
@@ -827,11 +835,10 @@ hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *f
     sor_begin(s, c, mask, rtol, inner);
     *failed = 0;
     if (sor_wants_seed(s, c)) {
-        HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red, 48 * sizeof(double), hipMemcpyDeviceToHost, s->st));
         HIPCHK(s, wait_stream(s->st));
-        sor_seed(s, c, s->hbuf + 44);
+        sor_seed(s, c, s->hmir + 44);
         if (bn2[0] < 0.0) {
-            for (int f = 0; f < 4; ++f) bn2[f] = s->hbuf[f];
+            for (int f = 0; f < 4; ++f) bn2[f] = s->hmir[f];
             for (int f = 0; f < 4; ++f)
                 if (!std::isfinite(bn2[f])) return fail(s, HOSC_E_NONFINITE, "non-finite right-hand side");
         }
@@ -857,16 +864,15 @@ hosc_status run_sor(hosc_solver *s, int mask, double bn2[4], SolveOut &o, int *f
         r = launch_check(s, "sweep");
         if (r) return r;
         Reductions()
-            .add(s->partR, s->L.nb_sp, 4, 0, s->red + 4)
-            .add(s->partB, s->L.nb_sp, 4, 0, s->red + 8)
-            .add(s->partR0, s->L.nb_sp, 4, 0, s->red + 32)
-            .add(s->partB0, s->L.nb_sp, 4, 0, s->red + 36)
+            .add(s->partR, s->L.nb_sp, 4, 0, s->red + 4, mir(s, s->red + 4))
+            .add(s->partB, s->L.nb_sp, 4, 0, s->red + 8, mir(s, s->red + 8))
+            .add(s->partR0, s->L.nb_sp, 4, 0, s->red + 32, mir(s, s->red + 32))
+            .add(s->partB0, s->L.nb_sp, 4, 0, s->red + 36, mir(s, s->red + 36))
             .launch(s->st);
-        HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red, 48 * sizeof(double), hipMemcpyDeviceToHost, s->st));
         HIPCHK(s, wait_stream(s->st));
         r = harvest_events(s);
         if (r) return r;
-        r = sor_decide<TM>(s, c, s->hbuf, bn2, o, a);
+        r = sor_decide<TM>(s, c, s->hmir, bn2, o, a);
         if (r) return r;
     }
     *failed = c.failed;
@@ -911,9 +917,8 @@ hosc_status run_bicg(hosc_solver *s, int mask, double bn2[4], SolveOut &o, BicgA
 {
     if (!mask) return HOSC_OK;
     if (bn2[0] < 0.0) {
-        HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red, 4 * sizeof(double), hipMemcpyDeviceToHost, s->st));
         HIPCHK(s, wait_stream(s->st));
-        for (int f = 0; f < 4; ++f) bn2[f] = s->hbuf[f];
+        for (int f = 0; f < 4; ++f) bn2[f] = s->hmir[f];
         for (int f = 0; f < 4; ++f)
             if (!std::isfinite(bn2[f])) return fail(s, HOSC_E_NONFINITE, "non-finite right-hand side");
     }
@@ -1166,13 +1171,15 @@ hosc_status refine_loop(hosc_solver *s, RefCtl &c, double bn2[4], SolveOut &o)
         r = launch_check(s, "refinement pass");
         if (r) return r;
         refine_folded(c);
-        Reductions().add(s->partR, s->L.nb_sp, 4, 0, s->red + 48).add(s->partB, s->L.nb_sp, 4, 0, s->red + 52).launch(s->st);
-        HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red, 56 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+        Reductions()
+            .add(s->partR, s->L.nb_sp, 4, 0, s->red + 48, mir(s, s->red + 48))
+            .add(s->partB, s->L.nb_sp, 4, 0, s->red + 52, mir(s, s->red + 52))
+            .launch(s->st);
         HIPCHK(s, wait_stream(s->st));
         r = harvest_events(s);
         if (r) return r;
         double inner_bn2[4], inner_rtol;
-        r = refine_decide(s, c, s->hbuf, bn2, o, inner_bn2, &inner_rtol);
+        r = refine_decide(s, c, s->hmir, bn2, o, inner_bn2, &inner_rtol);
         if (r) return r;
         if (!c.active) break;
         int failed = 0;
@@ -1271,7 +1278,10 @@ hosc_status assemble(hosc_solver *s, bool rows32)
                                            s->fta[2]);
     r = timed_end(s, 1, assemble_bytes(s->g));
     if (r) return r;
-    Reductions().add(s->partR, s->L.nb_int, 4, 0, s->red).add(s->partB, s->L.nb_int, 2, 1, s->red + 44).launch(s->st);
+    Reductions()
+        .add(s->partR, s->L.nb_int, 4, 0, s->red, mir(s, s->red))
+        .add(s->partB, s->L.nb_int, 2, 1, s->red + 44, mir(s, s->red + 44))
+        .launch(s->st);
     return launch_check(s, "assemble");
 }
 
@@ -1295,12 +1305,11 @@ hosc_status pressure_iterations(hosc_solver *s, bool first, SolveOut &so)
     for (int it = 1; it < s->P.p_iters; ++it) {
         k_divergence_trial<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, s->u, s->v, s->w, s->md[0], s->md[1],
                                                                      s->md[2], s->dbg, s->partR0);
-        Reductions().add(s->partR0, s->L.nb_int, 1, 1, s->red + 62).launch(s->st);
+        Reductions().add(s->partR0, s->L.nb_int, 1, 1, s->red + 62, mir(s, s->red + 62)).launch(s->st);
         hosc_status r = launch_check(s, "trial divergence");
         if (r) return r;
-        HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red + 62, sizeof(double), hipMemcpyDeviceToHost, s->st));
         HIPCHK(s, wait_stream(s->st));
-        if (!(s->hbuf[0] > s->P.div_tol)) break;    // within tolerance (a non-finite value fails later)
+        if (!(s->hmir[62] > s->P.div_tol)) break;    // within tolerance (a non-finite value fails later)
         k_pressure_apply<<<s->L.grd_int, s->L.blk_int, 0, s->st>>>(s->g, s->ph, s->dbg, s->p);
         k_p_walls<<<s->L.grd_face, s->L.blk_face, 0, s->st>>>(s->g, s->p);
         so.corrections += 1;
@@ -1351,11 +1360,12 @@ hosc_status post_launch(hosc_solver *s)
                                                    (int)s->L.grd_face.x, (int)s->L.grd_face.y, s->nuh, s->nuc,
                                                    s->avh, s->avc, s->mxh);
     Reductions rd;
-    rd.add(s->partR, s->L.nb_int, 8, 0, s->red + 12)
-        .add(s->partB, s->L.nb_face, 2, 0, s->red + 20)
-        .add(s->partR0, s->L.nb_int, 1, 1, s->red + 22)
-        .add(s->partB0, s->L.nb_all, 3, 0, s->red + 24);
-    k_tail_reduce<<<rd.n + 1, 1024, 0, s->st>>>(rd.r, rd.n, g, s->wq, s->avh, s->avc, s->mxh, s->red + 56);
+    rd.add(s->partR, s->L.nb_int, 8, 0, s->red + 12, mir(s, s->red + 12))
+        .add(s->partB, s->L.nb_face, 2, 0, s->red + 20, mir(s, s->red + 20))
+        .add(s->partR0, s->L.nb_int, 1, 1, s->red + 22, mir(s, s->red + 22))
+        .add(s->partB0, s->L.nb_all, 3, 0, s->red + 24, mir(s, s->red + 24));
+    k_tail_reduce<<<rd.n + 1, 1024, 0, s->st>>>(rd.r, rd.n, g, s->wq, s->avh, s->avc, s->mxh, s->red + 56,
+                                                mir(s, s->red + 56));
     return launch_check(s, "update/divergence/diagnostics");
 }
 
@@ -1449,9 +1459,8 @@ hosc_status one_step(hosc_solver *s, hosc_step_info *info)
     if (r) return r;
     r = post_launch(s);
     if (r) return r;
-    HIPCHK(s, hipMemcpyAsync(s->hbuf, s->red + 12, kPost * sizeof(double), hipMemcpyDeviceToHost, s->st));
     HIPCHK(s, wait_stream(s->st));
-    return post_finish(s, s->hbuf, so, info);
+    return post_finish(s, s->hmir + 12, so, info);
 }
 
 // ---------------------------------------------------------------------------
@@ -1482,7 +1491,7 @@ struct Fused {
     std::vector<GraphEntry> graphs;
     bool use_graphs = false;
     int64_t graph_launches = 0;
-    double *d_gather = nullptr, *h_gather = nullptr;
+    double *h_gather = nullptr, *h_gather_dev = nullptr;   // mapped host memory the gathers write to
     std::string err;
     bool prof = false;
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -1508,7 +1517,7 @@ size_t fused_table_bytes(int cap)
     return align_up((size_t)cap * sizeof(TileMap)) + align_up((size_t)cap * kCavEntry)
            + align_up((size_t)cap * 4 * sizeof(ReduceJob)) + 2 * align_up((size_t)cap * sizeof(double *));
 }
-size_t fused_device_bytes(int cap) { return fused_table_bytes(cap) + align_up((size_t)cap * 64 * sizeof(double)); }
+size_t fused_device_bytes(int cap) { return fused_table_bytes(cap); }
 
 hosc_status ffail(Fused &F, hosc_status st, const std::string &msg)
 {
@@ -1537,9 +1546,10 @@ hosc_status fused_init(Fused &F, int cap, char *d_dev, hipStream_t st)
     F.tab_bytes = fused_table_bytes(cap);
     F.use_graphs = st != nullptr;
     F.d_tab = d_dev;
-    F.d_gather = reinterpret_cast<double *>(d_dev + F.tab_bytes);
     FHIPCHK(F, hipHostMalloc(reinterpret_cast<void **>(&F.h_tab), F.tab_bytes));
-    FHIPCHK(F, hipHostMalloc(reinterpret_cast<void **>(&F.h_gather), (size_t)cap * 64 * sizeof(double)));
+    FHIPCHK(F, hipHostMalloc(reinterpret_cast<void **>(&F.h_gather), (size_t)cap * 64 * sizeof(double),
+                             hipHostMallocMapped | hipHostMallocCoherent));
+    FHIPCHK(F, hipHostGetDevicePointer(reinterpret_cast<void **>(&F.h_gather_dev), F.h_gather, 0));
     std::memset(F.h_tab, 0, F.tab_bytes);
     FHIPCHK(F, hipEventCreate(&F.ev[0]));
     FHIPCHK(F, hipEventCreate(&F.ev[1]));
@@ -1570,6 +1580,7 @@ void fused_free(Fused &F)
     F.fork = nullptr;
     F.h_tab = nullptr;
     F.h_gather = nullptr;
+    F.h_gather_dev = nullptr;
 }
 
 void tile_map_of(TileMap &m, dim3 grd, dim3 blk, int &total)
@@ -1588,13 +1599,12 @@ void tile_map_sweep(TileMap &m, const hosc_solver *s, int &total) { tile_map_of(
 int fused_grid(const Fused &F, int total) { return F.grid > 0 ? std::min(F.grid, total) : total; }
 
 // Upload the table block and run the reductions in h_jobs[0..njobs), then gather
-// len doubles from each of h_src[0..nsrc) into h_gather (one host copy, synchronised).
+// len doubles from each of h_src[0..nsrc) into the mapped h_gather, synchronised.
 hosc_status fused_reduce_gather(Fused &F, int njobs, int nsrc, int len)
 {
     if (njobs > 0) k_reduce_jobs<<<njobs, 1024, 0, F.st>>>(F.djobs());
-    k_gather<<<nsrc, 64, 0, F.st>>>(F.dsrc(), len, F.d_gather);
+    k_gather<<<nsrc, 64, 0, F.st>>>(F.dsrc(), len, F.h_gather_dev);
     FHIPCHK(F, hipGetLastError());
-    FHIPCHK(F, hipMemcpyAsync(F.h_gather, F.d_gather, (size_t)nsrc * len * sizeof(double), hipMemcpyDeviceToHost, F.st));
     FHIPCHK(F, wait_stream(F.st));
     return HOSC_OK;
 }
@@ -1607,6 +1617,8 @@ void add_job(ReduceJob *jobs, int &n, const double *part, int nb, int nc, int op
     j.nc = nc;
     j.op = op;
     j.out = out;
+    j.out_host = nullptr;
+    j.pad = 0;
 }
 
 template <typename TM> SweepArgs<TM> cavity_sweep_args(hosc_solver *s);
@@ -2002,12 +2014,10 @@ hosc_status fused_step(Fused &F, hosc_solver *const *cav, int n, hosc_step_info 
             });
             if (fr) return fr;
             if (first_err) return ffail(F, first_err, msg);
-            k_gather<<<n, 64, 0, F.st>>>(F.dsrc2(), kPost, F.d_gather);
+            k_gather<<<n, 64, 0, F.st>>>(F.dsrc2(), kPost, F.h_gather_dev);
             return HOSC_OK;
         });
         if (r) return r;
-        FHIPCHK(F, hipMemcpyAsync(F.h_gather, F.d_gather, (size_t)n * kPost * sizeof(double), hipMemcpyDeviceToHost,
-                                  F.st));
         FHIPCHK(F, wait_stream(F.st));
     } else if (nact) {
         std::vector<int> post(n, 0);
@@ -2308,11 +2318,21 @@ hosc_status hosc_create(const hosc_params *p, void *d_ws, size_t ws_bytes, hipSt
         delete s;
         return fail(nullptr, HOSC_E_DEVICE, "hipHostMalloc of the staging buffer failed");
     }
+    if (hipHostMalloc(reinterpret_cast<void **>(&s->hmir), kRed * sizeof(double),
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess
+        || hipHostGetDevicePointer(reinterpret_cast<void **>(&s->hmir_dev), s->hmir, 0) != hipSuccess) {
+        if (s->hmir) (void)hipHostFree(s->hmir);
+        (void)hipHostFree(s->hbuf);
+        delete s;
+        return fail(nullptr, HOSC_E_DEVICE, "hipHostMalloc of the mapped reduction mirror failed");
+    }
+    std::memset(s->hmir, 0, kRed * sizeof(double));
     carve(s, static_cast<char *>(d_ws));
     std::vector<double> wq = simpson(p->N);
     hipError_t he = hipMemcpy(s->wq, wq.data(), wq.size() * sizeof(double), hipMemcpyHostToDevice);
     if (he != hipSuccess) {
         (void)hipHostFree(s->hbuf);
+        (void)hipHostFree(s->hmir);
         delete s;
         return fail(nullptr, HOSC_E_DEVICE, std::string("copy of quadrature weights: ") + hipGetErrorString(he));
     }
@@ -2326,6 +2346,7 @@ hosc_status hosc_destroy(hosc_solver *s)
     (void)hipStreamSynchronize(s->st);
     for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
     if (s->hbuf) (void)hipHostFree(s->hbuf);
+    if (s->hmir) (void)hipHostFree(s->hmir);
     delete s;
     return HOSC_OK;
 }
@@ -2576,7 +2597,10 @@ hosc_status hosc_transport_step(hosc_solver *s, const double *L, const double *G
         k_rows_f32<<<2048, 256, 0, s->st>>>(2 * s->g.cs, s->ms, s->ma[0], s->ma[1], s->ma[2], s->ta[0], s->ta[1],
                                            s->ta[2], s->fms, s->fma[0], s->fma[1], s->fma[2], s->fta[0], s->fta[1],
                                            s->fta[2]);
-    Reductions().add(s->partR, s->L.nb_int, 4, 0, s->red).add(s->partB, s->L.nb_int, 2, 1, s->red + 44).launch(s->st);
+    Reductions()
+        .add(s->partR, s->L.nb_int, 4, 0, s->red, mir(s, s->red))
+        .add(s->partB, s->L.nb_int, 2, 1, s->red + 44, mir(s, s->red + 44))
+        .launch(s->st);
     r = launch_check(s, "transport assembly");
     if (r) return r;
     SolveOut so;

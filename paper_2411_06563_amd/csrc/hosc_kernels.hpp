@@ -147,7 +147,18 @@ __device__ __forceinline__ void fold_records(const double *part, int nb, int op,
     }
 }
 
-__device__ __forceinline__ void reduce_block(const double *part, int nb, int nc, int op, double *out)
+// A value written to pinned host memory (mapped, coherent) as well: a system-scope
+// store and fence, so the host reads it once the stream has completed, without a
+// device-to-host copy.
+__device__ __forceinline__ void store_host(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __threadfence_system();
+}
+
+// out_host (may be null): the same outputs to mapped host memory.
+__device__ __forceinline__ void reduce_block(const double *part, int nb, int nc, int op, double *out,
+                                             double *out_host = nullptr)
 {
     __shared__ double sh[8][16];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -177,6 +188,7 @@ __device__ __forceinline__ void reduce_block(const double *part, int nb, int nc,
         double s = sh[t][0];
         for (int w = 1; w < 16; ++w) s = op == 0 ? s + sh[t][w] : nanmax(s, sh[t][w]);
         out[t] = s;
+        if (out_host) store_host(out_host + t, s);
     }
 }
 
@@ -190,12 +202,13 @@ __global__ void __launch_bounds__(1024) k_reduce(const double *part, int nb, int
 struct ReduceJob {
     const double *part;
     double *out;
+    double *out_host;       // null, or mapped host memory receiving the outputs too
     int nb, nc, op, pad;
 };
 __global__ void __launch_bounds__(1024) k_reduce_jobs(const ReduceJob *__restrict__ jobs)
 {
     const ReduceJob jb = jobs[blockIdx.x];
-    reduce_block(jb.part, jb.nb, jb.nc, jb.op, jb.out);
+    reduce_block(jb.part, jb.nb, jb.nc, jb.op, jb.out, jb.out_host);
 }
 
 // Up to four reductions passed by value (no table upload), one block each.
@@ -205,15 +218,16 @@ struct ReduceJobs4 {
 __global__ void __launch_bounds__(1024) k_reduce4(ReduceJobs4 jobs)
 {
     const ReduceJob &jb = jobs.j[blockIdx.x];
-    reduce_block(jb.part, jb.nb, jb.nc, jb.op, jb.out);
+    reduce_block(jb.part, jb.nb, jb.nc, jb.op, jb.out, jb.out_host);
 }
 
 // Gather len doubles from each of gridDim.x device blocks into one contiguous array
 // (one host copy then reads every cavity's reduction outputs).
+// (dst: mapped host memory; the host reads it once the stream has completed.)
 __global__ void __launch_bounds__(64) k_gather(const double *const *__restrict__ src, int len, double *__restrict__ dst)
 {
     const double *s = src[blockIdx.x];
-    for (int t = threadIdx.x; t < len; t += blockDim.x) dst[(size_t)blockIdx.x * len + t] = s[t];
+    for (int t = threadIdx.x; t < len; t += blockDim.x) store_host(dst + (size_t)blockIdx.x * len + t, s[t]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1679,7 +1693,8 @@ __global__ void __launch_bounds__(256) k_nu_rows(Geo g, const double *__restrict
 // hot-wall Nu (over the rows' maxima): one block of 1024 threads, fixed-order trees.
 __device__ __forceinline__ void nu_final_block(const Geo &g, const double *__restrict__ wq,
                                                const double *__restrict__ avh, const double *__restrict__ avc,
-                                               const double *__restrict__ mxh, double *__restrict__ out)
+                                               const double *__restrict__ mxh, double *__restrict__ out,
+                                               double *__restrict__ out_host = nullptr)
 {
     __shared__ double sh[5][16];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -1705,6 +1720,7 @@ __device__ __forceinline__ void nu_final_block(const Geo &g, const double *__res
         double x = sh[t][0];
         for (int w = 1; w < 16; ++w) x = t < 2 ? x + sh[t][w] : nanmax(x, sh[t][w]);
         out[t] = x;
+        if (out_host) store_host(out_host + t, x);
     }
 }
 __global__ void __launch_bounds__(1024) k_nu_final(Geo g, const double *__restrict__ wq, const double *__restrict__ avh,
@@ -1862,15 +1878,17 @@ __global__ void __launch_bounds__(256) k_tail_diag(Geo g, Phys P, const double *
 
 // Blocks [0, n): the reductions of the step's partial sums; block n: the Nusselt
 // means and maxima.
+// nu_host (may be null): the Nusselt outputs to mapped host memory as well.
 __global__ void __launch_bounds__(1024) k_tail_reduce(ReduceJobs4 jobs, int n, Geo g, const double *__restrict__ wq,
                                                       const double *__restrict__ avh, const double *__restrict__ avc,
-                                                      const double *__restrict__ mxh, double *__restrict__ nu_out)
+                                                      const double *__restrict__ mxh, double *__restrict__ nu_out,
+                                                      double *__restrict__ nu_host)
 {
     if ((int)blockIdx.x < n) {
         const ReduceJob &jb = jobs.j[blockIdx.x];
-        reduce_block(jb.part, jb.nb, jb.nc, jb.op, jb.out);
+        reduce_block(jb.part, jb.nb, jb.nc, jb.op, jb.out, jb.out_host);
     } else {
-        nu_final_block(g, wq, avh, avc, mxh, nu_out);
+        nu_final_block(g, wq, avh, avc, mxh, nu_out, nu_host);
     }
 }
 
