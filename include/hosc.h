@@ -167,7 +167,10 @@ hosc_status hosc_workspace_bytes(const hosc_params *p, size_t *bytes);
 
 /* Create a solver on the current HIP device.  d_ws: device buffer of ws_bytes >=
  * hosc_workspace_bytes(p), 256-byte aligned; stream: where all work is ordered
- * (0 = null stream).  The state is unset until hosc_init_fields / hosc_set_state. */
+ * (0 = null stream).  The state is unset until hosc_init_fields / hosc_set_state.
+ * Allocates only pinned host memory: a staging buffer and a mapped, coherent copy
+ * of the reduction results, which the kernels write and the convergence checks read
+ * (HOSC_E_DEVICE if that allocation fails). */
 hosc_status hosc_create(const hosc_params *p, void *d_ws, size_t ws_bytes, hipStream_t stream, hosc_solver **out);
 
 /* Release the handle (not the workspace).  Accepts NULL. */
