@@ -380,19 +380,25 @@ def bench_serve(args, W, hosc, torch):
     import numpy as np
     from paper_2411_06563_amd.inputs import serving_trace
     nreq = args.requests if args.requests is not None else W["requests"]
+    max_steps = args.max_steps if args.max_steps is not None else W["max_steps"]
     trace = serving_trace(500, W["rate"], W["trace_seed"])[:nreq]
+    # --to-steady: every request marched to res_tol (the step cap only as a guard),
+    # with the viscosity relaxation of the time-to-steady leg
+    relax = (lambda n: steady_relax(n)) if args.to_steady else (lambda n: 1.0)
     plist = [hosc.params(r["N"], Ra=r["Ra"], n_pl=r["n_pl"], Pr=r["Pr"], dt=W["dt_over_h2"] / (r["N"] - 1) ** 2,
-                         solve_rtol=W["solve_rtol"], precision=W["precision"]) for r in trace]
+                         solve_rtol=W["solve_rtol"], precision=W["precision"], eta_relax=relax(r["n_pl"]))
+             for r in trace]
     srv = hosc.Server(W["budget"], max_resident=W["max_resident"])
     t0 = srv.now()
     ids, results = {}, {}
     nxt = 0
     max_queued = 0
+    next_report = 5000
     while len(results) < nreq:
         now = srv.now() - t0
         while nxt < nreq and trace[nxt]["arrival"] <= now:
             r = trace[nxt]
-            ids[srv.submit(plist[nxt], r["seed"], W["noise"], W["res_tol"], W["max_steps"], t0 + r["arrival"])] = nxt
+            ids[srv.submit(plist[nxt], r["seed"], W["noise"], W["res_tol"], max_steps, t0 + r["arrival"])] = nxt
             nxt += 1
         st = srv.stats()
         max_queued = max(max_queued, st["queued"])
@@ -402,8 +408,12 @@ def bench_serve(args, W, hosc, torch):
             time.sleep(min(0.005, max(0.0, trace[nxt]["arrival"] - (srv.now() - t0))))
         for r in srv.poll():
             results[ids[r["id"]]] = r
-            if len(results) % 20 == 0:
+            if len(results) % 20 == 0 or args.to_steady:
                 print(f"serve: {len(results)}/{nreq} done", file=sys.stderr, flush=True)
+        if args.to_steady and st["server_steps"] >= next_report:
+            next_report += 5000
+            print(f"serve: server step {st['server_steps']}, {st['resident']} resident, {len(results)} done",
+                  file=sys.stderr, flush=True)
     st = srv.stats()
     srv.close()
     ok = [i for i in range(nreq) if results[i]["status"] == 0]
@@ -439,7 +449,10 @@ def bench_serve(args, W, hosc, torch):
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{W['label']}; first {nreq} requests of the 500-request trace"},
+        "config": {"workload": W["label"].replace("or 200 steps", f"or {max_steps} steps")
+                   + f"; first {nreq} requests of the 500-request trace",
+                   "max_steps": max_steps,
+                   "viscosity_relaxation": "0.1 for n < 1, 0.5 for n > 1" if args.to_steady else "none"},
         "latency_s": {"over": "requests that reached the steady residual",
                       "p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                       "mean": float(lat.mean())},
@@ -700,6 +713,11 @@ def main():
     ap.add_argument("--batch-steady", type=int, default=24,
                     help="default workload: small trace requests of the batched time-to-steady leg (0 = skip the "
                          "batch object)")
+    ap.add_argument("--max-steps", type=int, default=None,
+                    help="serve: step cap of each replayed request (default: the workload's 200)")
+    ap.add_argument("--to-steady", action="store_true",
+                    help="serve: march every replayed request to res 1e-8 with the viscosity relaxation "
+                         "(use with a large --max-steps)")
     ap.add_argument("--stream-grid", type=int, default=257,
                     help="default workload: grid of the HBM-streaming half-sweep measurement (0 = skip)")
     args = ap.parse_args()
