@@ -381,7 +381,12 @@ def bench_serve(args, W, hosc, torch):
     from paper_2411_06563_amd.inputs import serving_trace
     nreq = args.requests if args.requests is not None else W["requests"]
     max_steps = args.max_steps if args.max_steps is not None else W["max_steps"]
-    trace = serving_trace(500, W["rate"], W["trace_seed"])[:nreq]
+    first = args.first
+    trace = [dict(r) for r in serving_trace(500, W["rate"], W["trace_seed"])[first:first + nreq]]
+    nreq = len(trace)
+    t_first = trace[0]["arrival"]
+    for r in trace:     # a later segment of the trace starts its clock at its own first arrival
+        r["arrival"] -= t_first
     # --to-steady: every request marched to res_tol (the step cap only as a guard),
     # with the viscosity relaxation of the time-to-steady leg
     relax = (lambda n: steady_relax(n)) if args.to_steady else (lambda n: 1.0)
@@ -425,7 +430,8 @@ def bench_serve(args, W, hosc, torch):
     span = max(results[i]["t_done"] for i in range(nreq)) - (t0 + trace[0]["arrival"])
     # mix vs alone on sampled successful requests
     pool = steady if steady else ok
-    sample = pool[:: max(1, len(pool) // W["sample"])][: W["sample"]]
+    nsample = args.sample if args.sample is not None else W["sample"]
+    sample = pool[:: max(1, len(pool) // nsample)][:nsample] if nsample > 0 else []
     same = 0
     for i in sample:
         s = hosc.Solver(plist[i])
@@ -450,9 +456,10 @@ def bench_serve(args, W, hosc, torch):
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": W["label"].replace("or 200 steps", f"or {max_steps} steps")
-                   + f"; first {nreq} requests of the 500-request trace",
+                   + f"; requests {first}..{first + nreq - 1} of the 500-request trace",
                    "max_steps": max_steps,
                    "viscosity_relaxation": "0.1 for n < 1, 0.5 for n > 1" if args.to_steady else "none"},
+        "steady_latencies_s": [round(float(x), 3) for x in lat] if args.to_steady else None,
         "latency_s": {"over": "requests that reached the steady residual",
                       "p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                       "mean": float(lat.mean())},
@@ -715,6 +722,10 @@ def main():
                          "batch object)")
     ap.add_argument("--max-steps", type=int, default=None,
                     help="serve: step cap of each replayed request (default: the workload's 200)")
+    ap.add_argument("--first", type=int, default=0,
+                    help="serve: first request of the replayed segment of the trace (its clock starts there)")
+    ap.add_argument("--sample", type=int, default=None,
+                    help="serve: served requests rerun alone for the mix-vs-alone check (default 20)")
     ap.add_argument("--to-steady", action="store_true",
                     help="serve: march every replayed request to res 1e-8 with the viscosity relaxation "
                          "(use with a large --max-steps)")
