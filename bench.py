@@ -40,7 +40,9 @@ Prints one JSON line: cell-updates/s (interior nodes x steps / second), the
 roofline of the dominant kernel (the red-black sweep, HIP events around every
 launch, algorithmic bytes per launch), with the whole step's algorithmic bytes
 against the HBM peak (`roofline.step`) and the half-sweep on a 257^3 grid whose
-working set streams from HBM (`roofline.hbm_streaming`), and the FP64 CPU oracle
+working set streams from HBM (`roofline.hbm_streaming`), each beside the library's
+streaming probe with the half-sweep's access mix on arrays of that grid's size
+(`mix_probe_GBs`, `frac_of_mix_probe`), and the FP64 CPU oracle
 timed on the host cores on a bounded sample of the same workload.  The default
 run also carries the metric's second half: `serving` (24 small requests of the
 seeded trace marched to res 1e-8 through the server, FP32 refined, against the
@@ -218,9 +220,18 @@ def stream_sweep(hosc, torch, W, N):
     torch.cuda.empty_cache()
     n = max(c["sweep_launches"], 1)
     gbs = c["sweep_bytes"] / (c["sweep_ms"] * 1e-3) / 1e9
+    mix = mix_probe(hosc, N)
     return {"grid": N, "kernel": "k_sweep", "half_sweeps": c["sweep_launches"],
             "bytes_per_launch": c["sweep_bytes"] / n, "avg_launch_us": c["sweep_ms"] / n * 1e3,
-            "achieved": gbs, "frac": gbs / HBM_PEAK_GBS}
+            "achieved": gbs, "frac": gbs / HBM_PEAK_GBS, "mix_probe_GBs": mix, "frac_of_mix_probe": gbs / mix}
+
+
+def mix_probe(hosc, N):
+    """GB/s of the library's streaming probe with the half-sweep's access mix (15
+    read-only arrays, 4 rewritten in place) on arrays of one colour half of the
+    N^3 grid's interior: what a plain streaming kernel achieves with the sweep's
+    reads, writes and working set."""
+    return hosc.stream_mix_bandwidth(8 * ((N - 2) ** 3 // 2), 20)
 
 
 def bench_sizes(args, W, hosc, torch):
@@ -867,6 +878,10 @@ def main():
     step_gbs = step_bytes / (el / args.steps) / 1e9
     out["roofline"]["step"] = {"bytes_per_step": step_bytes, "achieved": step_gbs, "frac": step_gbs / HBM_PEAK_GBS}
     out["roofline"]["copy_probe_GBs"] = hosc.copy_bandwidth(1 << 30, 10)
+    if args.workload == "fp64":
+        mix = mix_probe(hosc, W["N"])
+        out["roofline"]["mix_probe_GBs"] = mix
+        out["roofline"]["frac_of_mix_probe"] = out["roofline"]["achieved"] / mix
     if args.workload == "fp64" and args.stream_grid > 0:
         out["roofline"]["hbm_streaming"] = stream_sweep(hosc, torch, W, args.stream_grid)
     if args.workload == "fp64" and args.serving > 0:

@@ -296,6 +296,21 @@ hosc_status hosc_perf_get(hosc_solver *s, hosc_perf *out);
 hosc_status hosc_copy_bandwidth(const void *d_src, void *d_dst, size_t bytes, int32_t reps, hipStream_t stream,
                                 double *ms_per_copy);
 
+/* Streaming probe with the access mix of a red-black half-sweep (measurement aid,
+ * not part of the method).  A half-sweep reads 19 and writes 4 elements per
+ * updated node (rows, right-hand sides, own and neighbouring increments; the own
+ * increments rewritten in place); the probe streams 15 read-only arrays, carved
+ * one after another from d_read (15 * bytes), and 4 arrays that it reads and
+ * rewrites in place, from d_inplace (4 * bytes): `bytes` per array, a multiple of
+ * 16, both buffers 16-byte aligned and not overlapping; one 16-byte element of
+ * every array per thread.  One warm-up launch, then `reps` launches on `stream`;
+ * returns the mean kernel time per launch (HIP events).  A launch moves
+ * 23 * bytes through HBM; d_inplace's contents change (each element becomes half
+ * itself plus the sum of the read elements), d_read is only read.  HOSC_E_ARG for
+ * null or misaligned buffers, overlap, bytes = 0 or reps < 1. */
+hosc_status hosc_stream_mix_bandwidth(const void *d_read, void *d_inplace, size_t bytes, int32_t reps,
+                                      hipStream_t stream, double *ms_per_launch);
+
 /* Message of the last failing call on the handle ("" if none; NULL handle: last
  * failing create). */
 const char *hosc_last_error(const hosc_solver *s);

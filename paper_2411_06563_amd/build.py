@@ -8,7 +8,8 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SRC = [os.path.join(PKG, "csrc", "hosc.hip")]
-DEPS = SRC + [os.path.join(PKG, "csrc", "hosc_kernels.hpp"), os.path.join(ROOT, "include", "hosc.h")]
+DEPS = SRC + [os.path.join(PKG, "csrc", "hosc_kernels.hpp"),
+                os.path.join(PKG, "csrc", "hosc_probes.hpp"), os.path.join(ROOT, "include", "hosc.h")]
 LIB = os.path.join(PKG, "libhosc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -24,6 +24,7 @@
 
 #include "hosc.h"
 #include "hosc_kernels.hpp"
+#include "hosc_probes.hpp"
 
 using namespace hosc;
 
@@ -2682,6 +2683,40 @@ hosc_status hosc_copy_bandwidth(const void *d_src, void *d_dst, size_t bytes, in
     (void)hipEventDestroy(e1);
     if (e != hipSuccess) return fail(nullptr, HOSC_E_DEVICE, std::string("copy probe: ") + hipGetErrorString(e));
     *ms_per_copy = ms / reps;
+    return HOSC_OK;
+}
+
+hosc_status hosc_stream_mix_bandwidth(const void *d_read, void *d_inplace, size_t bytes, int32_t reps,
+                                      hipStream_t stream, double *ms_per_launch)
+{
+    if (!d_read || !d_inplace || !ms_per_launch || reps < 1 || bytes == 0)
+        return fail(nullptr, HOSC_E_ARG, "invalid stream-mix probe arguments");
+    if (bytes % 16 || reinterpret_cast<uintptr_t>(d_read) % 16 || reinterpret_cast<uintptr_t>(d_inplace) % 16)
+        return fail(nullptr, HOSC_E_ARG, "stream-mix probe buffers and size must be 16-byte aligned");
+    const size_t n = bytes / 16;
+    if ((n + 255) / 256 > 0x7fffffffu) return fail(nullptr, HOSC_E_ARG, "stream-mix probe arrays too long");
+    const uintptr_t rd = reinterpret_cast<uintptr_t>(d_read);
+    const uintptr_t up = reinterpret_cast<uintptr_t>(d_inplace);
+    if (rd < up + (size_t)kMixInPlace * bytes && up < rd + (size_t)kMixRead * bytes)
+        return fail(nullptr, HOSC_E_ARG, "stream-mix probe buffers overlap");
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(nullptr, HOSC_E_DEVICE, "hipEventCreate failed");
+    const unsigned blocks = (unsigned)((n + 255) / 256);    // one element of every array per thread
+    const double2 *src = static_cast<const double2 *>(d_read);
+    double2 *dst = static_cast<double2 *>(d_inplace);
+    k_stream_mix<<<blocks, 256, 0, stream>>>(src, dst, n);    // warm-up
+    hipError_t e = hipEventRecord(e0, stream);
+    for (int q = 0; q < reps && e == hipSuccess; ++q) k_stream_mix<<<blocks, 256, 0, stream>>>(src, dst, n);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventRecord(e1, stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(nullptr, HOSC_E_DEVICE, std::string("stream-mix probe: ") + hipGetErrorString(e));
+    *ms_per_launch = ms / reps;
     return HOSC_OK;
 }
 

@@ -123,6 +123,8 @@ def lib() -> ctypes.CDLL:
     L.hosc_perf_enable.argtypes = [vp, ctypes.c_int32]
     L.hosc_perf_get.argtypes = [vp, ctypes.POINTER(CPerf)]
     L.hosc_copy_bandwidth.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_double)]
+    L.hosc_stream_mix_bandwidth.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int32, vp,
+                                            ctypes.POINTER(ctypes.c_double)]
     L.hosc_last_error.argtypes = [vp]
     L.hosc_last_error.restype = ctypes.c_char_p
     L.hosc_batch_workspace_bytes.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
@@ -220,6 +222,24 @@ def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 10, device: str = "cuda:0"
         torch.cuda.synchronize()
     return 2.0 * nbytes / (ms.value * 1e-3) / 1e9
 
+
+
+def stream_mix_bandwidth(nbytes: int, reps: int = 10, device: str = "cuda:0") -> float:
+    """Bandwidth (GB/s, 23 * nbytes per launch) of a streaming kernel with a
+    red-black half-sweep's mix: 15 read-only arrays and 4 rewritten in place, nbytes
+    each (rounded down to a multiple of 16)."""
+    import torch
+    nbytes -= nbytes % 16
+    with torch.cuda.device(torch.device(device)):
+        rd = torch.ones(15 * nbytes // 8, dtype=torch.float64, device=device)
+        up = torch.ones(4 * nbytes // 8, dtype=torch.float64, device=device)
+        ms = ctypes.c_double(0.0)
+        st = torch.cuda.current_stream().cuda_stream
+        _check(lib().hosc_stream_mix_bandwidth(ctypes.c_void_p(rd.data_ptr()), ctypes.c_void_p(up.data_ptr()), nbytes,
+                                               reps, ctypes.c_void_p(st), ctypes.byref(ms)))
+        torch.cuda.synchronize()
+        del rd, up
+    return 23.0 * nbytes / (ms.value * 1e-3) / 1e9
 
 @dataclass
 class StepInfo:

@@ -110,3 +110,17 @@ def test_server_workspace_sizing_and_create_validation():
     assert L.hosc_server_create(ctypes.c_void_p(256 * 1024 + 8), 1 << 30, 1 << 20, 4, None, ctypes.byref(h)) == -1
     assert L.hosc_server_create(ctypes.c_void_p(256 * 1024), 1000, 1 << 20, 4, None, ctypes.byref(h)) == -2
     assert not h.value
+
+
+def test_stream_mix_probe_rejects_bad_arguments():
+    """The measurement probe validates its buffers on the host before any HIP call."""
+    L = hosc.lib()
+    ms = ctypes.c_double(0.0)
+    cases = [(None, 4096, 160, 1), (4096, None, 160, 1), (4096, 1 << 20, 0, 1), (4096, 1 << 20, 160, 0),
+             (4104, 1 << 20, 160, 1), (4096, (1 << 20) + 8, 160, 1), (4096, 1 << 20, 168, 1),
+             (4096, 4096 + 14 * 160, 160, 1),    # in-place arrays start inside the read arrays
+             (1 << 20, (1 << 20) - 4 * 160 + 16, 160, 1)]    # read arrays start inside the in-place arrays
+    for rd, up, nbytes, reps in cases:
+        st = L.hosc_stream_mix_bandwidth(ctypes.c_void_p(rd) if rd else None, ctypes.c_void_p(up) if up else None,
+                                         nbytes, reps, None, ctypes.byref(ms))
+        assert L.hosc_status_string(st).decode() == "HOSC_E_ARG", (rd, up, nbytes, reps)
