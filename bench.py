@@ -238,7 +238,8 @@ def bench_sizes(args, W, hosc, torch):
     """Half-sweep bandwidth (algorithmic bytes / HIP-event launch time) for grids
     from 129^3, whose per-launch working set (about 150 MB) partly stays in the
     256 MB Infinity Cache between launches, to 385^3 (4.7 GB per launch), which
-    streams from HBM; plus the library's copy probe."""
+    streams from HBM; each beside the library's streaming probe with the
+    half-sweep's access mix on arrays of that grid's size, plus the copy probe."""
     rows = []
     t0 = time.perf_counter()
     for N in W["grids"]:
@@ -255,10 +256,14 @@ def bench_sizes(args, W, hosc, torch):
         rows.append({"grid": N, "half_sweeps": c["sweep_launches"], "mb_per_launch": c["sweep_bytes"] / n / 1e6,
                      "us_per_launch": c["sweep_ms"] / n * 1e3,
                      "gb_per_s": c["sweep_bytes"] / (c["sweep_ms"] * 1e-3) / 1e9})
-        print(f"[sizes] {rows[-1]}", file=sys.stderr, flush=True)
         s.close()
         del s
         torch.cuda.empty_cache()
+        mix = mix_probe(hosc, N)
+        torch.cuda.empty_cache()
+        rows[-1]["mix_probe_gb_per_s"] = mix
+        rows[-1]["frac_of_mix_probe"] = rows[-1]["gb_per_s"] / mix
+        print(f"[sizes] {rows[-1]}", file=sys.stderr, flush=True)
     el = time.perf_counter() - t0
     copy = hosc.copy_bandwidth()
     big = rows[-1]
