@@ -2239,6 +2239,31 @@ size_t batch_layout(const hosc_params *p, int count, std::vector<size_t> *offset
     return off + fused_device_bytes(count);
 }
 
+// Mean kernel time of `reps` launches of `launch` on `stream`, after one untimed
+// warm-up launch (HIP events; both events are released on every path).
+template <typename F>
+hipError_t time_launches(hipStream_t stream, int reps, F launch, double *ms_per_launch)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) {
+        launch();
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(e0, stream);
+    for (int q = 0; q < reps && e == hipSuccess; ++q) launch();
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventRecord(e1, stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e == hipSuccess) *ms_per_launch = ms / reps;
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2665,24 +2690,12 @@ hosc_status hosc_copy_bandwidth(const void *d_src, void *d_dst, size_t bytes, in
     if (bytes % 16 || reinterpret_cast<uintptr_t>(d_src) % 16 || reinterpret_cast<uintptr_t>(d_dst) % 16)
         return fail(nullptr, HOSC_E_ARG, "copy buffers and size must be 16-byte aligned");
     const size_t n = bytes / 16;
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-        return fail(nullptr, HOSC_E_DEVICE, "hipEventCreate failed");
     const int blocks = 256 * 8;    // 8 workgroups of 256 threads per compute unit
     const double2 *src = static_cast<const double2 *>(d_src);
     double2 *dst = static_cast<double2 *>(d_dst);
-    k_copy<<<blocks, 256, 0, stream>>>(src, dst, n);    // warm-up
-    hipError_t e = hipEventRecord(e0, stream);
-    for (int q = 0; q < reps && e == hipSuccess; ++q) k_copy<<<blocks, 256, 0, stream>>>(src, dst, n);
-    if (e == hipSuccess) e = hipGetLastError();
-    if (e == hipSuccess) e = hipEventRecord(e1, stream);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    float ms = 0.0f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    const hipError_t e =
+        time_launches(stream, reps, [&] { k_copy<<<blocks, 256, 0, stream>>>(src, dst, n); }, ms_per_copy);
     if (e != hipSuccess) return fail(nullptr, HOSC_E_DEVICE, std::string("copy probe: ") + hipGetErrorString(e));
-    *ms_per_copy = ms / reps;
     return HOSC_OK;
 }
 
@@ -2699,24 +2712,12 @@ hosc_status hosc_stream_mix_bandwidth(const void *d_read, void *d_inplace, size_
     const uintptr_t up = reinterpret_cast<uintptr_t>(d_inplace);
     if (rd < up + (size_t)kMixInPlace * bytes && up < rd + (size_t)kMixRead * bytes)
         return fail(nullptr, HOSC_E_ARG, "stream-mix probe buffers overlap");
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-        return fail(nullptr, HOSC_E_DEVICE, "hipEventCreate failed");
     const unsigned blocks = (unsigned)((n + 255) / 256);    // one element of every array per thread
     const double2 *src = static_cast<const double2 *>(d_read);
     double2 *dst = static_cast<double2 *>(d_inplace);
-    k_stream_mix<<<blocks, 256, 0, stream>>>(src, dst, n);    // warm-up
-    hipError_t e = hipEventRecord(e0, stream);
-    for (int q = 0; q < reps && e == hipSuccess; ++q) k_stream_mix<<<blocks, 256, 0, stream>>>(src, dst, n);
-    if (e == hipSuccess) e = hipGetLastError();
-    if (e == hipSuccess) e = hipEventRecord(e1, stream);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    float ms = 0.0f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    const hipError_t e =
+        time_launches(stream, reps, [&] { k_stream_mix<<<blocks, 256, 0, stream>>>(src, dst, n); }, ms_per_launch);
     if (e != hipSuccess) return fail(nullptr, HOSC_E_DEVICE, std::string("stream-mix probe: ") + hipGetErrorString(e));
-    *ms_per_launch = ms / reps;
     return HOSC_OK;
 }
 
