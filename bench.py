@@ -42,7 +42,9 @@ launch, algorithmic bytes per launch), with the whole step's algorithmic bytes
 against the HBM peak (`roofline.step`) and the half-sweep on a 257^3 grid whose
 working set streams from HBM (`roofline.hbm_streaming`), each beside the library's
 streaming probe with the half-sweep's access mix on arrays of that grid's size
-(`mix_probe_GBs`, `frac_of_mix_probe`), and the FP64 CPU oracle
+(`mix_probe_GBs`, `frac_of_mix_probe`), the same segment with its state handed
+over from and back to host memory through the C ABI (`pcie_inclusive`; `value`
+itself starts and ends with the state in HBM), and the FP64 CPU oracle
 timed on the host cores on a bounded sample of the same workload.  The default
 run also carries the metric's second half: `serving` (24 small requests of the
 seeded trace marched to res 1e-8 through the server, FP32 refined, against the
@@ -224,6 +226,58 @@ def stream_sweep(hosc, torch, W, N):
     return {"grid": N, "kernel": "k_sweep", "half_sweeps": c["sweep_launches"],
             "bytes_per_launch": c["sweep_bytes"] / n, "avg_launch_us": c["sweep_ms"] / n * 1e3,
             "achieved": gbs, "frac": gbs / HBM_PEAK_GBS, "mix_probe_GBs": mix, "frac_of_mix_probe": gbs / mix}
+
+
+def pcie_inclusive(s, reset, torch, M3, seg, reps=3):
+    """The benchmark segment with its input handed over from host memory and its
+    result read back to host memory: hosc_set_state from pageable numpy arrays (the
+    segment's start state, u, v, w, theta, p), `seg` steps with the per-step
+    diagnostics, hosc_get_state into pageable numpy arrays, timed end to end (best
+    of `reps`); and the two transfers alone.  Then the same with page-locked host
+    arrays."""
+    reset(s)
+    host = s.get_state()
+    nbytes = sum(a.nbytes for a in host.values())
+    best, best_xfer = float("inf"), float("inf")
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.set_state(**host, apply_bc=False)
+        s.get_state()
+        best_xfer = min(best_xfer, time.perf_counter() - t0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.set_state(**host, apply_bc=False)
+        for _ in range(seg):
+            s.step(1)
+            s.diagnostics(arrays=False)
+        s.get_state()
+        best = min(best, time.perf_counter() - t0)
+    # the same with page-locked host arrays (torch's pinned allocation, viewed as numpy)
+    pin = {f: torch.empty(a.shape, dtype=torch.float64, pin_memory=True).numpy() for f, a in host.items()}
+    back = {f: torch.empty(a.shape, dtype=torch.float64, pin_memory=True).numpy() for f, a in host.items()}
+    for f in host:
+        pin[f][...] = host[f]
+    best_pin, best_pin_xfer = float("inf"), float("inf")
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.set_state(**pin, apply_bc=False)
+        s.get_state(out=back)
+        best_pin_xfer = min(best_pin_xfer, time.perf_counter() - t0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.set_state(**pin, apply_bc=False)
+        for _ in range(seg):
+            s.step(1)
+            s.diagnostics(arrays=False)
+        s.get_state(out=back)
+        best_pin = min(best_pin, time.perf_counter() - t0)
+    return {"segment_steps": seg, "state_bytes_each_way": nbytes,
+            "pageable": {"ms_per_segment": best * 1e3, "cell_updates_per_s": M3 * seg / best,
+                         "transfers_alone_ms": best_xfer * 1e3, "transfer_GBs": 2 * nbytes / best_xfer / 1e9},
+            "pinned": {"ms_per_segment": best_pin * 1e3, "cell_updates_per_s": M3 * seg / best_pin,
+                       "transfers_alone_ms": best_pin_xfer * 1e3, "transfer_GBs": 2 * nbytes / best_pin_xfer / 1e9}}
 
 
 def mix_probe(hosc, N):
@@ -869,6 +923,8 @@ def main():
                      "refine_us": perf["refine_ms"] * 1e3 / max(perf["refine_launches"], 1),
                      "refine_time_frac": perf["refine_ms"] * 1e-3 / el},
     }
+    if args.workload == "fp64":
+        out["pcie_inclusive"] = pcie_inclusive(s, reset, torch, M3, args.segment)
     s.close()
     if W["precision"] != 0:
         out["precision_check"] = precision_check(hosc, W, kw, reset, args.segment)

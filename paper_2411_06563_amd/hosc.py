@@ -315,10 +315,18 @@ class Solver:
                 raise ValueError("fields must hold N^3 values")
         _check(lib().hosc_set_state(self.h, *(_ptr(a) for a in arrs), int(apply_bc)), self.h)
 
-    def get_state(self) -> dict:
+    def get_state(self, out: dict = None) -> dict:
+        """u, v, w, T, p as (N, N, N) arrays; `out` may hold the five arrays to fill
+        (C-contiguous float64 of N^3 values each, e.g. views of page-locked memory)."""
         N = self.N
-        out = {f: np.empty((N, N, N)) for f in ("u", "v", "w", "T", "p")}
-        _check(lib().hosc_get_state(self.h, *(_ptr(out[f]) for f in ("u", "v", "w", "T", "p"))), self.h)
+        names = ("u", "v", "w", "T", "p")
+        if out is None:
+            out = {f: np.empty((N, N, N)) for f in names}
+        for f in names:
+            a = out[f]
+            if a.dtype != np.float64 or not a.flags["C_CONTIGUOUS"] or a.size != N ** 3 or not a.flags["WRITEABLE"]:
+                raise ValueError(f"out[{f!r}] must be a writeable C-contiguous float64 array of N^3 values")
+        _check(lib().hosc_get_state(self.h, *(_ptr(out[f]) for f in names)), self.h)
         return out
 
     def step(self, n: int = 1) -> StepInfo:

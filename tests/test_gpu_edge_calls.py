@@ -132,3 +132,37 @@ def test_solvers_on_their_own_streams(hosc):
         for f in g:
             assert np.array_equal(g[f], r[f]), f
         s.close()
+
+
+def test_state_through_caller_and_page_locked_arrays(hosc):
+    """get_state into caller arrays (page-locked ones included) equals get_state into
+    its own arrays bitwise; a state set from page-locked arrays steps exactly like one
+    set from pageable arrays; arrays of the wrong kind are refused before the call."""
+    import torch
+    N = 11
+    say(f"[state arrays] N={N}")
+    p = hosc.params(N, Ra=1e4, n_pl=0.75, dt=1e-3)
+    st = initial_state(N, 3, 1e-3)
+    pin = {f: torch.empty((N, N, N), dtype=torch.float64, pin_memory=True).numpy() for f in st}
+    for f in st:
+        pin[f][...] = st[f]
+    a, b = hosc.Solver(p), hosc.Solver(p)
+    a.set_state(**st)
+    b.set_state(**pin)
+    a.step(3)
+    b.step(3)
+    ga = a.get_state()
+    out = {f: torch.empty((N, N, N), dtype=torch.float64, pin_memory=True).numpy() for f in ga}
+    gb = b.get_state(out=out)
+    assert gb is out
+    for f in ga:
+        assert np.array_equal(ga[f], gb[f]), f
+    bad = dict(out)
+    bad["T"] = np.empty((N, N, N), dtype=np.float32)
+    with pytest.raises(ValueError):
+        a.get_state(out=bad)
+    bad["T"] = np.empty((N, N, N))[:, :, ::-1]
+    with pytest.raises(ValueError):
+        a.get_state(out=bad)
+    a.close()
+    b.close()
