@@ -801,6 +801,8 @@ def main():
                          "(use with a large --max-steps)")
     ap.add_argument("--stream-grid", type=int, default=257,
                     help="default workload: grid of the HBM-streaming half-sweep measurement (0 = skip)")
+    ap.add_argument("--pcie", type=int, default=1,
+                    help="1: also time the segment with its state handed over through host memory")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the HOSC hot path is measured on one MI355X "
@@ -923,7 +925,7 @@ def main():
                      "refine_us": perf["refine_ms"] * 1e3 / max(perf["refine_launches"], 1),
                      "refine_time_frac": perf["refine_ms"] * 1e-3 / el},
     }
-    if args.workload == "fp64":
+    if args.workload == "fp64" and args.pcie:
         out["pcie_inclusive"] = pcie_inclusive(s, reset, torch, M3, args.segment)
     s.close()
     if W["precision"] != 0:
