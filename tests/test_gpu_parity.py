@@ -252,18 +252,27 @@ def test_config2_first_steps_full_size(hosc, oracle_lib):
     s.init_fields(2, 1e-3)
     o.set_state(**initial_state(N, 2, 1e-3))
     for q in range(3):
-        s.step(1)
-        o.step(1)
-        say(f"[config2] step {q + 1} done")
+        gi = s.step(1)
+        oi = o.step(1)[0]
+        say(f"[config2] step {q + 1} done, res {list(gi.res)} (oracle {list(oi.res)})")
+        # res = ||chi^(n+1) - chi^n|| / ||chi^(n+1)||: fields within 1e-10 of the
+        # oracle's (relative L2) move it by at most about 2e-10 + 1e-10 res
+        for f in range(4):
+            assert abs(gi.res[f] - oi.res[f]) <= 3e-10 + 1e-10 * oi.res[f], (q + 1, f, gi.res[f], oi.res[f])
     g = s.get_state()
     for f in ("u", "v", "w", "T", "p"):
         e = rel(g[f], o.a[f])
         say(f"[config2] {f} rel L2 {e:.3e}")
         assert e <= 1e-10, f
     d = s.diagnostics()
-    r = o.diagnostics()
-    assert abs(d["nu_mean_hot"] - r["nu_mean_hot"]) <= 1e-10 * abs(r["nu_mean_hot"])
-    assert abs(d["e_total"] - r["e_total"]) <= 1e-10 * abs(r["e_total"])
+    r = o.diagnostics(fields=True)
+    for key in ("nu_mean_hot", "nu_mean_cold", "nu_max_hot", "nu_max_cold", "nu_local_max_hot", "e_total", "e_ht",
+                "e_ff", "be_global", "be_mean"):
+        assert abs(d[key] - r[key]) <= 1e-10 * max(abs(r[key]), 1e-300), (key, d[key], r[key])
+    assert rel(d["nu_hot"], r["nu_hot"]) <= 1e-10 and rel(d["nu_cold"], r["nu_cold"]) <= 1e-10
+    assert rel(d["nuavg_hot"], r["nuavg_hot"]) <= 1e-10 and rel(d["nuavg_cold"], r["nuavg_cold"]) <= 1e-10
+    el, bl = s.entropy_fields()
+    assert rel(el, r["e_local"]) <= 1e-10 and rel(bl, r["be_local"]) <= 1e-10
     s.close()
 
 
