@@ -94,3 +94,30 @@ def test_transport_step_diffusion_mode_decay(hosc, abc, L0, dt):
     assert 1e-3 < g ** steps < 0.9
     # 50 solves, each stopped at a relative residual of 1e-14 (measured: 1e-15 to 3e-14)
     assert err <= 1e-12, err
+
+
+def test_steady_state_energy_identities(hosc):
+    """At a steady state the energy equation gives two identities (Secs. 4.2-4.3):
+    the heat entering at the hot wall leaves at the cold one (Nu_hot = Nu_cold), and
+    Green's identity with no-slip, incompressible flow and adiabatic side walls gives
+    integral of |grad theta|^2 = Nu_hot, i.e. E_HT = Nu_hot.  On 33^3 and 65^3
+    (Newtonian, Ra = 1e4, Pr = 1, marched to a steady residual of 1e-9) the discrete
+    wall fluxes balance to the distance from the steady state (measured 3e-9 and
+    4e-8), and E_HT approaches Nu_hot as the grid is refined: measured gaps +1.9e-3
+    and -1.2e-4 (the sign changes), asserted to shrink at least by the factor 4 of a
+    second-order error."""
+    gaps = {}
+    for N in (33, 65):
+        s = hosc.Solver(hosc.params(N, Ra=1e4, n_pl=1.0, Pr=1.0, dt=0.2 / (N - 1) ** 2, solve_rtol=1e-10))
+        s.init_fields(5, 1e-3)
+        info = s.run_to_steady(1e-9, 60000)
+        assert max(info.res) < 1e-9, (N, info.step, max(info.res))
+        d = s.diagnostics(arrays=False)
+        s.close()
+        nu = d["nu_mean_hot"]
+        gaps[N] = (abs(d["nu_mean_cold"] - nu) / nu, abs(d["e_ht"] - nu) / nu)
+        say(f"[identities] N={N} steady after {info.step} steps: Nu {nu:.8f}/{d['nu_mean_cold']:.8f}, "
+            f"E_HT {d['e_ht']:.8f}; gaps {gaps[N][0]:.3e} (cold wall), {gaps[N][1]:.3e} (E_HT)")
+    assert gaps[33][0] < 1e-6 and gaps[65][0] < 1e-6, gaps
+    assert gaps[33][1] < 1e-2 and gaps[65][1] < 1e-3, gaps
+    assert gaps[65][1] < gaps[33][1] / 4.0, gaps
