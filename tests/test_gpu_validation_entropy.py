@@ -257,7 +257,14 @@ def test_shear_thinning_ra1e5_branch_by_continuation():
     0.9, 0.875, 0.85 the paper's statements hold (Sec. 4.2, 4.3): the mean Nusselt
     number, the largest local Nusselt number on the hot wall and the total entropy
     generation rise as n falls, and max_z Nu_avg with them; each state has the
-    hot/cold Nusselt balance of a steady state."""
+    hot/cold Nusselt balance of a steady state.  And the double peak of Nu_avg(z)
+    that the paper shows for the shear-thinning fluid at Ra = 1e5 (Sec. 4.2, Fig. 9)
+    appears along the branch: the Newtonian profile has its single maximum at
+    z = 1/2, the shear-thinning ones two local maxima placed symmetrically about
+    z = 1/2 with a dip between them that deepens, and maxima that move apart, as n
+    falls (dip 0.27 % at n = 0.9 and 1.1 % at n = 0.85 here; 2.5 % at n = 0.8 and
+    3.0 % at n = 0.7875 on 129^3)."""
+    import numpy as np
     import torch
     assert torch.cuda.is_available()
     from paper_2411_06563_amd import hosc
@@ -272,7 +279,7 @@ def test_shear_thinning_ra1e5_branch_by_continuation():
         else:
             s.set_state(**state)
         info = s.run_to_steady(1e-8, 20000)
-        d = s.diagnostics(arrays=False)
+        d = s.diagnostics(arrays=True)
         state = s.get_state()
         s.close()
         print(f"[Ra=1e5 branch] n={n}: {info.step} steps, res {max(info.res):.2e}, Nu {d['nu_mean_hot']:.5f}/"
@@ -286,3 +293,21 @@ def test_shear_thinning_ra1e5_branch_by_continuation():
         assert b["nu_local_max_hot"] > a["nu_local_max_hot"]
         assert b["nu_max_hot"] > a["nu_max_hot"]
         assert b["e_total"] > a["e_total"]
+    # local maxima of Nu_avg(z) over the interior z, and the dip between the outer two
+    peaks = []
+    for n, d in zip((1.0, 0.9, 0.875, 0.85), rows):
+        avg = np.asarray(d["nuavg_hot"])[1:-1]
+        mx = [i for i in range(1, len(avg) - 1) if avg[i] > avg[i - 1] and avg[i] >= avg[i + 1]]
+        dip = 0.0
+        if len(mx) == 2:
+            lo = float(avg[mx[0]:mx[1] + 1].min())
+            dip = (min(avg[mx[0]], avg[mx[1]]) - lo) / lo
+        zs = [(i + 1) / (N - 1) for i in mx]
+        print(f"[Ra=1e5 branch] n={n}: Nu_avg(z) local maxima at z = {[round(z, 4) for z in zs]}, dip {dip:.3e}",
+              flush=True)
+        peaks.append((zs, dip))
+    assert peaks[0][0] == [0.5]                                        # Newtonian: one maximum, at z = 1/2
+    for zs, dip in peaks[1:]:
+        assert len(zs) == 2 and abs(zs[0] + zs[1] - 1.0) < 1e-12 and dip > 1e-3
+    for (za, da), (zb, db) in zip(peaks[1:], peaks[2:]):
+        assert db > da and zb[0] <= za[0]                              # deeper, and apart, as n falls
