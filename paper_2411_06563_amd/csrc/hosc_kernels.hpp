@@ -306,21 +306,22 @@ __device__ __forceinline__ bool all_node(const Geo &g, const Tile &tl, int &i, i
 // ---------------------------------------------------------------------------
 // Derivatives at any node: central inside, 2nd-order one-sided on a wall normal to
 // the axis (velocity, eta, theta); the wall-normal pressure derivative is zero.
-// Branch-free: every lane reads three points at offsets and weights chosen per
-// lane (inside: f(+1) - f(-1) + 0 f(0), exactly the central difference; on a
-// wall: the one-sided weights -3, 4, -1 or 3, -4, 1), so the loads of all the
-// derivatives of a node issue together instead of the wall and interior paths of
-// a wavefront running one after the other (nearly every wavefront of an all-node
-// launch holds an x-wall lane).
+// Branch-free: every lane combines the node's own value fc (loaded once per field
+// and shared by its three axes) with two more points at offsets and weights chosen
+// per lane (inside: 0 fc + f(+1) - f(-1), exactly the central difference; on a wall
+// the one-sided weights -3, 4, -1 on fc, f(+1), f(+2), or 3, -4, 1 on fc, f(-1),
+// f(-2)), so the loads of all the derivatives of a node issue together instead of
+// the wall and interior paths of a wavefront running one after the other (nearly
+// every wavefront of an all-node launch holds an x-wall lane).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double dnode(const double *f, size_t c, size_t s, int idx, int N, double inv2h)
+__device__ __forceinline__ double dnode(const double *f, double fc, size_t c, size_t s, int idx, int N, double inv2h)
 {
     const bool lo = idx == 0, hi = idx == N - 1;
     const ptrdiff_t t = (ptrdiff_t)s;
-    const ptrdiff_t o0 = (lo || hi) ? 0 : t, o1 = lo ? t : -t, o2 = lo ? 2 * t : (hi ? -2 * t : 0);
-    const double w0 = lo ? -3.0 : (hi ? 3.0 : 1.0), w1 = lo ? 4.0 : (hi ? -4.0 : -1.0), w2 = lo ? -1.0 : (hi ? 1.0 : 0.0);
-    const double a = f[(ptrdiff_t)c + o0], b = f[(ptrdiff_t)c + o1], e = f[(ptrdiff_t)c + o2];
-    return (w0 * a + w1 * b + w2 * e) * inv2h;
+    const ptrdiff_t o1 = hi ? -t : t, o2 = lo ? 2 * t : (hi ? -2 * t : -t);
+    const double w0 = lo ? -3.0 : (hi ? 3.0 : 0.0), w1 = lo ? 4.0 : (hi ? -4.0 : 1.0), w2 = lo ? -1.0 : (hi ? 1.0 : -1.0);
+    const double b = f[(ptrdiff_t)c + o1], e = f[(ptrdiff_t)c + o2];
+    return (w0 * fc + w1 * b + w2 * e) * inv2h;
 }
 __device__ __forceinline__ double dpnode(const double *p, size_t c, size_t s, int idx, int N, double inv2h)
 {
@@ -337,16 +338,17 @@ __device__ __forceinline__ VelGrad vel_grad(const Geo &g, const double *u, const
                                             int j, int k)
 {
     const size_t c = nid(g, i, j, k), sy = (size_t)g.N, sz = (size_t)g.N * g.N;
+    const double uc = u[c], vc = v[c], wc = w[c];
     VelGrad d;
-    d.ux = dnode(u, c, 1, i, g.N, g.inv2h);
-    d.uy = dnode(u, c, sy, j, g.N, g.inv2h);
-    d.uz = dnode(u, c, sz, k, g.N, g.inv2h);
-    d.vx = dnode(v, c, 1, i, g.N, g.inv2h);
-    d.vy = dnode(v, c, sy, j, g.N, g.inv2h);
-    d.vz = dnode(v, c, sz, k, g.N, g.inv2h);
-    d.wx = dnode(w, c, 1, i, g.N, g.inv2h);
-    d.wy = dnode(w, c, sy, j, g.N, g.inv2h);
-    d.wz = dnode(w, c, sz, k, g.N, g.inv2h);
+    d.ux = dnode(u, uc, c, 1, i, g.N, g.inv2h);
+    d.uy = dnode(u, uc, c, sy, j, g.N, g.inv2h);
+    d.uz = dnode(u, uc, c, sz, k, g.N, g.inv2h);
+    d.vx = dnode(v, vc, c, 1, i, g.N, g.inv2h);
+    d.vy = dnode(v, vc, c, sy, j, g.N, g.inv2h);
+    d.vz = dnode(v, vc, c, sz, k, g.N, g.inv2h);
+    d.wx = dnode(w, wc, c, 1, i, g.N, g.inv2h);
+    d.wy = dnode(w, wc, c, sy, j, g.N, g.inv2h);
+    d.wz = dnode(w, wc, c, sz, k, g.N, g.inv2h);
     return d;
 }
 
@@ -382,11 +384,12 @@ __global__ void __launch_bounds__(256) k_estar(Geo g, Phys P, const double *__re
     if (!all_node(g, tl, i, j, k)) return;
     const size_t c = nid(g, i, j, k), sy = (size_t)g.N, sz = (size_t)g.N * g.N;
     const VelGrad d = vel_grad(g, u, v, w, i, j, k);
-    const double ex = dnode(eta, c, 1, i, g.N, g.inv2h), ey = dnode(eta, c, sy, j, g.N, g.inv2h),
-                 ez = dnode(eta, c, sz, k, g.N, g.inv2h);
+    const double etac = eta[c];
+    const double ex = dnode(eta, etac, c, 1, i, g.N, g.inv2h), ey = dnode(eta, etac, c, sy, j, g.N, g.inv2h),
+                 ez = dnode(eta, etac, c, sz, k, g.N, g.inv2h);
     const double px = dpnode(p, c, 1, i, g.N, g.inv2h), py = dpnode(p, c, sy, j, g.N, g.inv2h),
                  pz = dpnode(p, c, sz, k, g.N, g.inv2h);
-    const double L = 1.0 / (P.Pr * eta[c]);
+    const double L = 1.0 / (P.Pr * etac);
     const double sxy = d.uy + d.vx, sxz = d.uz + d.wx, syz = d.vz + d.wy;
     Eu[c] = L * (-px + P.Pr * (2.0 * d.ux * ex + sxy * ey + sxz * ez));
     Ev[c] = L * (-py + P.Pr * (sxy * ex + 2.0 * d.vy * ey + syz * ez) + P.Ra * P.Pr * (T[c] - P.theta_ref));
@@ -1793,8 +1796,9 @@ __device__ __forceinline__ void entropy_block(const Geo &g, const Phys &P, const
     double acc[3] = {0.0, 0.0, 0.0};
     if (all_node(g, tl, i, j, k)) {
         const size_t c = nid(g, i, j, k), sy = (size_t)g.N, sz = (size_t)g.N * g.N;
-        const double tx = dnode(T, c, 1, i, g.N, g.inv2h), ty = dnode(T, c, sy, j, g.N, g.inv2h),
-                     tz = dnode(T, c, sz, k, g.N, g.inv2h);
+        const double Tc = T[c];
+        const double tx = dnode(T, Tc, c, 1, i, g.N, g.inv2h), ty = dnode(T, Tc, c, sy, j, g.N, g.inv2h),
+                     tz = dnode(T, Tc, c, sz, k, g.N, g.inv2h);
         const double eht = tx * tx + ty * ty + tz * tz;
         const VelGrad d = vel_grad(g, u, v, w, i, j, k);
         const double I2 = strain_I2(d);
